@@ -1,0 +1,22 @@
+"""FP64 CPU oracle -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously correct reference implementations of what the GPU
+library computes, written from the paper's definitions:
+
+  fci.py     determinant-basis Hamiltonian and exact diagonalization (the
+             Hamiltonian of real orbitals in second quantization; the
+             eigenproblem of the time-independent DMRG equation at full M);
+  fock.py    brute-force Jordan-Wigner Fock-space matrices for tiny systems
+             (an independent construction used only to pin fci.py);
+  mpsvec.py  MPS -> FCI vector, the product-basis maps P_i of the one-site and
+             two-site mixed-canonical forms, and the dense explicit effective
+             Hamiltonian P^T H P (definition of the site problem, Sec. II A);
+  tda.py     the Tamm-Dancoff eigenproblem as Rayleigh-Ritz of H in the MPS
+             tangent space with the reference removed (Sec. II C-D);
+  blocksparse.py  a plain per-block numpy sigma used only as the CPU timing
+             baseline of the benchmark.
+
+Only tests/, the smoke check in __graft_entry__.py and the cpu_baseline leg
+of bench.py may import this package.  The GPU library never does, and this
+package never imports the GPU library.
+"""
