@@ -1,0 +1,204 @@
+/*
+ * C-ABI of the MI355X DMRG linear-response library (DMRG sigma, block
+ * renormalization, ground-state sweeps and DMRG-TDA Davidson sweeps).
+ *
+ * Method: Nakatani, Wouters, Van Neck, Chan, "Linear response theory for the
+ * density matrix renormalization group" (arXiv:1311.1646).  Section and
+ * equation labels below refer to that paper.
+ *
+ * Conventions shared by every entry point
+ *  - Sites are spatial orbitals 0..L-1; the local basis of a site is
+ *    n = 0:|0>, 1:|alpha>, 2:|beta>, 3:|alpha beta> = a+_alpha a+_beta |0>;
+ *    fermion order is site-major, alpha before beta.
+ *  - Bond b (0..L) lies left of site b; its symmetry sectors are labelled by
+ *    the (n_alpha, n_beta) counted over sites 0..b-1, listed in increasing
+ *    (n_alpha, n_beta) order.
+ *  - A one-site coefficient tensor at site i has one dense row-major block per
+ *    (left sector a of bond i, n) whose right sector c = q_a + q(n) exists at
+ *    bond i+1; blocks are stored consecutively ordered by a then n (the
+ *    "flat layout").  A two-site tensor at (i, i+1) uses (a, n1, n2) ordering
+ *    with c at bond i+2.  dmrg_get_layout reports the blocks.
+ *  - Integrals: h is L*L row-major; eri is L^4 row-major, chemist notation
+ *    (pq|rs), real orbitals (8-fold symmetry is assumed, not checked).
+ *  - Every call returns 0 (DMRG_OK) or a negative code; no exception crosses
+ *    the ABI.  dmrg_last_error gives the message of the last failure.
+ *  - Device work is enqueued on the stream given to dmrg_create; calls that
+ *    return host scalars synchronize that stream.
+ */
+#ifndef DMRG_H_
+#define DMRG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  DMRG_OK = 0,
+  DMRG_ERR_INVALID_ARG = -1,
+  DMRG_ERR_OOM = -2,
+  DMRG_ERR_NOT_CONVERGED = -3,
+  DMRG_ERR_SINGULAR = -4,
+  DMRG_ERR_HIP = -5,
+  DMRG_ERR_STATE = -6,
+  DMRG_ERR_INTERNAL = -7
+};
+
+/* Arithmetic of the operator contractions (sigma and renormalization).
+ * FP64 everywhere; FP32 operands with FP32 accumulation; BF16X3: FP32
+ * operands split x = hi + lo into bfloat16 parts, products hi*hi + hi*lo +
+ * lo*hi accumulated in FP32.  Davidson data, gauge transforms and reduced
+ * matrices are FP64 in every mode. */
+enum { DMRG_FP64 = 0, DMRG_FP32 = 1, DMRG_BF16X3 = 2 };
+
+/* Kinds of sigma (Sec. III B-D):
+ *  ZEROTH_1SITE : sigma = H_0^[i] C, the one-site effective Hamiltonian
+ *                 L_{i-1} x h_i x R_i (eq. hzero_sb) applied to nvec vectors.
+ *  ZEROTH_2SITE : the two-site effective Hamiltonian on sites (i, i+1).
+ *  TDA_FULL     : sigma_i^mu of eq. sigv1 for the TDA trial vectors held by the
+ *                 library (internal use by dmrg_tda_roots; not callable).
+ *  TDA_DH_LEFT  : the first-order left part of eq. sigv2 (internal). */
+enum { DMRG_SIGMA_ZEROTH_1SITE = 0, DMRG_SIGMA_ZEROTH_2SITE = 1,
+       DMRG_SIGMA_TDA_FULL = 2, DMRG_SIGMA_TDA_DH_LEFT = 3 };
+
+enum { DMRG_DIR_LEFT = 0, DMRG_DIR_RIGHT = 1 };
+
+typedef struct dmrg_ctx dmrg_ctx;
+
+typedef struct {
+  /* optional device allocator; NULL members mean hipMalloc/hipFree */
+  void* (*alloc)(size_t bytes, void* stream, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} dmrg_allocator;
+
+/* Create a context for L orbitals and (n_alpha, n_beta) electrons.
+ * The integrals are copied; the caller keeps ownership of h and eri.
+ * device < 0 creates a host-only context on which only the host/test-support
+ * calls (dmrg_debug_*, layout queries) are valid.  stream: a hipStream_t or
+ * NULL for the null stream.  alloc may be NULL.
+ * Errors: INVALID_ARG (sizes, electron counts), HIP_ERROR, OOM. */
+int dmrg_create(int L, int n_alpha, int n_beta, const double* h, const double* eri,
+                double ecore, int device, void* stream, const dmrg_allocator* alloc,
+                dmrg_ctx** out);
+int dmrg_destroy(dmrg_ctx* ctx);
+const char* dmrg_last_error(const dmrg_ctx* ctx);
+
+/* Number of channels (normal + complementary operators) of the block
+ * operator sets at bond b: the "x" summation of eq. hzero_sb made explicit. */
+int dmrg_num_channels(dmrg_ctx* ctx, int bond, int* out);
+
+/* Import a mixed-canonical MPS (host FP64; copied to the device).
+ *  nsec[b], b = 0..L: number of sectors of bond b;
+ *  sectors: for all bonds in order, (n_alpha, n_beta, dim) per sector;
+ *  Ldata / Rdata / Cdata: for all sites in order, the flat one-site layout of
+ *  the left-orthonormal L_i, right-orthonormal R_i and C_i = L_i Lambda_i =
+ *  Lambda_{i-1} R_i (Sec. II A, eq. gauge-shift);
+ *  lam: for all bonds in order, per sector, the diagonal of Lambda_b.
+ * Bonds 0 and L must hold the single sectors (0,0) and (n_alpha,n_beta) of
+ * dimension 1.  Errors: INVALID_ARG on inconsistent tables. */
+int dmrg_import_mps(dmrg_ctx* ctx, const int* nsec, const int* sectors, const double* Ldata,
+                    const double* Rdata, const double* Cdata, const double* lam);
+
+/* Export the current MPS in the same format.  Call with NULL data pointers
+ * to get the sizes: nsec_out must hold L+1 ints; sizes_out[0..3] receives the
+ * number of sector triples and the lengths of L/R/C data and of lam. */
+int dmrg_export_mps(dmrg_ctx* ctx, int* nsec_out, int* sectors_out, double* Ldata,
+                    double* Rdata, double* Cdata, double* lam, size_t* sizes_out);
+
+/* Layout of the one-site (width 1) or two-site (width 2) coefficient tensor
+ * at `site`: nblocks_out receives the block count; if blocks_out is non-NULL
+ * it receives 6 ints per block (a, n, c, rows, cols, offset); size_out
+ * receives the element count. */
+int dmrg_get_layout(dmrg_ctx* ctx, int site, int width, int* nblocks_out, int* blocks_out,
+                    size_t* size_out);
+
+/* Build the zeroth-order renormalized block operators H_0^{L_b} and
+ * H_0^{R_b} (normal and complementary) at every bond from the imported MPS
+ * (Sec. III B: the operators "known from the ground-state DMRG").
+ * prec selects the storage/compute precision of the operator pools. */
+int dmrg_build_ops(dmrg_ctx* ctx, int prec);
+
+/* Sigma vectors: sigma = H_eff C for nvec vectors (Sec. II A eq. dmrg and
+ * Sec. III B eq. hzero_sb).  C_in and sigma_out are device FP64 arrays of
+ * nvec * size elements (vector-major, each vector in the flat layout of the
+ * one-site tensor at `site` or of the two-site tensor at (site, site+1)).
+ * Requires dmrg_build_ops.  Errors: STATE before build_ops, INVALID_ARG. */
+int dmrg_sigma(dmrg_ctx* ctx, int site, int kind, int nvec, const double* C_in,
+               double* sigma_out, int prec);
+
+/* Diagonal of the one-site effective Hamiltonian at `site` (the Davidson
+ * preconditioner of eq. error), written to a device FP64 array of `size`. */
+int dmrg_diag(dmrg_ctx* ctx, int site, int width, double* diag_out, int prec);
+
+/* Recompute the zeroth-order block operators of one bond from the current
+ * MPS: dir LEFT builds H_0^{L_{site+1}} from H_0^{L_site} and L_site; RIGHT
+ * builds H_0^{R_site} from H_0^{R_{site+1}} and R_site.  order must be 0
+ * (first-order sets are internal to dmrg_tda_roots). */
+int dmrg_renormalize(dmrg_ctx* ctx, int site, int dir, int order, int prec);
+
+typedef struct {
+  int nsweeps;            /* two-site sweeps (left->right->left counts 1)  */
+  const int* M_schedule;  /* bond dimension per sweep (nsweeps entries)    */
+  const double* noise;    /* density-matrix noise per sweep (may be NULL)  */
+  double davidson_tol;    /* residual norm^2 threshold of the local solver */
+  int davidson_max_iter;  /* per site                                      */
+  int seed;               /* initial state                                 */
+  int prec;               /* DMRG_FP64 / FP32 / BF16X3 contractions        */
+  int verbose;
+} dmrg_sweep_params;
+
+/* Ground state by two-site sweeps with Davidson (Sec. II A, eq. dmrg and
+ * eq. gauge-shift), followed by one non-truncating one-site pass that leaves
+ * a consistent mixed-canonical MPS (L_i, C_i, R_i, Lambda_i at every site)
+ * and its zeroth-order operators for dmrg_tda_roots.
+ * energy receives <Psi|H|Psi> of the final MPS; discarded the largest
+ * discarded weight of the last sweep.  NOT_CONVERGED still leaves a state. */
+int dmrg_sweep_ground(dmrg_ctx* ctx, const dmrg_sweep_params* p, double* energy,
+                      double* discarded);
+
+typedef struct {
+  int max_iter;        /* Davidson iterations (one forward+backward sweep each) */
+  int max_space;       /* N: maximum number of trial vectors (0: 3n, >= n+8)     */
+  double tol;          /* convergence: max_mu sum_i |r_i^mu|^2 < tol             */
+  int seed;            /* random initial trial vectors                           */
+  int prec;            /* contraction precision                                  */
+  int verbose;
+} dmrg_davidson_params;
+
+/* DMRG-TDA roots by the sweep Davidson algorithm (Sec. III, Fig. alg:dmrgtda)
+ * on the current MPS (imported or from dmrg_sweep_ground; build_ops first).
+ * Outputs (host, nroots each): omega = E_mu - E_0 with E_0 = <Psi0|H|Psi0>,
+ * e_total = E_mu, resid2 = sum over sites of |r_i^mu|^2 of the last
+ * iteration; iters = Davidson iterations used.  NOT_CONVERGED fills the
+ * outputs with the last iterate. */
+int dmrg_tda_roots(dmrg_ctx* ctx, int nroots, const dmrg_davidson_params* p, double* omega,
+                   double* e_total, double* resid2, int* iters);
+
+typedef struct {
+  double sigma_flops;      /* algorithmic flops of the last dmrg_sigma call        */
+  double sigma_ms;         /* device time of the last dmrg_sigma call              */
+  double sigma_main_ms;    /* device time of its dominant (stage-2) kernel         */
+  double sigma_main_flops; /* algorithmic flops of that kernel                     */
+  double sigma_main_bytes; /* algorithmic HBM bytes of that kernel                 */
+  double renorm_flops, renorm_ms;
+  double op_bytes;         /* device bytes held by zeroth-order operator pools     */
+  double tda_iter_ms;      /* wall time of the last TDA Davidson iteration         */
+  double tda_sigma_flops;  /* algorithmic flops of that iteration                   */
+  int tda_iters;
+} dmrg_stats;
+
+int dmrg_get_stats(dmrg_ctx* ctx, dmrg_stats* out);
+
+/* Test support (host only, L <= 5): contract the channel site operators into
+ * the dense 4^L x 4^L Fock-space Hamiltonian, basis index sum_i n_i 4^i.
+ * wide_bond >= 0 uses the two-site operator on (wide_bond, wide_bond+1);
+ * from_right selects the right-to-left contraction. */
+int dmrg_debug_mpo_dense(dmrg_ctx* ctx, int wide_bond, int from_right, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMRG_H_ */

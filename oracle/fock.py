@@ -10,17 +10,19 @@ runs over all lower modes.
 from __future__ import annotations
 
 import numpy as np
+import scipy.sparse as sp
 
 
 def annihilator(nmodes, m):
     """Matrix of a_m on the full Fock space, basis index = bit string."""
     dim = 1 << nmodes
-    A = np.zeros((dim, dim))
+    rows, cols, vals = [], [], []
     for s in range(dim):
         if s >> m & 1:
-            sign = (-1) ** bin(s & ((1 << m) - 1)).count("1")
-            A[s ^ (1 << m), s] = sign
-    return A
+            rows.append(s ^ (1 << m))
+            cols.append(s)
+            vals.append((-1) ** bin(s & ((1 << m) - 1)).count("1"))
+    return sp.csr_matrix((vals, (rows, cols)), shape=(dim, dim))
 
 
 def fock_hamiltonian(h, eri, ecore):
@@ -29,7 +31,7 @@ def fock_hamiltonian(h, eri, ecore):
     a = [annihilator(nm, m) for m in range(nm)]
     c = [x.T for x in a]
     dim = 1 << nm
-    H = ecore * np.eye(dim)
+    H = ecore * sp.identity(dim, format="csr")
     for p in range(L):
         for q in range(L):
             for s in range(2):
@@ -45,7 +47,7 @@ def fock_hamiltonian(h, eri, ecore):
                         for tg in range(2):
                             H += 0.5 * v * (c[2 * p + sg] @ c[2 * r + tg]
                                             @ a[2 * s_ + tg] @ a[2 * q + sg])
-    return H
+    return H.toarray()
 
 
 def sector_indices(L, Na, Nb):

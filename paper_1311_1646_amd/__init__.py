@@ -1,0 +1,221 @@
+"""Python binding of libdmrg.so (MI355X DMRG sigma / renormalization / TDA).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  Device arrays are torch tensors (float64, on the context's GPU);
+torch supplies device memory and the stream, nothing else.  The library must
+be built first (``python -m paper_1311_1646_amd.build``); importing this module
+without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdmrg.so")
+
+FP64, FP32, BF16X3 = 0, 1, 2
+SIGMA_ZEROTH_1SITE, SIGMA_ZEROTH_2SITE = 0, 1
+DIR_LEFT, DIR_RIGHT = 0, 1
+
+_ERRORS = {
+    -1: "INVALID_ARG", -2: "OOM", -3: "NOT_CONVERGED", -4: "SINGULAR",
+    -5: "HIP_ERROR", -6: "STATE", -7: "INTERNAL",
+}
+
+
+class DMRGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1311_1646_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_D = ctypes.c_double
+_IP = ctypes.POINTER(ctypes.c_int)
+_DP = ctypes.POINTER(ctypes.c_double)
+_SP = ctypes.POINTER(ctypes.c_size_t)
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in (
+        "sigma_flops", "sigma_ms", "sigma_main_ms", "sigma_main_flops", "sigma_main_bytes",
+        "renorm_flops", "renorm_ms", "op_bytes", "tda_iter_ms", "tda_sigma_flops")] + [("tda_iters", ctypes.c_int)]
+
+
+class SweepParams(ctypes.Structure):
+    _fields_ = [("nsweeps", _I), ("M_schedule", _IP), ("noise", _DP), ("davidson_tol", _D),
+                ("davidson_max_iter", _I), ("seed", _I), ("prec", _I), ("verbose", _I)]
+
+
+class DavidsonParams(ctypes.Structure):
+    _fields_ = [("max_iter", _I), ("max_space", _I), ("tol", _D), ("seed", _I), ("prec", _I),
+                ("verbose", _I)]
+
+
+def _sig(name, *args):
+    f = getattr(_lib, name)
+    f.argtypes = list(args)
+    f.restype = _I
+    return f
+
+
+_create = _sig("dmrg_create", _I, _I, _I, _DP, _DP, _D, _I, _P, _P, ctypes.POINTER(_P))
+_destroy = _sig("dmrg_destroy", _P)
+_lib.dmrg_last_error.argtypes = [_P]
+_lib.dmrg_last_error.restype = ctypes.c_char_p
+_num_channels = _sig("dmrg_num_channels", _P, _I, _IP)
+_import = _sig("dmrg_import_mps", _P, _IP, _IP, _DP, _DP, _DP, _DP)
+_export = _sig("dmrg_export_mps", _P, _IP, _IP, _DP, _DP, _DP, _DP, _SP)
+_layout = _sig("dmrg_get_layout", _P, _I, _I, _IP, _IP, _SP)
+_build_ops = _sig("dmrg_build_ops", _P, _I)
+_sigma = _sig("dmrg_sigma", _P, _I, _I, _I, _P, _P, _I)
+_diag = _sig("dmrg_diag", _P, _I, _I, _P, _I)
+_renorm = _sig("dmrg_renormalize", _P, _I, _I, _I, _I)
+_sweep = _sig("dmrg_sweep_ground", _P, ctypes.POINTER(SweepParams), _DP, _DP)
+_tda = _sig("dmrg_tda_roots", _P, _I, ctypes.POINTER(DavidsonParams), _DP, _DP, _DP, _IP)
+_stats = _sig("dmrg_get_stats", _P, ctypes.POINTER(Stats))
+_debug_dense = _sig("dmrg_debug_mpo_dense", _P, _I, _I, _DP)
+
+
+def _dp(a):
+    return a.ctypes.data_as(_DP)
+
+
+def _ip(a):
+    return a.ctypes.data_as(_IP)
+
+
+class Context:
+    """One problem (integrals, electron numbers) on one GPU (device >= 0) or
+    host-only (device < 0: layout and test-support calls only)."""
+
+    def __init__(self, L, n_alpha, n_beta, h, eri, ecore=0.0, device=0, stream=None):
+        self.L, self.na, self.nb = L, n_alpha, n_beta
+        h = np.ascontiguousarray(h, dtype=np.float64)
+        eri = np.ascontiguousarray(eri, dtype=np.float64)
+        if stream is None and device >= 0:
+            import torch
+            torch.cuda.set_device(device)
+            stream = torch.cuda.current_stream(device).cuda_stream
+        self.device = device
+        self._h = ctypes.c_void_p()
+        rc = _create(L, n_alpha, n_beta, _dp(h), _dp(eri), float(ecore), device,
+                     ctypes.c_void_p(stream or 0), None, ctypes.byref(self._h))
+        if rc != 0:
+            raise DMRGError(rc, _lib.dmrg_last_error(None).decode())
+
+    def _check(self, rc):
+        if rc != 0:
+            raise DMRGError(rc, _lib.dmrg_last_error(self._h).decode())
+
+    def close(self):
+        if self._h:
+            _destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- structure
+    def num_channels(self, bond):
+        out = ctypes.c_int()
+        self._check(_num_channels(self._h, bond, ctypes.byref(out)))
+        return out.value
+
+    def import_mps(self, nsec, sectors, Ldata, Rdata, Cdata, lam):
+        nsec = np.ascontiguousarray(nsec, np.int32)
+        sectors = np.ascontiguousarray(sectors, np.int32)
+        arrs = [np.ascontiguousarray(a, np.float64) for a in (Ldata, Rdata, Cdata, lam)]
+        self._check(_import(self._h, _ip(nsec), _ip(sectors), *[_dp(a) for a in arrs]))
+
+    def export_mps(self):
+        nsec = np.zeros(self.L + 1, np.int32)
+        sizes = np.zeros(4, np.uint64)
+        self._check(_export(self._h, _ip(nsec), None, None, None, None, None,
+                            sizes.ctypes.data_as(_SP)))
+        sec = np.zeros(3 * int(sizes[0]), np.int32)
+        Ld = np.zeros(int(sizes[1]))
+        Rd = np.zeros(int(sizes[1]))
+        Cd = np.zeros(int(sizes[1]))
+        lam = np.zeros(int(sizes[3]))
+        self._check(_export(self._h, _ip(nsec), _ip(sec), _dp(Ld), _dp(Rd), _dp(Cd), _dp(lam),
+                            sizes.ctypes.data_as(_SP)))
+        return nsec, sec.reshape(-1, 3), Ld, Rd, Cd, lam
+
+    def layout(self, site, width=1):
+        nb = ctypes.c_int()
+        size = ctypes.c_size_t()
+        self._check(_layout(self._h, site, width, ctypes.byref(nb), None, ctypes.byref(size)))
+        blocks = np.zeros(6 * nb.value, np.int32)
+        self._check(_layout(self._h, site, width, ctypes.byref(nb), _ip(blocks), ctypes.byref(size)))
+        return blocks.reshape(-1, 6), size.value
+
+    # ---- compute
+    def build_ops(self, prec=FP64):
+        self._check(_build_ops(self._h, prec))
+
+    def sigma(self, site, C, kind=SIGMA_ZEROTH_1SITE, prec=FP64, out=None):
+        """C: torch float64 CUDA tensor (nvec, size) or (size,)."""
+        import torch
+        assert C.dtype == torch.float64 and C.is_cuda and C.is_contiguous()
+        nvec = 1 if C.dim() == 1 else C.shape[0]
+        if out is None:
+            out = torch.empty_like(C)
+        self._check(_sigma(self._h, site, kind, nvec, ctypes.c_void_p(C.data_ptr()),
+                           ctypes.c_void_p(out.data_ptr()), prec))
+        return out
+
+    def diag(self, site, width=1, prec=FP64):
+        import torch
+        _, size = self.layout(site, width)
+        out = torch.empty(size, dtype=torch.float64, device=f"cuda:{self.device}")
+        self._check(_diag(self._h, site, width, ctypes.c_void_p(out.data_ptr()), prec))
+        return out
+
+    def renormalize(self, site, direction, order=0, prec=FP64):
+        self._check(_renorm(self._h, site, direction, order, prec))
+
+    def sweep_ground(self, M_schedule, noise=None, davidson_tol=1e-12, davidson_max_iter=40,
+                     seed=1, prec=FP64, verbose=0):
+        Ms = np.ascontiguousarray(M_schedule, np.int32)
+        nz = None if noise is None else np.ascontiguousarray(noise, np.float64)
+        p = SweepParams(len(Ms), _ip(Ms), _dp(nz) if nz is not None else None, davidson_tol,
+                        davidson_max_iter, seed, prec, verbose)
+        e = ctypes.c_double()
+        dw = ctypes.c_double()
+        rc = _sweep(self._h, ctypes.byref(p), ctypes.byref(e), ctypes.byref(dw))
+        if rc not in (0, -3):
+            self._check(rc)
+        return e.value, dw.value, rc == 0
+
+    def tda_roots(self, nroots, max_iter=60, max_space=0, tol=1e-9, seed=7, prec=FP64, verbose=0):
+        p = DavidsonParams(max_iter, max_space, tol, seed, prec, verbose)
+        om = np.zeros(nroots)
+        et = np.zeros(nroots)
+        r2 = np.zeros(nroots)
+        it = ctypes.c_int()
+        rc = _tda(self._h, nroots, ctypes.byref(p), _dp(om), _dp(et), _dp(r2), ctypes.byref(it))
+        if rc not in (0, -3):
+            self._check(rc)
+        return om, et, r2, it.value, rc == 0
+
+    def stats(self):
+        s = Stats()
+        self._check(_stats(self._h, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def debug_mpo_dense(self, wide_bond=-1, from_right=False):
+        out = np.zeros((4 ** self.L, 4 ** self.L))
+        self._check(_debug_dense(self._h, wide_bond, int(from_right), _dp(out)))
+        return out

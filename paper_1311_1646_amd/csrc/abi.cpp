@@ -1,0 +1,176 @@
+// extern "C" entry points (see include/dmrg.h).
+#include <cstring>
+#include <new>
+
+#include "engine.hpp"
+
+namespace dmrg {
+int debug_mpo_dense_left(QCHamiltonian& H, int wide_bond, double* out);
+int debug_mpo_dense_right(QCHamiltonian& H, int wide_bond, double* out);
+}  // namespace dmrg
+
+struct dmrg_ctx {
+  dmrg::Ctx* x;
+};
+
+namespace {
+thread_local std::string g_create_error;
+
+template <class F>
+int guard(dmrg_ctx* c, F&& f) {
+  if (!c || !c->x) return DMRG_ERR_INVALID_ARG;
+  try {
+    c->x->err.clear();
+    f(*c->x);
+    return DMRG_OK;
+  } catch (const dmrg::Error& e) {
+    c->x->err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    c->x->err = "host allocation failed";
+    return DMRG_ERR_OOM;
+  } catch (const std::invalid_argument& e) {
+    c->x->err = e.what();
+    return DMRG_ERR_INVALID_ARG;
+  } catch (const std::exception& e) {
+    c->x->err = e.what();
+    return DMRG_ERR_INTERNAL;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+int dmrg_create(int L, int n_alpha, int n_beta, const double* h, const double* eri, double ecore, int device,
+                void* stream, const dmrg_allocator* alloc, dmrg_ctx** out) {
+  if (!out) return DMRG_ERR_INVALID_ARG;
+  *out = nullptr;
+  try {
+    auto* c = new dmrg_ctx{new dmrg::Ctx(L, n_alpha, n_beta, h, eri, ecore, device, stream, alloc)};
+    *out = c;
+    return DMRG_OK;
+  } catch (const dmrg::Error& e) {
+    g_create_error = e.what();
+    return e.code;
+  } catch (const std::invalid_argument& e) {
+    g_create_error = e.what();
+    return DMRG_ERR_INVALID_ARG;
+  } catch (const std::bad_alloc&) {
+    g_create_error = "host allocation failed";
+    return DMRG_ERR_OOM;
+  } catch (const std::exception& e) {
+    g_create_error = e.what();
+    return DMRG_ERR_INTERNAL;
+  }
+}
+
+int dmrg_destroy(dmrg_ctx* ctx) {
+  if (!ctx) return DMRG_ERR_INVALID_ARG;
+  delete ctx->x;
+  delete ctx;
+  return DMRG_OK;
+}
+
+const char* dmrg_last_error(const dmrg_ctx* ctx) {
+  if (!ctx || !ctx->x) return g_create_error.c_str();
+  return ctx->x->err.c_str();
+}
+
+int dmrg_num_channels(dmrg_ctx* ctx, int bond, int* out) {
+  return guard(ctx, [&](dmrg::Ctx& x) {
+    DMRG_REQUIRE(bond >= 0 && bond <= x.L && out, DMRG_ERR_INVALID_ARG, "bad bond");
+    *out = int(x.H->channels(bond).ch.size());
+  });
+}
+
+int dmrg_import_mps(dmrg_ctx* ctx, const int* nsec, const int* sectors, const double* Ldata, const double* Rdata,
+                    const double* Cdata, const double* lam) {
+  return guard(ctx, [&](dmrg::Ctx& x) { x.import_mps(nsec, sectors, Ldata, Rdata, Cdata, lam); });
+}
+
+int dmrg_export_mps(dmrg_ctx* ctx, int* nsec_out, int* sectors_out, double* Ldata, double* Rdata, double* Cdata,
+                    double* lam, size_t* sizes_out) {
+  return guard(ctx, [&](dmrg::Ctx& x) { x.export_mps(nsec_out, sectors_out, Ldata, Rdata, Cdata, lam, sizes_out); });
+}
+
+int dmrg_get_layout(dmrg_ctx* ctx, int site, int width, int* nblocks_out, int* blocks_out, size_t* size_out) {
+  return guard(ctx, [&](dmrg::Ctx& x) {
+    const dmrg::SiteLayout& S = x.layout(site, width);
+    if (nblocks_out) *nblocks_out = int(S.blk.size());
+    if (size_out) *size_out = S.size;
+    if (blocks_out)
+      for (size_t b = 0; b < S.blk.size(); ++b) {
+        int* o = blocks_out + 6 * b;
+        o[0] = S.blk[b].a;
+        o[1] = S.blk[b].n;
+        o[2] = S.blk[b].c;
+        o[3] = S.blk[b].rows;
+        o[4] = S.blk[b].cols;
+        o[5] = int(S.blk[b].off);
+      }
+  });
+}
+
+int dmrg_build_ops(dmrg_ctx* ctx, int prec) {
+  return guard(ctx, [&](dmrg::Ctx& x) { x.build_ops(prec); });
+}
+
+int dmrg_sigma(dmrg_ctx* ctx, int site, int kind, int nvec, const double* C_in, double* sigma_out, int prec) {
+  return guard(ctx, [&](dmrg::Ctx& x) {
+    DMRG_REQUIRE(prec == DMRG_FP64, DMRG_ERR_INVALID_ARG, "unsupported precision");
+    DMRG_REQUIRE(kind == DMRG_SIGMA_ZEROTH_1SITE || kind == DMRG_SIGMA_ZEROTH_2SITE, DMRG_ERR_INVALID_ARG,
+                 "TDA sigma kinds are internal to dmrg_tda_roots");
+    x.sigma(site, kind == DMRG_SIGMA_ZEROTH_1SITE ? 1 : 2, nvec, C_in, sigma_out);
+  });
+}
+
+int dmrg_diag(dmrg_ctx* ctx, int site, int width, double* diag_out, int prec) {
+  return guard(ctx, [&](dmrg::Ctx& x) {
+    DMRG_REQUIRE(prec == DMRG_FP64, DMRG_ERR_INVALID_ARG, "unsupported precision");
+    x.diag(site, width, diag_out);
+  });
+}
+
+int dmrg_renormalize(dmrg_ctx* ctx, int site, int dir, int order, int prec) {
+  return guard(ctx, [&](dmrg::Ctx& x) {
+    x.require_gpu();
+    DMRG_REQUIRE(order == 0, DMRG_ERR_INVALID_ARG, "first-order sets are internal to dmrg_tda_roots");
+    DMRG_REQUIRE(prec == DMRG_FP64, DMRG_ERR_INVALID_ARG, "unsupported precision");
+    DMRG_REQUIRE(x.ops_prec >= 0, DMRG_ERR_STATE, "call dmrg_build_ops first");
+    DMRG_REQUIRE(site >= 0 && site < x.L, DMRG_ERR_INVALID_ARG, "bad site");
+    if (dir == DMRG_DIR_LEFT) {
+      x.alloc_opset(x.left[site + 1], site + 1, 0);
+      x.renorm_left(site, x.site[site].L.as<double>(), x.site[site].L.as<double>(), x.left[site], x.left[site + 1]);
+    } else {
+      x.alloc_opset(x.right[site], site, 1);
+      x.renorm_right(site, x.site[site].R.as<double>(), x.site[site].R.as<double>(), x.right[site + 1],
+                     x.right[site]);
+    }
+  });
+}
+
+int dmrg_sweep_ground(dmrg_ctx* ctx, const dmrg_sweep_params*, double*, double*) {
+  return guard(ctx, [&](dmrg::Ctx&) { throw dmrg::Error(DMRG_ERR_STATE, "not available in this build"); });
+}
+
+int dmrg_tda_roots(dmrg_ctx* ctx, int, const dmrg_davidson_params*, double*, double*, double*, int*) {
+  return guard(ctx, [&](dmrg::Ctx&) { throw dmrg::Error(DMRG_ERR_STATE, "not available in this build"); });
+}
+
+int dmrg_get_stats(dmrg_ctx* ctx, dmrg_stats* out) {
+  return guard(ctx, [&](dmrg::Ctx& x) {
+    DMRG_REQUIRE(out, DMRG_ERR_INVALID_ARG, "null stats");
+    *out = x.stats;
+  });
+}
+
+int dmrg_debug_mpo_dense(dmrg_ctx* ctx, int wide_bond, int from_right, double* out) {
+  return guard(ctx, [&](dmrg::Ctx& x) {
+    DMRG_REQUIRE(x.L <= 5 && out, DMRG_ERR_INVALID_ARG, "dense contraction only for L <= 5");
+    DMRG_REQUIRE(wide_bond < x.L - 1, DMRG_ERR_INVALID_ARG, "bad wide bond");
+    if (from_right) dmrg::debug_mpo_dense_right(*x.H, wide_bond, out);
+    else dmrg::debug_mpo_dense_left(*x.H, wide_bond, out);
+  });
+}
+
+}  // extern "C"
