@@ -753,7 +753,10 @@ static void exec_sigma(Ctx& x, int i, int width, const std::vector<STerm>& terms
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipEventDestroy(e2);
-  if (flops_out) *flops_out = st1.flops(nvec) + st2.flops(nvec);
+  if (flops_out) {
+    flops_out[0] = st1.flops(nvec) + st2.flops(nvec);
+    flops_out[1] = st2.flops(nvec);
+  }
   if (ms_out) *ms_out = a;
   if (main_ms) *main_ms = b2;
 }
@@ -829,10 +832,11 @@ void Ctx::sigma(int i, int width, int nvec, const double* Cin, double* Sout) {
   LinComb form;
   std::vector<STerm> terms = sigma_terms(*this, i, width, pool, form);
   form.run(*this, 1, 0);
-  double fl = 0;
+  double fl[2] = {0, 0};
   float ms = 0, mms = 0;
-  exec_sigma(*this, i, width, terms, nvec, Cin, Sout, &fl, &ms, &mms);
-  stats.sigma_flops = fl;
+  exec_sigma(*this, i, width, terms, nvec, Cin, Sout, fl, &ms, &mms);
+  stats.sigma_flops = fl[0];
+  stats.sigma_main_flops = fl[1];
   stats.sigma_ms = ms;
   stats.sigma_main_ms = mms;
 }
