@@ -128,6 +128,7 @@ int dmrg_diag(dmrg_ctx* ctx, int site, int width, double* diag_out, int prec) {
   return guard(ctx, [&](dmrg::Ctx& x) {
     DMRG_REQUIRE(prec == DMRG_FP64, DMRG_ERR_INVALID_ARG, "unsupported precision");
     x.diag(site, width, diag_out);
+    x.sync();
   });
 }
 
@@ -139,13 +140,13 @@ int dmrg_renormalize(dmrg_ctx* ctx, int site, int dir, int order, int prec) {
     DMRG_REQUIRE(x.ops_prec >= 0, DMRG_ERR_STATE, "call dmrg_build_ops first");
     DMRG_REQUIRE(site >= 0 && site < x.L, DMRG_ERR_INVALID_ARG, "bad site");
     if (dir == DMRG_DIR_LEFT) {
-      x.alloc_opset(x.left[site + 1], site + 1, 0);
-      x.renorm_left(site, x.site[site].L.as<double>(), x.site[site].L.as<double>(), x.left[site], x.left[site + 1]);
+      x.renorm(DMRG_DIR_LEFT, site, x.site[site].L.as<double>(), x.site[site].L.as<double>(), 0, x.left[site],
+               x.left[site + 1], false, 1);
     } else {
-      x.alloc_opset(x.right[site], site, 1);
-      x.renorm_right(site, x.site[site].R.as<double>(), x.site[site].R.as<double>(), x.right[site + 1],
-                     x.right[site]);
+      x.renorm(DMRG_DIR_RIGHT, site, x.site[site].R.as<double>(), x.site[site].R.as<double>(), 0,
+               x.right[site + 1], x.right[site], false, 1);
     }
+    x.sync();
   });
 }
 
@@ -153,8 +154,19 @@ int dmrg_sweep_ground(dmrg_ctx* ctx, const dmrg_sweep_params*, double*, double*)
   return guard(ctx, [&](dmrg::Ctx&) { throw dmrg::Error(DMRG_ERR_STATE, "not available in this build"); });
 }
 
-int dmrg_tda_roots(dmrg_ctx* ctx, int, const dmrg_davidson_params*, double*, double*, double*, int*) {
-  return guard(ctx, [&](dmrg::Ctx&) { throw dmrg::Error(DMRG_ERR_STATE, "not available in this build"); });
+int dmrg_tda_roots(dmrg_ctx* ctx, int nroots, const dmrg_davidson_params* p, double* omega, double* e_total,
+                   double* resid2, int* iters) {
+  bool conv = false;
+  int rc = guard(ctx, [&](dmrg::Ctx& x) {
+    DMRG_REQUIRE(p, DMRG_ERR_INVALID_ARG, "null parameters");
+    DMRG_REQUIRE(p->prec == DMRG_FP64, DMRG_ERR_INVALID_ARG, "unsupported precision");
+    x.tda_roots(nroots, *p, omega, e_total, resid2, iters, &conv);
+  });
+  if (rc == DMRG_OK && !conv) {
+    ctx->x->err = "Davidson iteration limit reached";
+    return DMRG_ERR_NOT_CONVERGED;
+  }
+  return rc;
 }
 
 int dmrg_get_stats(dmrg_ctx* ctx, dmrg_stats* out) {

@@ -1,15 +1,17 @@
-// Context, MPS storage, operator pools, renormalization and sigma planners.
+// Context, MPS storage, operator sets, and the planners of the block
+// renormalization and of the sigma vector.
 //
-// Every contraction is planned on the host as lists of block GEMMs and
-// executed by the device kernels in kernels.hip; no arithmetic of the method
-// runs on the host.
+// Every contraction is planned once on the host as device-resident lists of
+// block GEMMs addressed relative to base slots, and executed by the kernels
+// in kernels.hip; no arithmetic of the method runs on the host.
 #include "engine.hpp"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <set>
-#include <tuple>
+#include <unordered_map>
 
 namespace dmrg {
 
@@ -35,53 +37,17 @@ void DBuf::alloc(Ctx* c, size_t nbytes) {
 }
 
 void DBuf::ensure(Ctx* c, size_t nbytes) {
-  if (nbytes > bytes) alloc(c, nbytes + nbytes / 4);
+  if (nbytes > bytes) {
+    if (p) c->sync();  // work still queued may use the old buffer
+    release();
+    alloc(c, nbytes + nbytes / 8);
+  }
 }
 
 void DBuf::release() {
   if (p && owner) owner->dev_free(p);
   p = nullptr;
   bytes = 0;
-}
-
-int OpPool::add(const OpLayout* lay) {
-  auto key = std::make_pair(lay->dna, lay->dnb);
-  auto it = class_of.find(key);
-  int c;
-  if (it == class_of.end()) {
-    c = int(classes.size());
-    class_of[key] = c;
-    classes.emplace_back();
-    classes.back().lay = lay;
-  } else {
-    c = it->second;
-  }
-  items.push_back({c, classes[c].nslots++});
-  return int(items.size()) - 1;
-}
-
-void OpPool::allocate(Ctx* x) {
-  for (auto& C : classes) C.data.alloc(x, size_t(C.nslots) * C.lay->size * sizeof(double));
-}
-
-// ---------------------------------------------------------------- execution lists
-
-int GemmList::job(void* C, int ldc, int m, int n, int flags) {
-  auto it = job_of.find(C);
-  if (it != job_of.end()) return it->second;
-  int j = int(jobs.size());
-  jobs.push_back({C, ldc, m, n, 0, 0, flags, 0});
-  per_job.emplace_back();
-  job_of[C] = j;
-  return j;
-}
-
-double GemmList::flops(int batch) const {
-  double f = 0;
-  for (size_t j = 0; j < jobs.size(); ++j)
-    for (auto& c : per_job[j])
-      if (!(c.flags & GC_A_IDENTITY)) f += 2.0 * jobs[j].m * jobs[j].n * c.k;
-  return f * batch;
 }
 
 namespace {
@@ -92,44 +58,141 @@ void upload(Ctx& x, DBuf& buf, const std::vector<T>& v) {
 }
 }  // namespace
 
-void GemmList::run(Ctx& x, int batch, long sA, long sB, long sC) {
-  if (jobs.empty()) return;
+void GemmPlan::launch(Ctx& x, const Bases& b, int batch) const {
+  if (ntiles == 0) return;
+  launch_grouped_gemm_f64(tiles.as<GTile>(), ntiles, jobs.as<GJob>(), con.as<GContrib>(), b, batch, x.stream);
+  DMRG_HIP(hipGetLastError());
+}
+
+void LinCombPlan::launch(Ctx& x, const Bases& b, int batch) const {
+  if (nt) launch_lincomb_f64(t.as<LCTarget>(), nt, s.as<LCSource>(), max_size, b, batch, x.stream);
+  if (nd) launch_diag_add_f64(d.as<DiagAdd>(), nd, b, batch, x.stream);
+  DMRG_HIP(hipGetLastError());
+}
+
+namespace {
+
+struct LinCombBuilder {
+  std::vector<LCTarget> t;
+  std::vector<LCSource> s;
+  std::vector<DiagAdd> d;
+  long max_size = 0;
+  void target(int base, long off, long size, bool acc) {
+    t.push_back({off, size, base, int(s.size()), int(s.size()), acc ? 1 : 0});
+    max_size = std::max(max_size, size);
+  }
+  void source(int base, long off, double c) {
+    s.push_back({off, base, 0, c});
+    t.back().s1 = int(s.size());
+  }
+  void finish(Ctx& x, LinCombPlan& P) {
+    upload(x, P.t, t);
+    upload(x, P.s, s);
+    upload(x, P.d, d);
+    P.nt = int(t.size());
+    P.nd = int(d.size());
+    P.max_size = max_size;
+  }
+};
+
+void make_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<std::vector<GContrib>>& per) {
   std::vector<GContrib> con;
   std::vector<GTile> tiles;
+  double fl = 0;
   for (size_t j = 0; j < jobs.size(); ++j) {
     jobs[j].c0 = int(con.size());
-    con.insert(con.end(), per_job[j].begin(), per_job[j].end());
+    for (auto& c : per[j]) {
+      con.push_back(c);
+      if (!(c.flags & GC_A_IDENTITY)) fl += 2.0 * jobs[j].m * jobs[j].n * c.k;
+    }
     jobs[j].c1 = int(con.size());
     const int tm = (jobs[j].m + 63) / 64, tn = (jobs[j].n + 63) / 64;
     for (int a = 0; a < tm; ++a)
       for (int b = 0; b < tn; ++b) tiles.push_back({int(j), a, b, 0});
   }
-  DBuf dt, dj, dc;
-  upload(x, dt, tiles);
-  upload(x, dj, jobs);
-  upload(x, dc, con);
-  launch_grouped_gemm_f64(dt.as<GTile>(), int(tiles.size()), dj.as<GJob>(), dc.as<GContrib>(), batch, sA, sB, sC,
-                          x.stream);
-  DMRG_HIP(hipGetLastError());
-  DMRG_HIP(hipStreamSynchronize(x.stream));
+  upload(x, P.tiles, tiles);
+  upload(x, P.jobs, jobs);
+  upload(x, P.con, con);
+  P.ntiles = int(tiles.size());
+  P.flops = fl;
 }
 
-void LinComb::run(Ctx& x, int batch, long stride) {
-  if (!t.empty()) {
-    DBuf dt, ds;
-    upload(x, dt, t);
-    upload(x, ds, s);
-    launch_lincomb_f64(dt.as<LCTarget>(), int(t.size()), ds.as<LCSource>(), max_size, batch, stride, x.stream);
-    DMRG_HIP(hipGetLastError());
-    DMRG_HIP(hipStreamSynchronize(x.stream));
+// Split the stage-1 items into chunks whose workspace fits the budget and
+// build the two device lists of each chunk.
+void finish_two_stage(Ctx& x, TwoStageBuilder& B, TwoStagePlan& P, bool overwrite) {
+  const long budget = x.t_budget_per_vec;
+  std::vector<int> chunk_of(B.t1.size());
+  std::vector<long> toff(B.t1.size());
+  long used = 0;
+  int nch = 0;
+  for (size_t k = 0; k < B.t1.size(); ++k) {
+    if (k == 0 || (used + B.t1[k].elems > budget && used > 0)) {
+      ++nch;
+      used = 0;
+    }
+    chunk_of[k] = nch - 1;
+    toff[k] = used;
+    used += B.t1[k].elems;
+    P.t_per_vec = std::max(P.t_per_vec, used);
   }
-  if (!d.empty()) {
-    DBuf dd;
-    upload(x, dd, d);
-    launch_diag_add_f64(dd.as<DiagAdd>(), int(d.size()), 0, x.stream);
-    DMRG_HIP(hipGetLastError());
-    DMRG_HIP(hipStreamSynchronize(x.stream));
+  if (nch == 0) nch = 1;
+  P.chunks.clear();
+  P.chunks.resize(nch);
+  P.flops1 = P.flops2 = 0;
+  for (int c = 0; c < nch; ++c) {
+    std::vector<GJob> j1;
+    std::vector<std::vector<GContrib>> p1;
+    for (size_t k = 0; k < B.t1.size(); ++k) {
+      if (chunk_of[k] != c) continue;
+      GJob j = B.t1[k].job;
+      j.offC = toff[k];
+      j.baseC = B_T;
+      j.flags = 0;
+      j1.push_back(j);
+      p1.push_back({B.t1[k].con});
+    }
+    make_gemm_plan(x, P.chunks[c].first, j1, p1);
+    std::vector<GJob> j2;
+    std::vector<std::vector<GContrib>> p2;
+    std::map<std::pair<int, long>, int> job_of;
+    auto job = [&](int base, long off, int ldc, int m, int n) {
+      auto key = std::make_pair(base, off);
+      auto it = job_of.find(key);
+      if (it != job_of.end()) return it->second;
+      GJob g{};
+      g.offC = off;
+      g.baseC = base;
+      g.ldc = ldc;
+      g.m = m;
+      g.n = n;
+      g.flags = (overwrite && c == 0) ? 0 : GJ_ACCUMULATE;
+      j2.push_back(g);
+      p2.emplace_back();
+      job_of[key] = int(j2.size()) - 1;
+      return int(j2.size()) - 1;
+    };
+    if (overwrite && c == 0)
+      for (auto& o : B.outputs) job(std::get<1>(o), std::get<0>(o), std::get<2>(o), std::get<3>(o), std::get<4>(o));
+    for (auto& s : B.s2) {
+      const int ck = s.t1 >= 0 ? chunk_of[s.t1] : 0;
+      if (ck != c) continue;
+      GContrib g = s.con;
+      if (s.t1 >= 0) {
+        g.offB += toff[s.t1];
+        g.baseB = B_T;
+      }
+      p2[job(s.baseC, s.offC, s.ldc, s.m, s.n)].push_back(g);
+    }
+    make_gemm_plan(x, P.chunks[c].second, j2, p2);
+    P.flops1 += P.chunks[c].first.flops;
+    P.flops2 += P.chunks[c].second.flops;
   }
+}
+
+}  // namespace
+
+void build_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<std::vector<GContrib>>& per) {
+  make_gemm_plan(x, P, jobs, per);
 }
 
 // ---------------------------------------------------------------- context
@@ -142,19 +205,30 @@ Ctx::Ctx(int L_, int na, int nb, const double* h, const double* eri, double ecor
   DMRG_REQUIRE(h && eri, DMRG_ERR_INVALID_ARG, "null integrals");
   if (alloc) allocator = *alloc;
   stream = static_cast<hipStream_t>(s);
+  const char* env = std::getenv("DMRG_T_BUDGET_PER_VEC");
+  t_budget_per_vec = env ? std::max(1L, std::atol(env)) : (32L << 20);
   if (device >= 0) DMRG_HIP(hipSetDevice(device));
   H.reset(new QCHamiltonian(L, h, eri, ecore));
 }
 
 Ctx::~Ctx() {
+  clear_plans();
   left.clear();
   right.clear();
   site.clear();
 }
 
+void Ctx::clear_plans() {
+  renorm_plans_.clear();
+  sigma_plans_.clear();
+  diag_plans_.clear();
+}
+
 void Ctx::require_gpu() const {
   DMRG_REQUIRE(device >= 0, DMRG_ERR_STATE, "host-only context: no device calls");
 }
+
+void Ctx::sync() { DMRG_HIP(hipStreamSynchronize(stream)); }
 
 void* Ctx::dev_alloc(size_t bytes) {
   require_gpu();
@@ -198,6 +272,12 @@ const OpLayout* Ctx::op_layout(int bond, int dna, int dnb) {
   return (op_layouts_[key] = std::move(O)).get();
 }
 
+long Ctx::bond_offset(int b, int sector) const {
+  long o = 0;
+  for (int s = 0; s < sector; ++s) o += bonds[b].dim[s];
+  return o;
+}
+
 // ---------------------------------------------------------------- MPS import/export
 
 void Ctx::import_mps(const int* nsec, const int* sectors, const double* Ld, const double* Rd, const double* Cd,
@@ -222,11 +302,13 @@ void Ctx::import_mps(const int* nsec, const int* sectors, const double* Ld, cons
                "bond 0 must be the vacuum");
   DMRG_REQUIRE(B[L].q.size() == 1 && B[L].q[0] == (QN{Na, Nb}) && B[L].dim[0] == 1, DMRG_ERR_INVALID_ARG,
                "bond L must hold the target (n_alpha, n_beta)");
+  clear_plans();
   bonds = std::move(B);
   layouts_.clear();
   op_layouts_.clear();
   left.clear();
   right.clear();
+  ops_prec = -1;
   have_mps = true;
   site.clear();
   site.resize(L);
@@ -246,6 +328,27 @@ void Ctx::import_mps(const int* nsec, const int* sectors, const double* Ld, cons
       lam[b].emplace_back(lamd + lo, lamd + lo + bonds[b].dim[s]);
       lo += bonds[b].dim[s];
     }
+  upload_lambda();
+}
+
+void Ctx::upload_lambda() {
+  lam_dev.clear();
+  laminv_dev.clear();
+  lam_dev.resize(L + 1);
+  laminv_dev.resize(L + 1);
+  for (int b = 0; b <= L; ++b) {
+    std::vector<double> v, vi;
+    double mx = 0;
+    for (auto& s : lam[b])
+      for (double x : s) mx = std::max(mx, std::fabs(x));
+    for (auto& s : lam[b])
+      for (double x : s) {
+        v.push_back(x);
+        vi.push_back(std::fabs(x) > 1e-14 * mx ? 1.0 / x : 0.0);
+      }
+    upload(*this, lam_dev[b], v);
+    upload(*this, laminv_dev[b], vi);
+  }
 }
 
 void Ctx::export_mps(int* nsec_out, int* sectors_out, double* Ld, double* Rd, double* Cd, double* lam_out,
@@ -282,47 +385,47 @@ void Ctx::export_mps(int* nsec_out, int* sectors_out, double* Ld, double* Rd, do
 
 // ---------------------------------------------------------------- operator sets
 
-void Ctx::alloc_opset(OpSet& S, int bond, int side) {
+void Ctx::alloc_opset(OpSet& S, int bond, int side, int nvec, bool first_order) {
   const BondChannels& B = H->channels(bond);
   S.bond = bond;
   S.side = side;
-  S.classes.clear();
-  S.cls.assign(B.ch.size(), -1);
-  S.slot.assign(B.ch.size(), 0);
-  std::map<std::pair<int, int>, int> cls_of;
+  S.nvec = nvec;
+  S.first_order = first_order;
   const uint64_t ident = side == 0 ? chan_key(CH_ID_H, -1, -1) : chan_key(CH_H_ID, -1, -1);
+  S.kind.assign(B.ch.size(), REF_OP);
+  S.off.assign(B.ch.size(), 0);
+  S.lay.assign(B.ch.size(), nullptr);
+  long off = 0;
+  std::map<std::pair<int, int>, std::vector<int>> by_shift;  // classes contiguous
   for (size_t w = 0; w < B.ch.size(); ++w) {
-    if (B.ch[w].key == ident) continue;
-    auto key = std::make_pair(B.ch[w].dna, B.ch[w].dnb);
-    auto it = cls_of.find(key);
-    int c;
-    if (it == cls_of.end()) {
-      c = int(S.classes.size());
-      cls_of[key] = c;
-      S.classes.emplace_back();
-      S.classes.back().lay = op_layout(bond, key.first, key.second);
-    } else {
-      c = it->second;
+    if (B.ch[w].key == ident) {
+      S.kind[w] = first_order ? REF_ZERO : REF_IDENTITY;
+      continue;
     }
-    S.cls[w] = c;
-    S.slot[w] = S.classes[c].nslots++;
+    by_shift[{B.ch[w].dna, B.ch[w].dnb}].push_back(int(w));
   }
-  for (auto& C : S.classes) C.data.alloc(this, std::max<size_t>(size_t(C.nslots) * C.lay->size, 1) * 8);
-  S.valid = true;
+  for (auto& kv : by_shift) {
+    const OpLayout* lay = op_layout(bond, kv.first.first, kv.first.second);
+    for (int w : kv.second) {
+      S.lay[w] = lay;
+      S.off[w] = off;
+      off += long(lay->size);
+    }
+  }
+  S.per_vec = off;
+  S.data.alloc(this, std::max<size_t>(size_t(off) * nvec, 1) * 8);
 }
-
 
 // ---------------------------------------------------------------- planning helpers
 
 namespace {
 
 struct Group {
-  int key_ch;  // channel the group is keyed on
-  int sid;     // dot string
-  std::vector<std::pair<int, double>> src;  // (other channel, coefficient)
+  int key_ch;
+  int sid;
+  std::vector<std::pair<int, double>> src;
 };
 
-// Group the entries of W by (dst, sid) (by_dst) or by (src, sid).
 std::vector<Group> group_entries(const SiteOp& W, bool by_dst, int skip_ch) {
   std::map<std::pair<int, int>, int> gi;
   std::vector<Group> G;
@@ -345,274 +448,269 @@ std::vector<Group> group_entries(const SiteOp& W, bool by_dst, int skip_ch) {
   return G;
 }
 
-inline int opblk(const ORef& r, int ket) { return r.identity() ? ket : r.lay->by_ket[ket]; }
+inline bool has_blk(const ORef& r, int ket) { return r.kind == REF_IDENTITY || r.lay->by_ket[ket] >= 0; }
 inline int opbra(const ORef& r, int ket) {
-  if (r.identity()) return ket;
+  if (r.kind == REF_IDENTITY) return ket;
   const int b = r.lay->by_ket[ket];
   return b < 0 ? -1 : r.lay->blk[b].bra;
 }
-inline const double* opptr(const ORef& r, int ket) { return r.p + r.lay->blk[r.lay->by_ket[ket]].off; }
+inline long opoff(const ORef& r, int ket) { return r.off + long(r.lay->blk[r.lay->by_ket[ket]].off); }
 
 using Sources = std::vector<std::pair<ORef, double>>;
 
-// Renormalization job: target += alpha * R(X, sid), R the one-site transform.
-struct RJob {
-  ORef X;
-  int dressed;  // >= 0: X is this dressed-pool item (resolved after allocation)
-  double alpha;
-  int sid;
-  int tkind;    // 0: channel of the destination set, 1: building-block item
-  int tgt;
-  int pz;       // parity of the right-block operator (right renormalization sign)
+// pool of dressed operators / building blocks inside one base
+struct Pool {
+  int base;
+  long size = 0;
+  ORef add(const OpLayout* lay) {
+    ORef r;
+    r.kind = REF_OP;
+    r.base = base;
+    r.off = size;
+    r.lay = lay;
+    size += long(lay->size);
+    return r;
+  }
 };
 
-struct DressPlan {
-  OpPool dressed, blocks;
-  std::vector<std::pair<int, Sources>> pend;
-  std::vector<RJob> jobs;
-  std::vector<std::tuple<int, int, double>> combine;  // (target channel, block item, c)
-};
-
-// Form all pending dressed operators: out = sum c_j src_j (+ c_id * 1).
-void emit_dressed(OpPool& pool, const std::vector<std::pair<int, Sources>>& pend, LinComb& lc) {
-  for (auto& pr : pend) {
-    ORef out = pool.ref(pr.first);
-    lc.target(const_cast<double*>(out.p), long(out.lay->size), false);
-    double cid = 0.0;
-    for (auto& s : pr.second) {
-      if (s.first.identity()) cid += s.second;
-      else lc.source(s.first.p, s.second);
-    }
-    if (cid != 0.0) {
-      DMRG_REQUIRE(out.lay->dna == 0 && out.lay->dnb == 0, DMRG_ERR_INTERNAL, "identity in a shifted class");
-      for (auto& b : out.lay->blk)
-        if (b.ket == b.bra) lc.d.push_back({const_cast<double*>(out.p) + b.off, b.rows, 0, cid});
-    }
+void emit_formation(LinCombBuilder& lc, const ORef& out, const Sources& srcs) {
+  lc.target(out.base, out.off, long(out.lay->size), false);
+  double cid = 0.0;
+  for (auto& s : srcs) {
+    if (s.first.kind == REF_IDENTITY) cid += s.second;
+    else if (s.first.kind == REF_OP) lc.source(s.first.base, s.first.off, s.second);
+  }
+  if (cid != 0.0) {
+    DMRG_REQUIRE(out.lay->dna == 0 && out.lay->dnb == 0, DMRG_ERR_INTERNAL, "identity in a shifted class");
+    for (auto& b : out.lay->blk)
+      if (b.ket == b.bra) lc.d.push_back({out.off + long(b.off), out.base, b.rows, cid});
   }
 }
+
+struct RJob {
+  ORef X;
+  double alpha;
+  int sid;
+  ORef tgt;
+  int pz;
+};
 
 }  // namespace
 
-// Decide, per target group, whether the sources are combined before the
-// one-site transform (one dressed operator per target) or after it (one
-// transformed building block per shared source, then a linear combination):
-// the cheaper one by the number of transforms each target accounts for.
-static void plan_renorm(Ctx& x, const std::vector<Group>& G, const OpSet& src, const BondChannels& Bt,
-                        const BondChannels& Bs, int dressed_bond, int target_bond, bool left, DressPlan& P) {
-  std::map<std::pair<int, int>, int> fan;
-  for (auto& g : G)
-    for (auto& s : g.src) fan[{s.first, g.sid}]++;
-  P.dressed.bond = dressed_bond;
-  P.blocks.bond = target_bond;
-  std::map<std::pair<int, int>, int> block_of;
-  for (auto& g : G) {
-    double share = 0;
-    for (auto& s : g.src) share += 1.0 / fan[{s.first, g.sid}];
-    const bool after = g.src.size() > 1 && share < 1.0 - 1e-9;
-    const DotString& ds = x.H->dot_string(1, g.sid);
-    const Channel& tch = Bt.ch[g.key_ch];
-    const int pz = left ? 0 : Bs.ch[g.src[0].first].parity;
-    if (!after) {
-      if (g.src.size() == 1) {
-        P.jobs.push_back({src.ref(g.src[0].first), -1, g.src[0].second, g.sid, 0, g.key_ch, pz});
-      } else {
-        Sources ss;
-        for (auto& s : g.src) ss.push_back({src.ref(s.first), s.second});
-        const int sa = left ? tch.dna - ds.dna : tch.dna + ds.dna;
-        const int sb = left ? tch.dnb - ds.dnb : tch.dnb + ds.dnb;
-        const int id = P.dressed.add(x.op_layout(dressed_bond, sa, sb));
-        P.pend.push_back({id, std::move(ss)});
-        P.jobs.push_back({ORef{}, id, 1.0, g.sid, 0, g.key_ch, pz});
-      }
-    } else {
-      for (auto& s : g.src) {
-        auto key = std::make_pair(s.first, g.sid);
-        auto it = block_of.find(key);
-        int item;
-        if (it == block_of.end()) {
-          item = P.blocks.add(x.op_layout(target_bond, tch.dna, tch.dnb));
-          block_of[key] = item;
-          const int pzs = left ? 0 : Bs.ch[s.first].parity;
-          P.jobs.push_back({src.ref(s.first), -1, 1.0, g.sid, 1, item, pzs});
-        } else {
-          item = it->second;
-        }
-        P.combine.push_back({g.key_ch, item, s.second});
-      }
-    }
-  }
-  P.dressed.allocate(&x);
-  P.blocks.allocate(&x);
-  for (auto& j : P.jobs)
-    if (j.dressed >= 0) j.X = P.dressed.ref(j.dressed);
-}
-
-static void finish_renorm(Ctx& x, DressPlan& P, OpSet& dst) {
-  LinComb post;
-  std::map<int, std::vector<std::pair<int, double>>> by_tgt;
-  for (auto& cb : P.combine) by_tgt[std::get<0>(cb)].push_back({std::get<1>(cb), std::get<2>(cb)});
-  for (auto& kv : by_tgt) {
-    ORef t = dst.ref(kv.first);
-    post.target(const_cast<double*>(t.p), long(t.lay->size), true);
-    for (auto& s : kv.second) post.source(P.blocks.ref(s.first).p, s.second);
-  }
-  post.run(x, 1, 0);
-}
-
-// ---------------------------------------------------------------- renormalization
-
-// Left block, across site i (bond i -> i+1):
-// Lop_{i+1}[w'] = sum_{(w,sid)} c A_bra^T (Lop_i[w] P^{p(sid)} (x) sid) A_ket.
-void Ctx::renorm_left(int i, const double* Abra, const double* Aket, const OpSet& src, OpSet& dst) {
-  const SiteOp& W = H->site_op(i, 1);
-  const SiteLayout& S = layout(i, 1);
-  const Bond& bl = bonds[i];
-  const BondChannels& B1 = H->channels(i + 1);
-  std::vector<Group> G = group_entries(W, true, B1.find(chan_key(CH_ID_H, -1, -1)));
-  DressPlan P;
-  plan_renorm(*this, G, src, B1, H->channels(i), i, i + 1, true, P);
-  for (auto& C : dst.classes) launch_fill_f64(C.data.as<double>(), long(C.data.bytes / 8), 0.0, stream);
-  for (auto& C : P.blocks.classes) launch_fill_f64(C.data.as<double>(), long(C.data.bytes / 8), 0.0, stream);
-  LinComb form;
-  emit_dressed(P.dressed, P.pend, form);
-  form.run(*this, 1, 0);
-  // stage 1: T(X, a, n) = X(a'<-a) A_ket(a, n, c)
-  GemmList st1, st2;
-  std::map<std::pair<const double*, int>, size_t> toff;
-  size_t tsize = 0;
-  std::vector<std::tuple<ORef, int, size_t>> need;
-  for (auto& j : P.jobs) {
-    if (j.X.identity()) continue;
-    const DotString& ds = H->dot_string(1, j.sid);
-    for (size_t e = 0; e < ds.val.size(); ++e)
-      for (int a = 0; a < int(bl.q.size()); ++a) {
-        const int b = S.find(a, ds.ket[e]);
-        if (b < 0 || opblk(j.X, a) < 0) continue;
-        auto key = std::make_pair(j.X.p, b);
-        if (toff.count(key)) continue;
-        toff[key] = tsize;
-        need.push_back({j.X, b, tsize});
-        tsize += size_t(bl.dim[opbra(j.X, a)]) * S.blk[b].cols;
-      }
-  }
-  DBuf T;
-  T.alloc(this, std::max<size_t>(tsize, 1) * 8);
-  double* Tp = T.as<double>();
-  for (auto& nd : need) {
-    const ORef& X = std::get<0>(nd);
-    const auto& blk = S.blk[std::get<1>(nd)];
-    const int ap = opbra(X, blk.a);
-    const int jb = st1.job(Tp + std::get<2>(nd), blk.cols, bl.dim[ap], blk.cols, 0);
-    st1.add(jb, {opptr(X, blk.a), Aket + blk.off, blk.rows, blk.cols, blk.rows, 0, 1.0});
-  }
-  // stage 2: target(c'<-c) += alpha val sign A_bra(a',n',c')^T T
-  for (auto& j : P.jobs) {
-    const DotString& ds = H->dot_string(1, j.sid);
-    const ORef tgt = j.tkind == 0 ? dst.ref(j.tgt) : P.blocks.ref(j.tgt);
-    for (size_t e = 0; e < ds.val.size(); ++e)
-      for (int a = 0; a < int(bl.q.size()); ++a) {
-        const int b = S.find(a, ds.ket[e]);
-        if (b < 0 || opblk(j.X, a) < 0) continue;
-        const int ap = opbra(j.X, a);
-        const int bp = S.find(ap, ds.bra[e]);
-        if (bp < 0) continue;
-        const int c = S.blk[b].c, cp = S.blk[bp].c;
-        const int tb = tgt.lay->by_ket[c];
-        DMRG_REQUIRE(tb >= 0 && tgt.lay->blk[tb].bra == cp, DMRG_ERR_INTERNAL, "left renorm target block mismatch");
-        const double sign = (ds.parity && (bl.q[a].n() & 1)) ? -1.0 : 1.0;
-        double* out = const_cast<double*>(tgt.p) + tgt.lay->blk[tb].off;
-        const int jb = st2.job(out, S.blk[b].cols, S.blk[bp].cols, S.blk[b].cols, GJ_ACCUMULATE);
-        const double* Bp = j.X.identity() ? Aket + S.blk[b].off : Tp + toff[{j.X.p, b}];
-        st2.add(jb, {Abra + S.blk[bp].off, Bp, S.blk[bp].cols, S.blk[b].cols, bl.dim[ap], GC_TRANS_A,
-                     j.alpha * ds.val[e] * sign});
-      }
-  }
-  st1.run(*this, 1, 0, 0, 0);
-  st2.run(*this, 1, 0, 0, 0);
-  stats.renorm_flops += st1.flops(1) + st2.flops(1);
-  finish_renorm(*this, P, dst);
-}
-
-// Right block, across site i (bond i+1 -> i):
-// Rop_i[w] = sum_{(w',sid)} c R_bra (sid P_D^{p(w')} (x) Rop_{i+1}[w']) R_ket^T.
-void Ctx::renorm_right(int i, const double* Abra, const double* Aket, const OpSet& src, OpSet& dst) {
+// Renormalization plan.  Per target group the sources are combined either
+// before the one-site transform (one dressed operator per target) or after it
+// (one transformed building block per shared source, then a linear
+// combination), whichever needs fewer transforms.
+ContractionPlan& Ctx::renorm_plan(int dir, int i, const OpSet& src, const OpSet& dst) {
+  auto key = std::make_tuple(dir, i, src.first_order ? 1 : 0, 0);
+  auto it = renorm_plans_.find(key);
+  if (it != renorm_plans_.end()) return *it->second;
+  auto P = std::make_unique<ContractionPlan>();
+  const bool leftdir = dir == DMRG_DIR_LEFT;
   const SiteOp& W = H->site_op(i, 1);
   const SiteLayout& S = layout(i, 1);
   const Bond& bl = bonds[i];
   const Bond& br = bonds[i + 1];
-  const BondChannels& B0 = H->channels(i);
-  std::vector<Group> G = group_entries(W, false, B0.find(chan_key(CH_H_ID, -1, -1)));
-  DressPlan P;
-  plan_renorm(*this, G, src, B0, H->channels(i + 1), i + 1, i, false, P);
-  for (auto& C : dst.classes) launch_fill_f64(C.data.as<double>(), long(C.data.bytes / 8), 0.0, stream);
-  for (auto& C : P.blocks.classes) launch_fill_f64(C.data.as<double>(), long(C.data.bytes / 8), 0.0, stream);
-  LinComb form;
-  emit_dressed(P.dressed, P.pend, form);
-  form.run(*this, 1, 0);
-  // stage 1: T(Z, a, n) = Z(c'<-c) R_ket(a, n, c)^T   (m_c' x m_a)
-  GemmList st1, st2;
-  std::map<std::pair<const double*, int>, size_t> toff;
-  size_t tsize = 0;
-  std::vector<std::tuple<ORef, int, size_t>> need;
-  for (auto& j : P.jobs) {
-    if (j.X.identity()) continue;
-    const DotString& ds = H->dot_string(1, j.sid);
-    for (size_t e = 0; e < ds.val.size(); ++e)
-      for (int a = 0; a < int(bl.q.size()); ++a) {
-        const int b = S.find(a, ds.ket[e]);
-        if (b < 0 || opblk(j.X, S.blk[b].c) < 0) continue;
-        auto key = std::make_pair(j.X.p, b);
-        if (toff.count(key)) continue;
-        toff[key] = tsize;
-        need.push_back({j.X, b, tsize});
-        tsize += size_t(br.dim[opbra(j.X, S.blk[b].c)]) * S.blk[b].rows;
+  const int tb = leftdir ? i + 1 : i;  // bond of the targets
+  const int db = leftdir ? i : i + 1;  // bond of sources / dressed operators
+  const BondChannels& Bt = H->channels(tb);
+  const BondChannels& Bs = H->channels(db);
+  const int skip = leftdir ? Bt.find(chan_key(CH_ID_H, -1, -1)) : Bt.find(chan_key(CH_H_ID, -1, -1));
+  std::vector<Group> G = group_entries(W, leftdir, skip);
+  for (auto& g : G) {
+    std::vector<std::pair<int, double>> keep;
+    for (auto& s : g.src)
+      if (src.kind[s.first] != REF_ZERO) keep.push_back(s);
+    g.src.swap(keep);
+  }
+  std::map<std::pair<int, int>, int> fan;
+  for (auto& g : G)
+    for (auto& s : g.src) fan[{s.first, g.sid}]++;
+  Pool dressed{B_DRESS}, blocks{B_BLK};
+  std::vector<std::pair<ORef, Sources>> pend;
+  std::vector<RJob> jobs;
+  std::map<std::pair<int, int>, ORef> block_of;
+  std::vector<std::tuple<ORef, ORef, double>> combine;  // target, block, c
+  for (auto& g : G) {
+    if (g.src.empty()) continue;
+    double share = 0;
+    for (auto& s : g.src) share += 1.0 / fan[{s.first, g.sid}];
+    const bool after = g.src.size() > 1 && share < 1.0 - 1e-9;
+    const DotString& ds = H->dot_string(1, g.sid);
+    const ORef tgt = dst.ref(g.key_ch, B_DST);
+    const Channel& tch = Bt.ch[g.key_ch];
+    if (!after) {
+      const int pz = leftdir ? 0 : Bs.ch[g.src[0].first].parity;
+      if (g.src.size() == 1) {
+        jobs.push_back({src.ref(g.src[0].first, B_SRC), g.src[0].second, g.sid, tgt, pz});
+      } else {
+        Sources ss;
+        for (auto& s : g.src) ss.push_back({src.ref(s.first, B_SRC), s.second});
+        const int sa = leftdir ? tch.dna - ds.dna : tch.dna + ds.dna;
+        const int sb = leftdir ? tch.dnb - ds.dnb : tch.dnb + ds.dnb;
+        ORef d = dressed.add(op_layout(db, sa, sb));
+        pend.push_back({d, std::move(ss)});
+        jobs.push_back({d, 1.0, g.sid, tgt, pz});
       }
+    } else {
+      for (auto& s : g.src) {
+        auto k2 = std::make_pair(s.first, g.sid);
+        auto f = block_of.find(k2);
+        ORef blk;
+        if (f == block_of.end()) {
+          blk = blocks.add(tgt.lay);
+          block_of[k2] = blk;
+          jobs.push_back({src.ref(s.first, B_SRC), 1.0, g.sid, blk, leftdir ? 0 : Bs.ch[s.first].parity});
+        } else {
+          blk = f->second;
+        }
+        combine.push_back({tgt, blk, s.second});
+      }
+    }
   }
-  DBuf T;
-  T.alloc(this, std::max<size_t>(tsize, 1) * 8);
-  double* Tp = T.as<double>();
-  for (auto& nd : need) {
-    const ORef& Z = std::get<0>(nd);
-    const auto& blk = S.blk[std::get<1>(nd)];
-    const int cp = opbra(Z, blk.c);
-    const int jb = st1.job(Tp + std::get<2>(nd), blk.rows, br.dim[cp], blk.rows, 0);
-    st1.add(jb, {opptr(Z, blk.c), Aket + blk.off, blk.cols, blk.cols, blk.cols, GC_TRANS_B, 1.0});
-  }
-  // stage 2: target(a'<-a) += alpha val sign R_bra(a',n',c') T
-  for (auto& j : P.jobs) {
+  LinCombBuilder form;
+  for (auto& p : pend) emit_formation(form, p.first, p.second);
+  form.finish(*this, P->form);
+  P->dressed_per_vec = dressed.size;
+  P->blocks_per_vec = blocks.size;
+  TwoStageBuilder TB;
+  for (auto& j : jobs) {
     const DotString& ds = H->dot_string(1, j.sid);
-    const ORef tgt = j.tkind == 0 ? dst.ref(j.tgt) : P.blocks.ref(j.tgt);
     for (size_t e = 0; e < ds.val.size(); ++e) {
       const int n = ds.ket[e], np = ds.bra[e];
-      const QN qn = site_qn(n), qnp = site_qn(np);
       for (int a = 0; a < int(bl.q.size()); ++a) {
         const int b = S.find(a, n);
         if (b < 0) continue;
         const int c = S.blk[b].c;
-        if (opblk(j.X, c) < 0) continue;
-        const int cp = opbra(j.X, c);
-        const int ap = bl.find(QN{br.q[cp].na - qnp.na, br.q[cp].nb - qnp.nb});
-        if (ap < 0) continue;
-        const int bp = S.find(ap, np);
-        if (bp < 0 || S.blk[bp].c != cp) continue;
-        const int tb = tgt.lay->by_ket[a];
-        DMRG_REQUIRE(tb >= 0 && tgt.lay->blk[tb].bra == ap, DMRG_ERR_INTERNAL, "right renorm target block mismatch");
-        const double sign = (j.pz && ((qn.na + qn.nb) & 1)) ? -1.0 : 1.0;
-        double* out = const_cast<double*>(tgt.p) + tgt.lay->blk[tb].off;
-        const int jb = st2.job(out, S.blk[b].rows, S.blk[bp].rows, S.blk[b].rows, GJ_ACCUMULATE);
-        const double al = j.alpha * ds.val[e] * sign;
-        if (j.X.identity())
-          st2.add(jb, {Abra + S.blk[bp].off, Aket + S.blk[b].off, S.blk[bp].cols, S.blk[b].cols, S.blk[b].cols,
-                       GC_TRANS_B, al});
-        else
-          st2.add(jb, {Abra + S.blk[bp].off, Tp + toff[{j.X.p, b}], S.blk[bp].cols, S.blk[b].rows, br.dim[cp], 0, al});
+        if (leftdir) {
+          // T = X(a'<-a) A_ket(a,n,c);  tgt(c'<-c) += al A_bra(a',n',c')^T T
+          if (!has_blk(j.X, a)) continue;
+          const int ap = opbra(j.X, a);
+          const int bp = S.find(ap, np);
+          if (bp < 0) continue;
+          const int cp = S.blk[bp].c;
+          const int tbk = j.tgt.lay->by_ket[c];
+          DMRG_REQUIRE(tbk >= 0 && j.tgt.lay->blk[tbk].bra == cp, DMRG_ERR_INTERNAL, "left renorm block mismatch");
+          const double sign = (ds.parity && (bl.q[a].n() & 1)) ? -1.0 : 1.0;
+          TwoStageBuilder::S2 s2{};
+          s2.offC = j.tgt.off + long(j.tgt.lay->blk[tbk].off);
+          s2.baseC = j.tgt.base;
+          s2.ldc = S.blk[b].cols;
+          s2.m = S.blk[bp].cols;
+          s2.n = S.blk[b].cols;
+          s2.con = {long(S.blk[bp].off), 0, S.blk[bp].cols, S.blk[b].cols, bl.dim[ap], GC_TRANS_A, B_ABRA, B_AKET,
+                    j.alpha * ds.val[e] * sign};
+          if (j.X.kind == REF_IDENTITY) {
+            s2.t1 = -1;
+            s2.con.offB = long(S.blk[b].off);
+          } else {
+            auto tk = std::make_tuple(j.X.base, j.X.off, b);
+            auto f = TB.t1_of.find(tk);
+            if (f == TB.t1_of.end()) {
+              TwoStageBuilder::T1 t{};
+              t.elems = long(bl.dim[ap]) * S.blk[b].cols;
+              t.job.ldc = S.blk[b].cols;
+              t.job.m = bl.dim[ap];
+              t.job.n = S.blk[b].cols;
+              t.con = {opoff(j.X, a), long(S.blk[b].off), S.blk[b].rows, S.blk[b].cols, S.blk[b].rows, 0, j.X.base,
+                       B_AKET, 1.0};
+              TB.t1.push_back(t);
+              f = TB.t1_of.emplace(tk, int(TB.t1.size()) - 1).first;
+            }
+            s2.t1 = f->second;
+            s2.con.offB = 0;
+          }
+          TB.s2.push_back(s2);
+        } else {
+          // T = Z(c'<-c) R_ket(a,n,c)^T;  tgt(a'<-a) += al R_bra(a',n',c') T
+          if (!has_blk(j.X, c)) continue;
+          const int cp = opbra(j.X, c);
+          const QN qnp = site_qn(np);
+          const int ap = bl.find(QN{br.q[cp].na - qnp.na, br.q[cp].nb - qnp.nb});
+          if (ap < 0) continue;
+          const int bp = S.find(ap, np);
+          if (bp < 0 || S.blk[bp].c != cp) continue;
+          const int tbk = j.tgt.lay->by_ket[a];
+          DMRG_REQUIRE(tbk >= 0 && j.tgt.lay->blk[tbk].bra == ap, DMRG_ERR_INTERNAL, "right renorm block mismatch");
+          const double sign = (j.pz && (site_qn(n).n() & 1)) ? -1.0 : 1.0;
+          TwoStageBuilder::S2 s2{};
+          s2.offC = j.tgt.off + long(j.tgt.lay->blk[tbk].off);
+          s2.baseC = j.tgt.base;
+          s2.ldc = S.blk[b].rows;
+          s2.m = S.blk[bp].rows;
+          s2.n = S.blk[b].rows;
+          if (j.X.kind == REF_IDENTITY) {
+            s2.t1 = -1;
+            s2.con = {long(S.blk[bp].off), long(S.blk[b].off), S.blk[bp].cols, S.blk[b].cols, S.blk[b].cols,
+                      GC_TRANS_B, B_ABRA, B_AKET, j.alpha * ds.val[e] * sign};
+          } else {
+            auto tk = std::make_tuple(j.X.base, j.X.off, b);
+            auto f = TB.t1_of.find(tk);
+            if (f == TB.t1_of.end()) {
+              TwoStageBuilder::T1 t{};
+              t.elems = long(br.dim[cp]) * S.blk[b].rows;
+              t.job.ldc = S.blk[b].rows;
+              t.job.m = br.dim[cp];
+              t.job.n = S.blk[b].rows;
+              t.con = {opoff(j.X, c), long(S.blk[b].off), S.blk[b].cols, S.blk[b].cols, S.blk[b].cols, GC_TRANS_B,
+                       j.X.base, B_AKET, 1.0};
+              TB.t1.push_back(t);
+              f = TB.t1_of.emplace(tk, int(TB.t1.size()) - 1).first;
+            }
+            s2.t1 = f->second;
+            s2.con = {long(S.blk[bp].off), 0, S.blk[bp].cols, S.blk[b].rows, br.dim[cp], 0, B_ABRA, B_T,
+                      j.alpha * ds.val[e] * sign};
+          }
+          TB.s2.push_back(s2);
+        }
       }
     }
   }
-  st1.run(*this, 1, 0, 0, 0);
-  st2.run(*this, 1, 0, 0, 0);
-  stats.renorm_flops += st1.flops(1) + st2.flops(1);
-  finish_renorm(*this, P, dst);
+  finish_two_stage(*this, TB, P->main, false);
+  LinCombBuilder post;
+  std::map<std::pair<int, long>, std::vector<std::pair<ORef, double>>> by_tgt;
+  for (auto& cb : combine)
+    by_tgt[{std::get<0>(cb).base, std::get<0>(cb).off}].push_back({std::get<1>(cb), std::get<2>(cb)});
+  for (auto& kv : by_tgt) {
+    const ORef& first = kv.second.front().first;
+    post.target(kv.first.first, kv.first.second, long(first.lay->size), true);
+    for (auto& s : kv.second) post.source(s.first.base, s.first.off, s.second);
+  }
+  post.finish(*this, P->post);
+  return *(renorm_plans_[key] = std::move(P));
+}
+
+void Ctx::renorm(int dir, int i, const double* Abra, const double* Aket, long aket_stride, const OpSet& src,
+                 OpSet& dst, bool accumulate, int batch) {
+  ContractionPlan& P = renorm_plan(dir, i, src, dst);
+  const bool src_b = src.nvec > 1, ket_b = aket_stride != 0;
+  const bool t_b = src_b || ket_b;
+  Bases b{};
+  b.p[B_ABRA] = const_cast<double*>(Abra);
+  b.p[B_AKET] = const_cast<double*>(Aket);
+  b.stride[B_AKET] = aket_stride;
+  b.p[B_SRC] = src.ptr();
+  b.stride[B_SRC] = src_b ? src.per_vec : 0;
+  b.p[B_DST] = dst.ptr();
+  b.stride[B_DST] = dst.nvec > 1 ? dst.per_vec : 0;
+  ws_dress.ensure(this, std::max<size_t>(size_t(P.dressed_per_vec) * (src_b ? batch : 1), 1) * 8);
+  ws_blk.ensure(this, std::max<size_t>(size_t(P.blocks_per_vec) * (t_b ? batch : 1), 1) * 8);
+  ws_T.ensure(this, std::max<size_t>(size_t(P.main.t_per_vec) * (t_b ? batch : 1), 1) * 8);
+  b.p[B_DRESS] = ws_dress.as<double>();
+  b.stride[B_DRESS] = src_b ? P.dressed_per_vec : 0;
+  b.p[B_BLK] = ws_blk.as<double>();
+  b.stride[B_BLK] = t_b ? P.blocks_per_vec : 0;
+  b.p[B_T] = ws_T.as<double>();
+  b.stride[B_T] = t_b ? P.main.t_per_vec : 0;
+  if (!accumulate) launch_fill_f64(dst.ptr(), long(dst.per_vec) * dst.nvec, 0.0, stream);
+  if (P.blocks_per_vec) launch_fill_f64(ws_blk.as<double>(), P.blocks_per_vec * (t_b ? batch : 1), 0.0, stream);
+  P.form.launch(*this, b, src_b ? batch : 1);
+  for (auto& ch : P.main.chunks) {
+    ch.first.launch(*this, b, t_b ? batch : 1);
+    ch.second.launch(*this, b, batch);
+  }
+  P.post.launch(*this, b, batch);
+  stats.renorm_flops += P.main.flops1 * (t_b ? batch : 1) + P.main.flops2 * batch;
 }
 
 void Ctx::build_ops(int prec) {
@@ -628,15 +726,15 @@ void Ctx::build_ops(int prec) {
   DMRG_HIP(hipEventCreate(&e0));
   DMRG_HIP(hipEventCreate(&e1));
   DMRG_HIP(hipEventRecord(e0, stream));
-  alloc_opset(left[0], 0, 0);
+  alloc_opset(left[0], 0, 0, 1, false);
   for (int i = 0; i < L; ++i) {
-    alloc_opset(left[i + 1], i + 1, 0);
-    renorm_left(i, site[i].L.as<double>(), site[i].L.as<double>(), left[i], left[i + 1]);
+    alloc_opset(left[i + 1], i + 1, 0, 1, false);
+    renorm(DMRG_DIR_LEFT, i, site[i].L.as<double>(), site[i].L.as<double>(), 0, left[i], left[i + 1], false, 1);
   }
-  alloc_opset(right[L], L, 1);
+  alloc_opset(right[L], L, 1, 1, false);
   for (int i = L - 1; i >= 0; --i) {
-    alloc_opset(right[i], i, 1);
-    renorm_right(i, site[i].R.as<double>(), site[i].R.as<double>(), right[i + 1], right[i]);
+    alloc_opset(right[i], i, 1, 1, false);
+    renorm(DMRG_DIR_RIGHT, i, site[i].R.as<double>(), site[i].R.as<double>(), 0, right[i + 1], right[i], false, 1);
   }
   DMRG_HIP(hipEventRecord(e1, stream));
   DMRG_HIP(hipEventSynchronize(e1));
@@ -661,48 +759,105 @@ struct STerm {
   double alpha;
   int pz;  // parity of the right-block operator
 };
+
+// Terms of H_eff on the dot (i, width) with operators X (left, base B_LOPS)
+// and Z (right, base B_ROPS); the channel site operator is dressed on the
+// side that needs fewer formed operators.
+std::vector<STerm> sigma_terms(Ctx& x, int i, int width, const OpSet& X, const OpSet& Z, Pool& pool,
+                               LinCombBuilder& form, bool& left_dressed) {
+  const SiteOp& W = x.H->site_op(i, width);
+  const BondChannels& B0 = x.H->channels(i);
+  const BondChannels& B1 = x.H->channels(i + width);
+  std::vector<Group> GL = group_entries(W, true, -1), GR = group_entries(W, false, -1);
+  auto prune = [&](std::vector<Group>& G, bool by_dst) {
+    std::vector<Group> out;
+    for (auto& g : G) {
+      const int kk = by_dst ? Z.kind[g.key_ch] : X.kind[g.key_ch];
+      if (kk == REF_ZERO) continue;
+      std::vector<std::pair<int, double>> keep;
+      for (auto& s : g.src) {
+        const int sk = by_dst ? X.kind[s.first] : Z.kind[s.first];
+        if (sk != REF_ZERO) keep.push_back(s);
+      }
+      if (keep.empty()) continue;
+      g.src.swap(keep);
+      out.push_back(std::move(g));
+    }
+    G.swap(out);
+  };
+  prune(GL, true);
+  prune(GR, false);
+  size_t fl = 0, fr = 0;
+  for (auto& g : GL) fl += g.src.size() > 1;
+  for (auto& g : GR) fr += g.src.size() > 1;
+  left_dressed = fl <= fr;
+  std::vector<STerm> terms;
+  for (auto& g : left_dressed ? GL : GR) {
+    const DotString& ds = x.H->dot_string(width, g.sid);
+    STerm t{};
+    t.sid = g.sid;
+    if (left_dressed) {
+      t.Z = Z.ref(g.key_ch, B_ROPS);
+      t.pz = B1.ch[g.key_ch].parity;
+      if (g.src.size() == 1) {
+        t.X = X.ref(g.src[0].first, B_LOPS);
+        t.alpha = g.src[0].second;
+      } else {
+        Sources ss;
+        for (auto& s : g.src) ss.push_back({X.ref(s.first, B_LOPS), s.second});
+        const Channel& ch = B1.ch[g.key_ch];
+        t.X = pool.add(x.op_layout(i, ch.dna - ds.dna, ch.dnb - ds.dnb));
+        emit_formation(form, t.X, ss);
+        t.alpha = 1.0;
+      }
+    } else {
+      t.X = X.ref(g.key_ch, B_LOPS);
+      t.pz = B1.ch[g.src[0].first].parity;
+      if (g.src.size() == 1) {
+        t.Z = Z.ref(g.src[0].first, B_ROPS);
+        t.alpha = g.src[0].second;
+      } else {
+        Sources ss;
+        for (auto& s : g.src) ss.push_back({Z.ref(s.first, B_ROPS), s.second});
+        const Channel& ch = B0.ch[g.key_ch];
+        t.Z = pool.add(x.op_layout(i + width, ch.dna + ds.dna, ch.dnb + ds.dnb));
+        emit_formation(form, t.Z, ss);
+        t.alpha = 1.0;
+      }
+    }
+    terms.push_back(t);
+  }
+  return terms;
+}
+
+inline int term_sign(const DotString& ds, const STerm& t, int nleft, int ndot) {
+  int sgn = 1;
+  if (((ds.parity + t.pz) & 1) && (nleft & 1)) sgn = -sgn;
+  if (t.pz && (ndot & 1)) sgn = -sgn;
+  return sgn;
+}
 }  // namespace
 
-// sigma = sum_t alpha_t (X_t P^{p(sid)+p(Z)} (x) sid P_D^{p(Z)} (x) Z_t) C
-static void exec_sigma(Ctx& x, int i, int width, const std::vector<STerm>& terms, int nvec, const double* Cin,
-                       double* Sout, double* flops_out, float* ms_out, float* main_ms) {
-  const SiteLayout& S = x.layout(i, width);
-  const Bond& bl = x.bonds[i];
-  const Bond& br = x.bonds[i + width];
-  GemmList st1, st2;
-  std::map<std::pair<const double*, int>, size_t> toff;
-  size_t tsize = 0;
-  std::vector<std::tuple<ORef, int, size_t>> need;
-  for (auto& t : terms) {
-    if (t.Z.identity()) continue;
-    const DotString& ds = x.H->dot_string(width, t.sid);
-    for (size_t e = 0; e < ds.val.size(); ++e)
-      for (int a = 0; a < int(bl.q.size()); ++a) {
-        const int b = S.find(a, ds.ket[e]);
-        if (b < 0 || opblk(t.Z, S.blk[b].c) < 0 || opblk(t.X, a) < 0) continue;
-        auto key = std::make_pair(t.Z.p, b);
-        if (toff.count(key)) continue;
-        toff[key] = tsize;
-        need.push_back({t.Z, b, tsize});
-        tsize += size_t(S.blk[b].rows) * br.dim[opbra(t.Z, S.blk[b].c)];
-      }
-  }
-  DBuf T;
-  T.alloc(&x, std::max<size_t>(tsize, 1) * 8 * nvec);
-  double* Tp = T.as<double>();
-  // stage 1: T(Z, a, n, c) = C(a,n,c) Z(c'<-c)^T   (m_a x m_c')
-  for (auto& nd : need) {
-    const ORef& Z = std::get<0>(nd);
-    const auto& blk = S.blk[std::get<1>(nd)];
-    const int cp = opbra(Z, blk.c);
-    const int jb = st1.job(Tp + std::get<2>(nd), br.dim[cp], blk.rows, br.dim[cp], GJ_C_BATCHED);
-    st1.add(jb, {Cin + blk.off, opptr(Z, blk.c), blk.cols, blk.cols, blk.cols, GC_TRANS_B | GC_A_BATCHED, 1.0});
-  }
-  // stage 2: sigma(a',n',c') = sum alpha val sign X(a'<-a) T
+ContractionPlan& Ctx::sigma_plan(int i, int width, const OpSet& X, const OpSet& Z) {
+  auto key = std::make_tuple(i, width, X.first_order ? 1 : 0, Z.first_order ? 1 : 0);
+  auto it = sigma_plans_.find(key);
+  if (it != sigma_plans_.end()) return *it->second;
+  auto P = std::make_unique<ContractionPlan>();
+  const SiteLayout& S = layout(i, width);
+  const Bond& bl = bonds[i];
+  const Bond& br = bonds[i + width];
+  Pool pool{B_DRESS};
+  LinCombBuilder form;
+  bool ld = true;
+  std::vector<STerm> terms = sigma_terms(*this, i, width, X, Z, pool, form, ld);
+  form.finish(*this, P->form);
+  P->dressed_per_vec = pool.size;
+  P->dress_left = ld;
+  TwoStageBuilder TB;
   for (size_t b = 0; b < S.blk.size(); ++b)
-    st2.job(Sout + S.blk[b].off, S.blk[b].cols, S.blk[b].rows, S.blk[b].cols, GJ_C_BATCHED);
+    TB.outputs.push_back({long(S.blk[b].off), B_SOUT, S.blk[b].cols, S.blk[b].rows, S.blk[b].cols});
   for (auto& t : terms) {
-    const DotString& ds = x.H->dot_string(width, t.sid);
+    const DotString& ds = H->dot_string(width, t.sid);
     for (size_t e = 0; e < ds.val.size(); ++e) {
       const int n = ds.ket[e], np = ds.bra[e];
       const int nd = dot_qn(n, width).n();
@@ -710,181 +865,173 @@ static void exec_sigma(Ctx& x, int i, int width, const std::vector<STerm>& terms
         const int b = S.find(a, n);
         if (b < 0) continue;
         const int c = S.blk[b].c;
-        if (opblk(t.Z, c) < 0 || opblk(t.X, a) < 0) continue;
+        if (!has_blk(t.Z, c) || !has_blk(t.X, a)) continue;
         const int cp = opbra(t.Z, c), ap = opbra(t.X, a);
         const int bp = S.find(ap, np);
         if (bp < 0 || S.blk[bp].c != cp) continue;
-        int sgn = 1;
-        if (((ds.parity + t.pz) & 1) && (bl.q[a].n() & 1)) sgn = -sgn;
-        if (t.pz && (nd & 1)) sgn = -sgn;
-        const int jb = st2.job(Sout + S.blk[bp].off, S.blk[bp].cols, S.blk[bp].rows, S.blk[bp].cols, GJ_C_BATCHED);
-        GContrib g;
-        g.A = t.X.identity() ? nullptr : opptr(t.X, a);
-        g.lda = S.blk[b].rows;
+        TwoStageBuilder::S2 s2{};
+        s2.offC = long(S.blk[bp].off);
+        s2.baseC = B_SOUT;
+        s2.ldc = S.blk[bp].cols;
+        s2.m = S.blk[bp].rows;
+        s2.n = S.blk[bp].cols;
+        GContrib g{};
         g.k = S.blk[b].rows;
-        g.alpha = t.alpha * ds.val[e] * sgn;
-        g.flags = (t.X.identity() ? GC_A_IDENTITY : 0);
-        if (t.Z.identity()) {
-          g.B = Cin + S.blk[b].off;
-          g.ldb = S.blk[b].cols;
-          g.flags |= GC_B_BATCHED_ALT;
+        g.lda = S.blk[b].rows;
+        g.alpha = t.alpha * ds.val[e] * term_sign(ds, t, bl.q[a].n(), nd);
+        if (t.X.kind == REF_IDENTITY) {
+          g.flags = GC_A_IDENTITY;
+          g.baseA = B_LOPS;
         } else {
-          g.flags |= GC_B_BATCHED;
-          g.B = Tp + toff[{t.Z.p, b}];
+          g.offA = opoff(t.X, a);
+          g.baseA = t.X.base;
+        }
+        if (t.Z.kind == REF_IDENTITY) {
+          s2.t1 = -1;
+          g.offB = long(S.blk[b].off);
+          g.baseB = B_CIN;
+          g.ldb = S.blk[b].cols;
+        } else {
+          auto tk = std::make_tuple(t.Z.base, t.Z.off, int(b));
+          auto f = TB.t1_of.find(tk);
+          if (f == TB.t1_of.end()) {
+            // T(Z, a, n, c) = C(a,n,c) Z(c'<-c)^T  (m_a x m_c')
+            TwoStageBuilder::T1 t1{};
+            t1.elems = long(S.blk[b].rows) * br.dim[cp];
+            t1.job.ldc = br.dim[cp];
+            t1.job.m = S.blk[b].rows;
+            t1.job.n = br.dim[cp];
+            t1.con = {long(S.blk[b].off), opoff(t.Z, c), S.blk[b].cols, S.blk[b].cols, S.blk[b].cols, GC_TRANS_B,
+                      B_CIN, t.Z.base, 1.0};
+            TB.t1.push_back(t1);
+            f = TB.t1_of.emplace(tk, int(TB.t1.size()) - 1).first;
+          }
+          s2.t1 = f->second;
+          g.offB = 0;
+          g.baseB = B_T;
           g.ldb = br.dim[cp];
         }
-        st2.add(jb, g);
+        s2.con = g;
+        TB.s2.push_back(s2);
       }
     }
   }
-  hipEvent_t e0, e1, e2;
-  DMRG_HIP(hipEventCreate(&e0));
-  DMRG_HIP(hipEventCreate(&e1));
-  DMRG_HIP(hipEventCreate(&e2));
-  DMRG_HIP(hipEventRecord(e0, x.stream));
-  st1.run(x, nvec, long(S.size), 0, long(tsize));
-  DMRG_HIP(hipEventRecord(e1, x.stream));
-  st2.run(x, nvec, long(S.size), long(tsize), long(S.size));
-  DMRG_HIP(hipEventRecord(e2, x.stream));
-  DMRG_HIP(hipEventSynchronize(e2));
-  float a = 0, b2 = 0;
-  DMRG_HIP(hipEventElapsedTime(&a, e0, e2));
-  DMRG_HIP(hipEventElapsedTime(&b2, e1, e2));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  (void)hipEventDestroy(e2);
-  if (flops_out) {
-    flops_out[0] = st1.flops(nvec) + st2.flops(nvec);
-    flops_out[1] = st2.flops(nvec);
-  }
-  if (ms_out) *ms_out = a;
-  if (main_ms) *main_ms = b2;
+  finish_two_stage(*this, TB, P->main, true);
+  return *(sigma_plans_[key] = std::move(P));
 }
 
-// Terms of the effective Hamiltonian on the dot (i, width): the channel site
-// operator is dressed on the side that needs fewer formed operators.
-static std::vector<STerm> sigma_terms(Ctx& x, int i, int width, OpPool& pool, LinComb& form) {
-  const SiteOp& W = x.H->site_op(i, width);
-  const OpSet& Lset = x.left[i];
-  const OpSet& Rset = x.right[i + width];
-  const BondChannels& B0 = x.H->channels(i);
-  const BondChannels& B1 = x.H->channels(i + width);
-  std::vector<Group> GL = group_entries(W, true, -1), GR = group_entries(W, false, -1);
-  size_t fl = 0, fr = 0;
-  for (auto& g : GL) fl += g.src.size() > 1;
-  for (auto& g : GR) fr += g.src.size() > 1;
-  const bool left_dressed = fl <= fr;
-  std::vector<STerm> terms;
-  std::vector<std::pair<int, Sources>> pend;
-  std::vector<std::pair<size_t, int>> fix;  // term -> dressed item
-  pool.bond = left_dressed ? i : i + width;
-  for (auto& g : left_dressed ? GL : GR) {
-    const DotString& ds = x.H->dot_string(width, g.sid);
-    STerm t{};
-    t.sid = g.sid;
-    if (left_dressed) {
-      t.Z = Rset.ref(g.key_ch);
-      t.pz = B1.ch[g.key_ch].parity;
-      if (g.src.size() == 1) {
-        t.X = Lset.ref(g.src[0].first);
-        t.alpha = g.src[0].second;
-      } else {
-        Sources ss;
-        for (auto& s : g.src) ss.push_back({Lset.ref(s.first), s.second});
-        const Channel& ch = B1.ch[g.key_ch];
-        const int id = pool.add(x.op_layout(i, ch.dna - ds.dna, ch.dnb - ds.dnb));
-        pend.push_back({id, std::move(ss)});
-        fix.push_back({terms.size(), id});
-        t.alpha = 1.0;
-      }
-    } else {
-      t.X = Lset.ref(g.key_ch);
-      t.pz = B1.ch[g.src[0].first].parity;
-      if (g.src.size() == 1) {
-        t.Z = Rset.ref(g.src[0].first);
-        t.alpha = g.src[0].second;
-      } else {
-        Sources ss;
-        for (auto& s : g.src) ss.push_back({Rset.ref(s.first), s.second});
-        const Channel& ch = B0.ch[g.key_ch];
-        const int id = pool.add(x.op_layout(i + width, ch.dna + ds.dna, ch.dnb + ds.dnb));
-        pend.push_back({id, std::move(ss)});
-        fix.push_back({terms.size(), id});
-        t.alpha = 1.0;
-      }
-    }
-    terms.push_back(t);
+void Ctx::sigma_general(int i, int width, const OpSet& X, const OpSet& Z, const double* C, long cstride, double* Sv,
+                        long sstride, int batch, bool accumulate) {
+  DMRG_REQUIRE(!accumulate, DMRG_ERR_INTERNAL, "accumulating sigma not supported");
+  ContractionPlan& P = sigma_plan(i, width, X, Z);
+  const bool xb = X.nvec > 1, zb = Z.nvec > 1, cb = cstride != 0;
+  const bool dress_b = P.dress_left ? xb : zb;
+  const bool t_b = cb || zb;
+  Bases b{};
+  b.p[B_CIN] = const_cast<double*>(C);
+  b.stride[B_CIN] = cstride;
+  b.p[B_SOUT] = Sv;
+  b.stride[B_SOUT] = sstride;
+  b.p[B_LOPS] = X.ptr();
+  b.stride[B_LOPS] = xb ? X.per_vec : 0;
+  b.p[B_ROPS] = Z.ptr();
+  b.stride[B_ROPS] = zb ? Z.per_vec : 0;
+  ws_dress.ensure(this, std::max<size_t>(size_t(P.dressed_per_vec) * (dress_b ? batch : 1), 1) * 8);
+  ws_T.ensure(this, std::max<size_t>(size_t(P.main.t_per_vec) * (t_b ? batch : 1), 1) * 8);
+  b.p[B_DRESS] = ws_dress.as<double>();
+  b.stride[B_DRESS] = dress_b ? P.dressed_per_vec : 0;
+  b.p[B_T] = ws_T.as<double>();
+  b.stride[B_T] = t_b ? P.main.t_per_vec : 0;
+  P.form.launch(*this, b, dress_b ? batch : 1);
+  for (auto& ch : P.main.chunks) {
+    ch.first.launch(*this, b, t_b ? batch : 1);
+    ch.second.launch(*this, b, batch);
   }
-  pool.allocate(&x);
-  for (auto& f : fix) {
-    if (left_dressed) terms[f.first].X = pool.ref(f.second);
-    else terms[f.first].Z = pool.ref(f.second);
-  }
-  emit_dressed(pool, pend, form);
-  return terms;
+  stats.sigma_flops = P.main.flops1 * (t_b ? batch : 1) + P.main.flops2 * batch;
+  stats.sigma_main_flops = P.main.flops2 * batch;
 }
 
 void Ctx::sigma(int i, int width, int nvec, const double* Cin, double* Sout) {
   require_gpu();
   DMRG_REQUIRE(ops_prec >= 0, DMRG_ERR_STATE, "call dmrg_build_ops first");
   DMRG_REQUIRE(nvec >= 1 && Cin && Sout, DMRG_ERR_INVALID_ARG, "bad sigma arguments");
-  OpPool pool;
-  LinComb form;
-  std::vector<STerm> terms = sigma_terms(*this, i, width, pool, form);
-  form.run(*this, 1, 0);
-  double fl[2] = {0, 0};
-  float ms = 0, mms = 0;
-  exec_sigma(*this, i, width, terms, nvec, Cin, Sout, fl, &ms, &mms);
-  stats.sigma_flops = fl[0];
-  stats.sigma_main_flops = fl[1];
+  const SiteLayout& S = layout(i, width);
+  sigma_plan(i, width, left[i], right[i + width]);  // plan outside the timed region
+  hipEvent_t e0, e1;
+  DMRG_HIP(hipEventCreate(&e0));
+  DMRG_HIP(hipEventCreate(&e1));
+  DMRG_HIP(hipEventRecord(e0, stream));
+  sigma_general(i, width, left[i], right[i + width], Cin, long(S.size), Sout, long(S.size), nvec);
+  DMRG_HIP(hipEventRecord(e1, stream));
+  DMRG_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  DMRG_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   stats.sigma_ms = ms;
-  stats.sigma_main_ms = mms;
 }
 
 void Ctx::diag(int i, int width, double* out) {
   require_gpu();
   DMRG_REQUIRE(ops_prec >= 0, DMRG_ERR_STATE, "call dmrg_build_ops first");
-  OpPool pool;
-  LinComb form;
-  std::vector<STerm> terms = sigma_terms(*this, i, width, pool, form);
-  form.run(*this, 1, 0);
+  auto key = std::make_pair(i, width);
+  auto it = diag_plans_.find(key);
   const SiteLayout& S = layout(i, width);
-  const Bond& bl = bonds[i];
-  std::vector<std::vector<DiagTerm>> per(S.blk.size());
-  for (auto& t : terms) {
-    if (t.X.lay && (t.X.lay->dna || t.X.lay->dnb)) continue;
-    if (t.Z.lay && (t.Z.lay->dna || t.Z.lay->dnb)) continue;
-    const DotString& ds = H->dot_string(width, t.sid);
-    for (size_t e = 0; e < ds.val.size(); ++e) {
-      if (ds.bra[e] != ds.ket[e]) continue;
-      const int n = ds.ket[e];
-      const int nd = dot_qn(n, width).n();
-      for (int a = 0; a < int(bl.q.size()); ++a) {
-        const int b = S.find(a, n);
-        if (b < 0) continue;
-        const int c = S.blk[b].c;
-        if (opblk(t.X, a) < 0 || opblk(t.Z, c) < 0) continue;
-        int sgn = 1;
-        if (((ds.parity + t.pz) & 1) && (bl.q[a].n() & 1)) sgn = -sgn;
-        if (t.pz && (nd & 1)) sgn = -sgn;
-        per[b].push_back({t.X.identity() ? nullptr : opptr(t.X, a), t.Z.identity() ? nullptr : opptr(t.Z, c),
-                          t.alpha * ds.val[e] * sgn});
+  if (it == diag_plans_.end()) {
+    auto P = std::make_unique<DiagPlan>();
+    Pool pool{B_DRESS};
+    LinCombBuilder form;
+    bool ld = true;
+    std::vector<STerm> terms = sigma_terms(*this, i, width, left[i], right[i + width], pool, form, ld);
+    form.finish(*this, P->form);
+    P->dressed_per_vec = pool.size;
+    const Bond& bl = bonds[i];
+    std::vector<std::vector<DiagTerm>> per(S.blk.size());
+    for (auto& t : terms) {
+      if (t.X.kind == REF_OP && (t.X.lay->dna || t.X.lay->dnb)) continue;
+      if (t.Z.kind == REF_OP && (t.Z.lay->dna || t.Z.lay->dnb)) continue;
+      const DotString& ds = H->dot_string(width, t.sid);
+      for (size_t e = 0; e < ds.val.size(); ++e) {
+        if (ds.bra[e] != ds.ket[e]) continue;
+        const int n = ds.ket[e];
+        const int nd = dot_qn(n, width).n();
+        for (int a = 0; a < int(bl.q.size()); ++a) {
+          const int b = S.find(a, n);
+          if (b < 0) continue;
+          const int c = S.blk[b].c;
+          if (!has_blk(t.X, a) || !has_blk(t.Z, c)) continue;
+          DiagTerm d{};
+          d.offX = t.X.kind == REF_IDENTITY ? -1 : opoff(t.X, a);
+          d.baseX = t.X.kind == REF_IDENTITY ? 0 : t.X.base;
+          d.offZ = t.Z.kind == REF_IDENTITY ? -1 : opoff(t.Z, c);
+          d.baseZ = t.Z.kind == REF_IDENTITY ? 0 : t.Z.base;
+          d.alpha = t.alpha * ds.val[e] * term_sign(ds, t, bl.q[a].n(), nd);
+          per[b].push_back(d);
+        }
       }
     }
+    std::vector<DiagJob> jobs;
+    std::vector<DiagTerm> dt;
+    for (size_t b = 0; b < S.blk.size(); ++b) {
+      jobs.push_back({long(S.blk[b].off), B_SOUT, S.blk[b].rows, S.blk[b].cols, int(dt.size()), 0, 0});
+      dt.insert(dt.end(), per[b].begin(), per[b].end());
+      jobs.back().t1 = int(dt.size());
+    }
+    upload(*this, P->jobs, jobs);
+    upload(*this, P->terms, dt);
+    P->njobs = int(jobs.size());
+    it = diag_plans_.emplace(key, std::move(P)).first;
   }
-  std::vector<DiagJob> jobs;
-  std::vector<DiagTerm> dt;
-  for (size_t b = 0; b < S.blk.size(); ++b) {
-    jobs.push_back({out + S.blk[b].off, S.blk[b].rows, S.blk[b].cols, int(dt.size()), 0});
-    dt.insert(dt.end(), per[b].begin(), per[b].end());
-    jobs.back().t1 = int(dt.size());
-  }
-  DBuf dj, dd;
-  upload(*this, dj, jobs);
-  upload(*this, dd, dt);
-  launch_diag_jobs_f64(dj.as<DiagJob>(), int(jobs.size()), dd.as<DiagTerm>(), stream);
+  DiagPlan& P = *it->second;
+  Bases b{};
+  b.p[B_LOPS] = left[i].ptr();
+  b.p[B_ROPS] = right[i + width].ptr();
+  b.p[B_SOUT] = out;
+  ws_dress.ensure(this, std::max<size_t>(size_t(P.dressed_per_vec), 1) * 8);
+  b.p[B_DRESS] = ws_dress.as<double>();
+  P.form.launch(*this, b, 1);
+  launch_diag_jobs_f64(P.jobs.as<DiagJob>(), P.njobs, P.terms.as<DiagTerm>(), b, stream);
   DMRG_HIP(hipGetLastError());
-  DMRG_HIP(hipStreamSynchronize(stream));
 }
 
 }  // namespace dmrg

@@ -1,8 +1,9 @@
-// Context, operator pools and the contraction planners (host side).
+// Context, operator sets and the contraction planners (host side).
 #pragma once
 #include <map>
 #include <memory>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "common.hpp"
@@ -30,81 +31,96 @@ struct DBuf {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
-// Reference to an operator (or the identity) at one bond.
-struct ORef {
-  const double* p = nullptr;
-  const OpLayout* lay = nullptr;  // null = identity
-  bool identity() const { return lay == nullptr; }
+// Base slots of the work lists (see kernels.hpp).
+enum : int {
+  B_CIN = 0, B_SOUT = 1, B_T = 2, B_LOPS = 3, B_ROPS = 4, B_DRESS = 5,
+  B_ABRA = 6, B_AKET = 7, B_SRC = 8, B_DST = 9, B_BLK = 10, B_AUX = 11
 };
 
-// Operators of one block at one bond: side 0 = left-block operators Lop_b[w],
-// side 1 = right-block operators Rop_b[w], for every channel w of the bond.
-struct OpClass {
+enum RefKind : int { REF_OP = 0, REF_IDENTITY = 1, REF_ZERO = 2 };
+
+// Reference to an operator (or the identity / zero) inside some base.
+struct ORef {
+  long off = 0;
   const OpLayout* lay = nullptr;
-  int nslots = 0;
-  DBuf data;
+  int kind = REF_IDENTITY;
+  int base = -1;
+  bool op() const { return kind == REF_OP; }
 };
+
+// Operators of one block at one bond for every channel w: side 0 the
+// left-block operators Lop_b[w], side 1 the right-block operators Rop_b[w].
+// A first-order set (bra zeroth order, ket first order) holds nvec copies and
+// its identity channel is zero.
 struct OpSet {
-  int bond = -1, side = 0;
-  bool valid = false;
-  std::vector<int> cls, slot;  // per channel; cls -1 = identity channel
-  std::vector<OpClass> classes;
-  ORef ref(int w) const {
+  int bond = -1, side = 0, nvec = 1;
+  bool first_order = false;
+  std::vector<int> kind;  // per channel: REF_OP / REF_IDENTITY / REF_ZERO
+  std::vector<long> off;
+  std::vector<const OpLayout*> lay;
+  long per_vec = 0;
+  DBuf data;
+  bool valid() const { return bond >= 0; }
+  ORef ref(int w, int base) const {
     ORef r;
-    if (cls[w] < 0) return r;
-    const OpClass& C = classes[cls[w]];
-    r.lay = C.lay;
-    r.p = C.data.as<double>() + size_t(slot[w]) * C.lay->size;
+    r.kind = kind[w];
+    r.base = base;
+    r.off = off[w];
+    r.lay = lay[w];
     return r;
   }
-  size_t bytes() const {
-    size_t b = 0;
-    for (auto& c : classes) b += c.data.bytes;
-    return b;
-  }
+  double* ptr() const { return data.as<double>(); }
+  size_t bytes() const { return data.bytes; }
 };
 
-// Scratch pool of extra operators (dressed operators, building blocks).
-struct OpPool {
-  int bond = -1;
-  std::map<std::pair<int, int>, int> class_of;
-  std::vector<OpClass> classes;
-  struct Item { int cls, slot; };
-  std::vector<Item> items;
-  int add(const OpLayout* lay);  // returns item id (before allocate())
-  void allocate(Ctx* c);
-  ORef ref(int id) const {
-    const OpClass& C = classes[items[id].cls];
-    return ORef{C.data.as<double>() + size_t(items[id].slot) * C.lay->size, C.lay};
-  }
+// Device-resident grouped-GEMM list.
+struct GemmPlan {
+  DBuf tiles, jobs, con;
+  int ntiles = 0;
+  double flops = 0;  // per batch entry
+  void launch(Ctx& x, const Bases& b, int batch) const;
 };
 
-// Device-side execution lists of one contraction step.
-struct GemmList {
-  std::vector<GJob> jobs;
-  std::vector<std::vector<GContrib>> per_job;
-  std::unordered_map<const void*, int> job_of;
-  int job(void* C, int ldc, int m, int n, int flags);
-  void add(int j, const GContrib& c) { per_job[j].push_back(c); }
-  double flops(int batch) const;
-  void run(Ctx& x, int batch, long sA, long sB, long sC);
-  bool empty() const { return jobs.empty(); }
-};
+void build_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<std::vector<GContrib>>& per);
 
-struct LinComb {
-  std::vector<LCTarget> t;
-  std::vector<LCSource> s;
-  std::vector<DiagAdd> d;
+struct LinCombPlan {
+  DBuf t, s, d;
+  int nt = 0, nd = 0;
   long max_size = 0;
-  void target(double* out, long size, bool acc) {
-    t.push_back({out, size, int(s.size()), int(s.size()), acc ? 1 : 0, 0});
-    if (size > max_size) max_size = size;
-  }
-  void source(const double* p, double c) {
-    s.push_back({p, c});
-    t.back().s1 = int(s.size());
-  }
-  void run(Ctx& x, int batch, long stride);
+  void launch(Ctx& x, const Bases& b, int batch) const;
+};
+
+// Host-side builder of a two-stage contraction (stage 1 writes workspace
+// blocks T, stage 2 consumes them), chunked so that T fits a budget.
+struct TwoStageBuilder {
+  struct T1 { long elems; GJob job; GContrib con; };
+  struct S2 { int t1; long offC; int baseC, ldc, m, n; GContrib con; };
+  std::vector<T1> t1;
+  std::map<std::tuple<int, long, int>, int> t1_of;  // (base, offset, block) -> item
+  std::vector<S2> s2;
+  std::vector<std::tuple<long, int, int, int, int>> outputs;  // all outputs (overwrite mode)
+};
+
+struct TwoStagePlan {
+  std::vector<std::pair<GemmPlan, GemmPlan>> chunks;
+  long t_per_vec = 0;
+  double flops1 = 0, flops2 = 0;  // per batch entry
+};
+
+// Cached plan of one renormalization or sigma variant.
+struct ContractionPlan {
+  LinCombPlan form;   // dressed operators
+  TwoStagePlan main;  // T and outputs
+  LinCombPlan post;   // building blocks -> targets
+  long dressed_per_vec = 0, blocks_per_vec = 0;
+  bool dress_left = true;
+};
+
+struct DiagPlan {
+  LinCombPlan form;
+  DBuf jobs, terms;
+  int njobs = 0;
+  long dressed_per_vec = 0;
 };
 
 struct SiteTensors {
@@ -123,41 +139,66 @@ class Ctx {
   dmrg_allocator allocator{};
   std::string err;
   std::unique_ptr<QCHamiltonian> H;
+  long t_budget_per_vec;  // workspace elements per batch entry
 
   // MPS
   bool have_mps = false;
   std::vector<Bond> bonds;
   std::vector<std::vector<std::vector<double>>> lam;  // [bond][sector] host
   std::vector<SiteTensors> site;
+  std::vector<DBuf> lam_dev, laminv_dev;  // per bond, flat over sectors
   const SiteLayout& layout(int i, int width);
   const OpLayout* op_layout(int bond, int dna, int dnb);
+  long bond_offset(int b, int sector) const;  // offset of a sector in the flat bond vector
 
   // zeroth-order operators
   std::vector<OpSet> left, right;  // left[b] = Lop_b, right[b] = Rop_b
   int ops_prec = -1;
 
-  // stats
+  // workspaces
+  DBuf ws_T, ws_dress, ws_blk, ws_aux;
+
   dmrg_stats stats{};
 
   void* dev_alloc(size_t bytes);
   void dev_free(void* p);
   void require_gpu() const;
+  void sync();
 
   void import_mps(const int* nsec, const int* sectors, const double* Ld, const double* Rd, const double* Cd,
                   const double* lam);
   void export_mps(int* nsec_out, int* sectors_out, double* Ld, double* Rd, double* Cd, double* lam_out,
                   size_t* sizes);
+  void upload_lambda();
   void build_ops(int prec);
-  void alloc_opset(OpSet& S, int bond, int side);
-  // zeroth-order renormalization across one site
-  void renorm_left(int i, const double* Abra, const double* Aket, const OpSet& src, OpSet& dst);
-  void renorm_right(int i, const double* Abra, const double* Aket, const OpSet& src, OpSet& dst);
+  void alloc_opset(OpSet& S, int bond, int side, int nvec, bool first_order);
+
+  // Renormalization across site i into dst (left: bond i -> i+1; right:
+  // bond i+1 -> i).  bra tensor Abra (unbatched), ket tensor Aket with batch
+  // stride aket_stride (0 = shared), src / dst operator sets (batched sets
+  // carry their own stride).  accumulate: add into dst instead of
+  // overwriting it.
+  void renorm(int dir, int i, const double* Abra, const double* Aket, long aket_stride, const OpSet& src,
+              OpSet& dst, bool accumulate, int batch);
+  // sigma = H_eff C with the left set X and the right set Z on the dot
+  // (i, width); C has batch stride cstride (0 = shared), outputs have stride
+  // sstride; batch = number of outputs.
+  void sigma_general(int i, int width, const OpSet& X, const OpSet& Z, const double* C, long cstride, double* S,
+                     long sstride, int batch, bool accumulate = false);
   void sigma(int i, int width, int nvec, const double* Cin, double* Sout);
   void diag(int i, int width, double* out);
+  void tda_roots(int nroots, const dmrg_davidson_params& p, double* omega, double* etot, double* resid2,
+                 int* iters, bool* converged);
 
  private:
   std::map<std::pair<int, int>, std::unique_ptr<SiteLayout>> layouts_;
   std::map<std::tuple<int, int, int>, std::unique_ptr<OpLayout>> op_layouts_;
+  std::map<std::tuple<int, int, int, int>, std::unique_ptr<ContractionPlan>> renorm_plans_;
+  std::map<std::tuple<int, int, int, int>, std::unique_ptr<ContractionPlan>> sigma_plans_;
+  std::map<std::pair<int, int>, std::unique_ptr<DiagPlan>> diag_plans_;
+  ContractionPlan& renorm_plan(int dir, int i, const OpSet& src, const OpSet& dst);
+  ContractionPlan& sigma_plan(int i, int width, const OpSet& X, const OpSet& Z);
+  void clear_plans();
 };
 
 }  // namespace dmrg

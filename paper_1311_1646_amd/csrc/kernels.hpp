@@ -1,4 +1,9 @@
 // Device kernel interfaces (implemented in kernels.hip).
+//
+// All work lists address memory as (base id, element offset): a launch
+// receives up to kMaxBases base pointers, each with its own batch stride
+// (0 = shared by all batch entries).  Lists are therefore independent of the
+// buffers they run on and are built once per site and kind, then reused.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -6,77 +11,114 @@
 
 namespace dmrg {
 
-// One GEMM contribution C_tile += alpha * op(A) * op(B).
+constexpr int kMaxBases = 12;
+
+struct Bases {
+  double* p[kMaxBases];
+  long stride[kMaxBases];
+};
+
 enum : int {
   GC_TRANS_A = 1,
   GC_TRANS_B = 2,
   GC_A_IDENTITY = 4,  // op(A) is the identity (A unused)
-  GC_A_BATCHED = 8,   // A advances by the launch's batch stride of A
-  GC_B_BATCHED = 16,
-  GC_B_BATCHED_ALT = 32,  // B advances by the batch stride of A (second batched space)
 };
+
+// One contribution C_tile += alpha * op(A) * op(B).
 struct GContrib {
-  const void* A;
-  const void* B;
+  long offA, offB;
   int lda, ldb, k, flags;
+  int baseA, baseB;
   double alpha;
 };
-enum : int { GJ_ACCUMULATE = 1, GJ_C_BATCHED = 2 };
+
+enum : int { GJ_ACCUMULATE = 1 };
 struct GJob {
-  void* C;
-  int ldc, m, n;
+  long offC;
+  int baseC, ldc, m, n;
   int c0, c1;  // contribution range
-  int flags;
-  int pad;
+  int flags, pad;
 };
 struct GTile {
   int job, tm, tn, pad;
 };
 
 // Grouped, tiled GEMM over a list of output tiles; each output tile sums all
-// contributions of its job in order (deterministic, no atomics).
-// grid.y = batch; batched operands advance by sA/sB/sC elements per batch.
+// contributions of its job in order (deterministic, no atomics).  grid.y =
+// batch entries.
 void launch_grouped_gemm_f64(const GTile* tiles, int ntiles, const GJob* jobs, const GContrib* con,
-                             int batch, long sA, long sB, long sC, hipStream_t s);
+                             const Bases& b, int batch, hipStream_t s);
 
-// Linear combinations out_t = [out_t +] sum_j c_j src_j over `size_t` elements.
+// Linear combinations out = [out +] sum_j c_j src_j.
 struct LCTarget {
-  double* out;
-  long size;
-  int s0, s1;  // source range
-  int accumulate;
-  int pad;
+  long off, size;
+  int base, s0, s1, accumulate;
 };
 struct LCSource {
-  const double* src;
+  long off;
+  int base, pad;
   double c;
 };
-void launch_lincomb_f64(const LCTarget* t, int ntargets, const LCSource* src, long max_size,
-                        int batch, long stride, hipStream_t s);
+void launch_lincomb_f64(const LCTarget* t, int ntargets, const LCSource* src, long max_size, const Bases& b,
+                        int batch, hipStream_t s);
 
-// out[off_k + i*(dim_k+1)] += c for i < dim_k (identity on diagonal blocks)
+// out[off + i*(dim+1)] += c for i < dim (identity added to a diagonal block)
 struct DiagAdd {
-  double* out;
-  int dim;
-  int pad;
+  long off;
+  int base, dim;
   double c;
 };
-void launch_diag_add_f64(const DiagAdd* d, int n, int maxdim, hipStream_t s);
+void launch_diag_add_f64(const DiagAdd* d, int n, const Bases& b, int batch, hipStream_t s);
 
 void launch_fill_f64(double* p, long n, double v, hipStream_t s);
 
 // Diagonal of sum_t alpha_t X_t (x) |n><n| (x) Z_t on one output block:
-// out[l, r] (+)= sum_t alpha_t X_t[l, l] Z_t[r, r]; one workgroup per job.
+// out[l, r] = sum_t alpha_t X_t[l, l] Z_t[r, r]; one workgroup per job.
 struct DiagTerm {
-  const double* X;  // diagonal block of the left operator (rows x rows) or null = identity
-  const double* Z;  // diagonal block of the right operator (cols x cols) or null = identity
+  long offX, offZ;  // -1 = identity
+  int baseX, baseZ;
   double alpha;
 };
 struct DiagJob {
-  double* out;
-  int rows, cols;
-  int t0, t1;
+  long off;
+  int base, rows, cols, t0, t1, pad;
 };
-void launch_diag_jobs_f64(const DiagJob* j, int n, const DiagTerm* t, hipStream_t s);
+void launch_diag_jobs_f64(const DiagJob* j, int n, const DiagTerm* t, const Bases& b, hipStream_t s);
+
+// ---- dense vector kernels on [nvec][n] arrays (FP64)
+
+// G[m*ldg + k] (+)= alpha * sum_e A[m*lda + e] * B[k*ldb + e]  (m < na, k < nb),
+// split over e with a deterministic two-pass reduction; part must hold
+// gram_parts(n) * na * nb doubles.
+int gram_parts(long n);
+void launch_gram_f64(const double* A, long lda, int na, const double* B, long ldb, int nb, long n, double* G,
+                     int ldg, double* part, double alpha, bool accumulate, hipStream_t s);
+
+// y[v][e] = a[v] * x[v][e] + b[v] * y[v][e]  (per-vector scalars in device memory)
+void launch_axpby_f64(const double* a, const double* x, long ldx, const double* b, double* y, long ldy, int nvec,
+                      long n, hipStream_t s);
+
+// z[v][e] = r[v][e] / g(d[e] - w[v]) with g(x) = x if |x| >= eps else +-eps
+void launch_precond_f64(const double* r, const double* d, const double* w, double* z, int nvec, long n,
+                        double eps, hipStream_t s);
+
+// Y[v][e] = sum_u X[u][e] * A[u + v*lda]  (v < nout, u < nin)
+void launch_rotate_f64(const double* X, long ldx, int nin, const double* A, int lda, int nout, double* Y, long ldy,
+                       long n, hipStream_t s);
+
+// scale the rows (by_rows) or columns of one block by entries of a vector
+struct BlockScale {
+  long off, vec_off;
+  int rows, cols, by_rows, pad;
+};
+void launch_block_scale_f64(const BlockScale* bs, int n, const double* vec, double* data, long stride, int batch,
+                            hipStream_t s);
+
+// Symmetric generalized eigenproblem H x = w S x (n <= 64) in one workgroup:
+// canonical orthogonalization of S (eigenvalues <= thr * max dropped), then
+// Jacobi on the projected H.  Ascending w[0..rank), vectors X (column-major,
+// leading dimension n; X^T S X = 1 on the kept columns), rank.
+void launch_gep_f64(const double* H, const double* S, int n, double thr, double* w, double* X, int* rank,
+                    hipStream_t s);
 
 }  // namespace dmrg

@@ -1,0 +1,534 @@
+// DMRG-TDA by the sweep Davidson algorithm (Sec. III of the paper, Fig.
+// alg:dmrgtda), all data device resident in FP64.
+//
+// Trial vectors are first-order MPS changes.  A forward sweep (site 0..L-1)
+// Ritz-rotates the right-gauge objects of the previous iteration (eq.
+// ritzrot2), moves the mixed-canonical centre with eq. gauge_fwd, forms the
+// sigma of eq. sigv1 (zeroth-order part, first-order left part, and the
+// stored first-order right part), the residual (eq. rnorm), the
+// diagonal-preconditioned correction (eq. error) projected by Q^C (eq.
+// param), the projected coefficients of eq. cwfn1st, accumulates H_R and S_R
+// (eqs. hleft2, sleft2) and builds L^(1) (eq. left1st) and the first-order
+// left operators (eq. lopr1st).  The backward sweep brings every trial vector
+// to the right gauge (eq. gauge_bwd, eq. right1st), builds the first-order
+// right operators (eq. ropr1st) and stores, per site, the first-order right
+// part of the sigma contracted with C^(0) (it is linear in the right
+// operators, so it is rotated instead of the operators themselves).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "engine.hpp"
+
+namespace dmrg {
+
+namespace {
+
+template <class T>
+void upload_vec(Ctx& x, DBuf& buf, const std::vector<T>& v) {
+  buf.alloc(&x, std::max<size_t>(v.size(), 1) * sizeof(T));
+  if (!v.empty()) DMRG_HIP(hipMemcpy(buf.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// deterministic normal deviates (splitmix64 + Box-Muller)
+struct HostRng {
+  uint64_t s;
+  explicit HostRng(uint64_t seed) : s(seed * 0x9E3779B97F4A7C15ULL + 12345) {}
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ULL);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+  }
+  double uniform() { return (double(next() >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+  double normal() {
+    const double u = uniform(), v = uniform();
+    return std::sqrt(-2.0 * std::log(u)) * std::cos(6.283185307179586 * v);
+  }
+};
+
+}  // namespace
+
+class TdaRunner {
+ public:
+  TdaRunner(Ctx& x, int nroots, const dmrg_davidson_params& p) : x_(x), n_(nroots), p_(p) {
+    L_ = x.L;
+    Nmax_ = p.max_space > 0 ? p.max_space : std::max(3 * n_, n_ + 8);
+    DMRG_REQUIRE(Nmax_ <= 64, DMRG_ERR_INVALID_ARG, "max_space must be <= 64");
+    DMRG_REQUIRE(n_ >= 1 && 2 * n_ <= Nmax_, DMRG_ERR_INVALID_ARG, "need 1 <= nroots and 2*nroots <= max_space");
+    size_.resize(L_);
+    maxsize_ = 1;
+    for (int i = 0; i < L_; ++i) {
+      size_[i] = long(x.layout(i, 1).size);
+      maxsize_ = std::max(maxsize_, size_[i]);
+    }
+    bm_off_.resize(L_ + 1);
+    bm_size_.assign(L_ + 1, 0);
+    long maxbm = 1;
+    for (int b = 0; b <= L_; ++b) {
+      bm_off_[b].resize(x.bonds[b].q.size());
+      long o = 0;
+      for (size_t s = 0; s < x.bonds[b].q.size(); ++s) {
+        bm_off_[b][s] = o;
+        o += long(x.bonds[b].dim[s]) * x.bonds[b].dim[s];
+      }
+      bm_size_[b] = o;
+      maxbm = std::max(maxbm, o);
+    }
+    // per-site storage
+    R1_.resize(L_);
+    G_.resize(L_);
+    Ct_.resize(L_);
+    diag_.resize(L_);
+    for (int i = 0; i < L_; ++i) {
+      R1_[i].alloc(&x, size_t(Nmax_) * size_[i] * 8);
+      G_[i].alloc(&x, size_t(Nmax_) * size_[i] * 8);
+      Ct_[i].alloc(&x, size_t(Nmax_) * size_[i] * 8);
+      diag_[i].alloc(&x, size_t(size_[i]) * 8);
+    }
+    const size_t vs = size_t(Nmax_) * maxsize_ * 8;
+    for (DBuf* b : {&Cm_, &Cprev_, &Cb_, &Sg_, &S0_, &Dl_, &Wk_, &R1r_, &Gr_}) b->alloc(&x, vs);
+    bm_.alloc(&x, size_t(Nmax_) * maxbm * 8);
+    HR_.alloc(&x, 64 * 64 * 8);
+    SR_.alloc(&x, 64 * 64 * 8);
+    alpha_.alloc(&x, 64 * 64 * 8);
+    w_.alloc(&x, 64 * 8);
+    rank_.alloc(&x, 8);
+    negw_.alloc(&x, 64 * 8);
+    ones_.alloc(&x, 64 * 8);
+    tmpd_.alloc(&x, 64 * 64 * 8);
+    part_.alloc(&x, size_t(gram_parts(maxsize_) + 1) * 64 * 64 * 8);
+    std::vector<double> one(64, 1.0);
+    DMRG_HIP(hipMemcpy(ones_.p, one.data(), 64 * 8, hipMemcpyHostToDevice));
+    for (int k = 0; k < 2; ++k) {
+      FL_[k].bond = -1;
+      FR_[k].bond = -1;
+    }
+    build_site_plans();
+  }
+
+  void run(double* omega, double* etot, double* resid2, int* iters, bool* converged);
+
+ private:
+  Ctx& x_;
+  int n_, L_, Nmax_;
+  dmrg_davidson_params p_;
+  std::vector<long> size_;
+  long maxsize_;
+  std::vector<std::vector<long>> bm_off_;
+  std::vector<long> bm_size_;
+  std::vector<DBuf> R1_, G_, Ct_, diag_;
+  DBuf Cm_, Cprev_, Cb_, Sg_, S0_, Dl_, Wk_, R1r_, Gr_, bm_;
+  DBuf HR_, SR_, alpha_, w_, rank_, negw_, ones_, tmpd_, part_;
+  OpSet FL_[2], FR_[2];
+  double E0_ = 0;
+  std::vector<double> hw_;  // host copy of Ritz values
+
+  // site-level GEMM plans
+  struct SiteOps {
+    GemmPlan lt, rt, lmul_add, lmul_sub, rmul_sub, rmul_add;
+    DBuf scale_rows, scale_cols;  // BlockScale lists
+    int nrows = 0, ncols = 0;
+  };
+  std::vector<SiteOps> sp_;
+
+  void build_site_plans();
+  // bond matrices: out[bond] = A^T B contracted over (l, n) (lt) or over (n, r) (rt)
+  void lt(int i, const double* A, long sa, const double* B, long sb, double* out, int batch);
+  void rt(int i, const double* A, long sa, const double* B, long sb, double* out, int batch);
+  // Out(a,n,c) += M[a] A(a,n,c)  /  -= M[a] A(a,n,c)
+  void lmul_add(int i, const double* M, long sm, const double* A, long sa, double* out, int batch);
+  void lmul_sub(int i, const double* M, long sm, const double* A, long sa, double* out, int batch);
+  // Out(a,n,c) -= A(a,n,c) M[c]  /  += A(a,n,c) M[c]
+  void rmul(int i, bool add, const double* A, long sa, const double* M, long sm, double* out, int batch);
+  void scale(int i, bool rows, bool inverse, double* data, int batch);
+  void copy(double* dst, const double* src, long n) {
+    if (n > 0) DMRG_HIP(hipMemcpyAsync(dst, src, size_t(n) * 8, hipMemcpyDeviceToDevice, x_.stream));
+  }
+  void gram(const double* A, long lda, int na, const double* B, long ldb, int nb, long n, double* G, int ldg,
+            double alpha, bool acc) {
+    launch_gram_f64(A, lda, na, B, ldb, nb, n, G, ldg, part_.as<double>(), alpha, acc, x_.stream);
+    DMRG_HIP(hipGetLastError());
+  }
+  void q_c_project(int i, double* z, int nv);  // z -= C0 (C0 . z)
+  void q_l_project(int i, const double* C, double* out, int nv);  // out = C - L (L^T C)
+  void forward(int m, int lprev, bool init, uint64_t seed, std::vector<double>& r2);
+  void backward(int l);
+};
+
+void TdaRunner::build_site_plans() {
+  sp_.resize(L_);
+  for (int i = 0; i < L_; ++i) {
+    const SiteLayout& S = x_.layout(i, 1);
+    SiteOps& so = sp_[i];
+    // lt: out[c] (bond i+1) = sum_{(a,n)->c} A(a,n,c)^T B(a,n,c)
+    {
+      std::vector<GJob> jobs;
+      std::vector<std::vector<GContrib>> per;
+      std::map<int, int> jo;
+      for (auto& b : S.blk) {
+        auto it = jo.find(b.c);
+        if (it == jo.end()) {
+          GJob j{};
+          j.offC = bm_off_[i + 1][b.c];
+          j.baseC = B_SOUT;
+          j.ldc = b.cols;
+          j.m = b.cols;
+          j.n = b.cols;
+          jobs.push_back(j);
+          per.emplace_back();
+          it = jo.emplace(b.c, int(jobs.size()) - 1).first;
+        }
+        per[it->second].push_back({long(b.off), long(b.off), b.cols, b.cols, b.rows, GC_TRANS_A, B_ABRA, B_AKET, 1.0});
+      }
+      build_gemm_plan(x_, so.lt, jobs, per);
+    }
+    // rt: out[a] (bond i) = sum_{(n,c)} A(a,n,c) B(a,n,c)^T
+    {
+      std::vector<GJob> jobs;
+      std::vector<std::vector<GContrib>> per;
+      std::map<int, int> jo;
+      for (auto& b : S.blk) {
+        auto it = jo.find(b.a);
+        if (it == jo.end()) {
+          GJob j{};
+          j.offC = bm_off_[i][b.a];
+          j.baseC = B_SOUT;
+          j.ldc = b.rows;
+          j.m = b.rows;
+          j.n = b.rows;
+          jobs.push_back(j);
+          per.emplace_back();
+          it = jo.emplace(b.a, int(jobs.size()) - 1).first;
+        }
+        per[it->second].push_back({long(b.off), long(b.off), b.cols, b.cols, b.cols, GC_TRANS_B, B_ABRA, B_AKET, 1.0});
+      }
+      build_gemm_plan(x_, so.rt, jobs, per);
+    }
+    // lmul: Out(a,n,c) +-= M[a] A(a,n,c)
+    for (int add = 0; add < 2; ++add) {
+      std::vector<GJob> jobs;
+      std::vector<std::vector<GContrib>> per;
+      for (auto& b : S.blk) {
+        GJob j{};
+        j.offC = long(b.off);
+        j.baseC = B_SOUT;
+        j.ldc = b.cols;
+        j.m = b.rows;
+        j.n = b.cols;
+        j.flags = GJ_ACCUMULATE;
+        jobs.push_back(j);
+        per.push_back({{bm_off_[i][b.a], long(b.off), b.rows, b.cols, b.rows, 0, B_AUX, B_AKET, add ? 1.0 : -1.0}});
+      }
+      build_gemm_plan(x_, add ? so.lmul_add : so.lmul_sub, jobs, per);
+    }
+    // rmul: Out(a,n,c) +-= A(a,n,c) M[c]
+    for (int add = 0; add < 2; ++add) {
+      std::vector<GJob> jobs;
+      std::vector<std::vector<GContrib>> per;
+      for (auto& b : S.blk) {
+        GJob j{};
+        j.offC = long(b.off);
+        j.baseC = B_SOUT;
+        j.ldc = b.cols;
+        j.m = b.rows;
+        j.n = b.cols;
+        j.flags = GJ_ACCUMULATE;
+        jobs.push_back(j);
+        per.push_back({{long(b.off), bm_off_[i + 1][b.c], b.cols, b.cols, b.cols, 0, B_AKET, B_AUX,
+                        add ? 1.0 : -1.0}});
+      }
+      build_gemm_plan(x_, add ? so.rmul_add : so.rmul_sub, jobs, per);
+    }
+    std::vector<BlockScale> rows, cols;
+    for (auto& b : S.blk) {
+      rows.push_back({long(b.off), x_.bond_offset(i, b.a), b.rows, b.cols, 1, 0});
+      cols.push_back({long(b.off), x_.bond_offset(i + 1, b.c), b.rows, b.cols, 0, 0});
+    }
+    upload_vec(x_, so.scale_rows, rows);
+    upload_vec(x_, so.scale_cols, cols);
+    so.nrows = int(rows.size());
+    so.ncols = int(cols.size());
+  }
+}
+
+}  // namespace dmrg
+
+namespace dmrg {
+
+void TdaRunner::lt(int i, const double* A, long sa, const double* B, long sb, double* out, int batch) {
+  Bases b{};
+  b.p[B_ABRA] = const_cast<double*>(A);
+  b.stride[B_ABRA] = sa;
+  b.p[B_AKET] = const_cast<double*>(B);
+  b.stride[B_AKET] = sb;
+  b.p[B_SOUT] = out;
+  b.stride[B_SOUT] = bm_size_[i + 1];
+  sp_[i].lt.launch(x_, b, batch);
+}
+
+void TdaRunner::rt(int i, const double* A, long sa, const double* B, long sb, double* out, int batch) {
+  Bases b{};
+  b.p[B_ABRA] = const_cast<double*>(A);
+  b.stride[B_ABRA] = sa;
+  b.p[B_AKET] = const_cast<double*>(B);
+  b.stride[B_AKET] = sb;
+  b.p[B_SOUT] = out;
+  b.stride[B_SOUT] = bm_size_[i];
+  sp_[i].rt.launch(x_, b, batch);
+}
+
+void TdaRunner::lmul_add(int i, const double* M, long sm, const double* A, long sa, double* out, int batch) {
+  Bases b{};
+  b.p[B_AUX] = const_cast<double*>(M);
+  b.stride[B_AUX] = sm;
+  b.p[B_AKET] = const_cast<double*>(A);
+  b.stride[B_AKET] = sa;
+  b.p[B_SOUT] = out;
+  b.stride[B_SOUT] = size_[i];
+  sp_[i].lmul_add.launch(x_, b, batch);
+}
+
+void TdaRunner::lmul_sub(int i, const double* M, long sm, const double* A, long sa, double* out, int batch) {
+  Bases b{};
+  b.p[B_AUX] = const_cast<double*>(M);
+  b.stride[B_AUX] = sm;
+  b.p[B_AKET] = const_cast<double*>(A);
+  b.stride[B_AKET] = sa;
+  b.p[B_SOUT] = out;
+  b.stride[B_SOUT] = size_[i];
+  sp_[i].lmul_sub.launch(x_, b, batch);
+}
+
+void TdaRunner::rmul(int i, bool add, const double* A, long sa, const double* M, long sm, double* out, int batch) {
+  Bases b{};
+  b.p[B_AUX] = const_cast<double*>(M);
+  b.stride[B_AUX] = sm;
+  b.p[B_AKET] = const_cast<double*>(A);
+  b.stride[B_AKET] = sa;
+  b.p[B_SOUT] = out;
+  b.stride[B_SOUT] = size_[i];
+  (add ? sp_[i].rmul_add : sp_[i].rmul_sub).launch(x_, b, batch);
+}
+
+void TdaRunner::scale(int i, bool rows, bool inverse, double* data, int batch) {
+  const int bond = rows ? i : i + 1;
+  const DBuf& v = inverse ? x_.laminv_dev[bond] : x_.lam_dev[bond];
+  const SiteOps& so = sp_[i];
+  launch_block_scale_f64(rows ? so.scale_rows.as<BlockScale>() : so.scale_cols.as<BlockScale>(),
+                         rows ? so.nrows : so.ncols, v.as<double>(), data, size_[i], batch, x_.stream);
+  DMRG_HIP(hipGetLastError());
+}
+
+void TdaRunner::q_c_project(int i, double* z, int nv) {
+  const double* C0 = x_.site[i].C.as<double>();
+  gram(z, size_[i], nv, C0, size_[i], 1, size_[i], tmpd_.as<double>(), 1, -1.0, false);
+  launch_axpby_f64(tmpd_.as<double>(), C0, 0, ones_.as<double>(), z, size_[i], nv, size_[i], x_.stream);
+  DMRG_HIP(hipGetLastError());
+}
+
+void TdaRunner::q_l_project(int i, const double* C, double* out, int nv) {
+  const double* Li = x_.site[i].L.as<double>();
+  lt(i, Li, 0, C, size_[i], bm_.as<double>(), nv);
+  if (out != C) copy(out, C, long(nv) * size_[i]);
+  rmul(i, false, Li, 0, bm_.as<double>(), bm_size_[i + 1], out, nv);
+}
+
+void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<double>& r2) {
+  const int l = m + n_;
+  r2.assign(n_, 0.0);
+  launch_fill_f64(HR_.as<double>(), long(l) * l, 0.0, x_.stream);
+  launch_fill_f64(SR_.as<double>(), long(l) * l, 0.0, x_.stream);
+  int cur = 0;
+  x_.alloc_opset(FL_[cur], 0, 0, Nmax_, true);
+  HostRng rng(seed);
+  std::vector<double> tmp;
+  for (int i = 0; i < L_; ++i) {
+    const long S = size_[i];
+    double* Cm = Cm_.as<double>();
+    const double* C0 = x_.site[i].C.as<double>();
+    // Ritz rotation of the right-gauge objects and gauge shift (eq. gauge_fwd)
+    if (m > 0) {
+      launch_rotate_f64(R1_[i].as<double>(), S, lprev, alpha_.as<double>(), lprev, m, R1r_.as<double>(), S, S,
+                        x_.stream);
+      launch_rotate_f64(G_[i].as<double>(), S, lprev, alpha_.as<double>(), lprev, m, Gr_.as<double>(), S, S,
+                        x_.stream);
+      DMRG_HIP(hipGetLastError());
+      copy(Cm, R1r_.as<double>(), long(m) * S);
+      scale(i, true, false, Cm, m);
+      if (i > 0) {
+        lt(i - 1, x_.site[i - 1].L.as<double>(), 0, Cprev_.as<double>(), size_[i - 1], bm_.as<double>(), m);
+        lmul_add(i, bm_.as<double>(), bm_size_[i], x_.site[i].R.as<double>(), 0, Cm, m);
+      }
+    }
+    // first-order left part of the sigma for all l vectors (eq. sigv2, first line)
+    double* Dl = Dl_.as<double>();
+    x_.sigma_general(i, 1, FL_[cur], x_.right[i + 1], C0, 0, Dl, S, l);
+    double* Wk = Wk_.as<double>();
+    if (!init) {
+      // sigma (eq. sigv1), residual (eq. rnorm), correction (eqs. error, param)
+      double* Sg = Sg_.as<double>();
+      x_.sigma_general(i, 1, x_.left[i], x_.right[i + 1], Cm, S, Sg, S, n_);
+      launch_axpby_f64(ones_.as<double>(), Dl, S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
+      launch_axpby_f64(ones_.as<double>(), Gr_.as<double>(), S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
+      launch_axpby_f64(negw_.as<double>(), Cm, S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
+      DMRG_HIP(hipGetLastError());
+      gram(Sg, S, n_, Sg, S, n_, S, tmpd_.as<double>(), n_, 1.0, false);
+      tmp.resize(size_t(n_) * n_);
+      DMRG_HIP(hipMemcpyAsync(tmp.data(), tmpd_.p, tmp.size() * 8, hipMemcpyDeviceToHost, x_.stream));
+      x_.sync();
+      for (int v = 0; v < n_; ++v) r2[v] += tmp[size_t(v) * n_ + v];
+      launch_precond_f64(Sg, diag_[i].as<double>(), w_.as<double>(), Wk, n_, S, 1e-8, x_.stream);
+      DMRG_HIP(hipGetLastError());
+    } else {
+      tmp.resize(size_t(n_) * S);
+      for (auto& v : tmp) v = rng.normal();
+      DMRG_HIP(hipMemcpy(Wk, tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice));
+    }
+    q_c_project(i, Wk, n_);
+    copy(Cm + long(m) * S, Wk, long(n_) * S);
+    // projected coefficients (eq. cwfn1st)
+    double* Ct = Ct_[i].as<double>();
+    q_l_project(i, Cm, Ct, l);
+    // reduced matrices (eqs. hleft2, sleft2)
+    double* S0 = S0_.as<double>();
+    x_.sigma_general(i, 1, x_.left[i], x_.right[i + 1], Ct, S, S0, S, l);
+    gram(Ct, S, l, Ct, S, l, S, SR_.as<double>(), l, 1.0, true);
+    gram(Ct, S, l, S0, S, l, S, HR_.as<double>(), l, 1.0, true);
+    gram(Ct, S, l, Dl, S, l, S, HR_.as<double>(), l, 1.0, true);
+    gram(Dl, S, l, Ct, S, l, S, HR_.as<double>(), l, 1.0, true);
+    if (i == L_ - 1) break;
+    // L^(1) (eq. left1st) and the first-order left operators (eq. lopr1st)
+    copy(Wk, Ct, long(l) * S);
+    scale(i, false, true, Wk, l);
+    const int nxt = 1 - cur;
+    x_.alloc_opset(FL_[nxt], i + 1, 0, Nmax_, true);
+    const double* Li = x_.site[i].L.as<double>();
+    x_.renorm(DMRG_DIR_LEFT, i, Li, Li, 0, FL_[cur], FL_[nxt], false, l);
+    x_.renorm(DMRG_DIR_LEFT, i, Li, Wk, S, x_.left[i], FL_[nxt], true, l);
+    if (m > 0) copy(Cprev_.as<double>(), Cm, long(m) * S);
+    x_.sync();
+    FL_[cur].data.release();
+    cur = nxt;
+  }
+  x_.sync();
+  FL_[0].data.release();
+  FL_[1].data.release();
+}
+
+void TdaRunner::backward(int l) {
+  int cur = 0;
+  x_.alloc_opset(FR_[cur], L_, 1, Nmax_, true);
+  double* Cb = Cb_.as<double>();
+  copy(Cb, Ct_[L_ - 1].as<double>(), long(l) * size_[L_ - 1]);
+  for (int i = L_ - 1; i >= 0; --i) {
+    const long S = size_[i];
+    const double* Ri = x_.site[i].R.as<double>();
+    // R^(1) (eq. right1st): Lambda^-1 C (1 - R^T R)
+    rt(i, Cb, S, Ri, 0, bm_.as<double>(), l);
+    double* R1 = R1_[i].as<double>();
+    copy(R1, Cb, long(l) * S);
+    lmul_sub(i, bm_.as<double>(), bm_size_[i], Ri, 0, R1, l);
+    scale(i, true, true, R1, l);
+    // first-order right part of the sigma contracted with C^(0)
+    x_.sigma_general(i, 1, x_.left[i], FR_[cur], x_.site[i].C.as<double>(), 0, G_[i].as<double>(), S, l);
+    if (i == 0) break;
+    // first-order right operators (eq. ropr1st)
+    const int nxt = 1 - cur;
+    x_.alloc_opset(FR_[nxt], i, 1, Nmax_, true);
+    x_.renorm(DMRG_DIR_RIGHT, i, Ri, Ri, 0, FR_[cur], FR_[nxt], false, l);
+    x_.renorm(DMRG_DIR_RIGHT, i, Ri, R1, S, x_.right[i + 1], FR_[nxt], true, l);
+    // gauge shift to site i-1 (eq. gauge_bwd): C_{i-1} = C~_{i-1} + L_{i-1} (C_i R_i^T)
+    double* Wk = Wk_.as<double>();
+    copy(Wk, Ct_[i - 1].as<double>(), long(l) * size_[i - 1]);
+    rmul(i - 1, true, x_.site[i - 1].L.as<double>(), 0, bm_.as<double>(), bm_size_[i], Wk, l);
+    copy(Cb, Wk, long(l) * size_[i - 1]);
+    x_.sync();
+    FR_[cur].data.release();
+    cur = nxt;
+  }
+  x_.sync();
+  FR_[0].data.release();
+  FR_[1].data.release();
+}
+
+}  // namespace dmrg
+
+namespace dmrg {
+
+void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, bool* converged) {
+  // reference energy E0 = <Psi0|H|Psi0> at site 0
+  {
+    const double* C0 = x_.site[0].C.as<double>();
+    x_.sigma_general(0, 1, x_.left[0], x_.right[1], C0, 0, Wk_.as<double>(), size_[0], 1);
+    gram(C0, size_[0], 1, Wk_.as<double>(), size_[0], 1, size_[0], tmpd_.as<double>(), 1, 1.0, false);
+    DMRG_HIP(hipMemcpy(&E0_, tmpd_.p, 8, hipMemcpyDeviceToHost));
+  }
+  for (int i = 0; i < L_; ++i) x_.diag(i, 1, diag_[i].as<double>());
+  std::vector<double> r2;
+  // initial trial vectors: random Q^C-projected components at every site,
+  // then the right-gauge objects and the first reduced matrices
+  forward(0, 0, true, uint64_t(p_.seed) * 7919 + 1, r2);
+  backward(n_);
+  int lcur = n_, m = n_;
+  bool conv = false;
+  int it = 0;
+  std::vector<double> w(64), last_w(n_, 0.0);
+  double tda_flops0 = 0;
+  (void)tda_flops0;
+  for (it = 1; it <= p_.max_iter; ++it) {
+    auto t0 = std::chrono::steady_clock::now();
+    // small generalized eigenproblem H_R a = w S_R a (eq. eigs)
+    launch_gep_f64(HR_.as<double>(), SR_.as<double>(), lcur, 1e-10, w_.as<double>(), alpha_.as<double>(),
+                   rank_.as<int>(), x_.stream);
+    DMRG_HIP(hipGetLastError());
+    int rank = 0;
+    DMRG_HIP(hipMemcpy(w.data(), w_.p, size_t(lcur) * 8, hipMemcpyDeviceToHost));
+    DMRG_HIP(hipMemcpy(&rank, rank_.p, sizeof(int), hipMemcpyDeviceToHost));
+    DMRG_REQUIRE(rank >= n_, DMRG_ERR_SINGULAR, "trial space lost rank below the number of roots");
+    m = std::min(m, rank);
+    std::vector<double> nw(64, 0.0);
+    for (int v = 0; v < n_; ++v) nw[v] = -w[v];
+    DMRG_HIP(hipMemcpy(negw_.p, nw.data(), 64 * 8, hipMemcpyHostToDevice));
+    for (int v = 0; v < n_; ++v) last_w[v] = w[v];
+    forward(m, lcur, false, 0, r2);
+    const int l = m + n_;
+    backward(l);
+    double mx = 0;
+    for (double v : r2) mx = std::max(mx, v);
+    auto t1 = std::chrono::steady_clock::now();
+    x_.stats.tda_iter_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    x_.stats.tda_iters = it;
+    if (p_.verbose) {
+      std::fprintf(stderr, "[tda] it %d l %d max|r|^2 %.3e  w0 %.10f (%.1f ms)\n", it, l, mx, w[0] - E0_,
+                   x_.stats.tda_iter_ms);
+    }
+    if (mx < p_.tol) {
+      conv = true;
+      break;
+    }
+    lcur = l;
+    m = (l + n_ <= Nmax_) ? l : n_;
+  }
+  for (int v = 0; v < n_; ++v) {
+    etot[v] = last_w[v];
+    omega[v] = last_w[v] - E0_;
+    resid2[v] = r2.empty() ? 0.0 : r2[v];
+  }
+  *iters = std::min(it, p_.max_iter);
+  *converged = conv;
+}
+
+void Ctx::tda_roots(int nroots, const dmrg_davidson_params& p, double* omega, double* etot, double* resid2,
+                    int* iters, bool* converged) {
+  require_gpu();
+  DMRG_REQUIRE(ops_prec >= 0, DMRG_ERR_STATE, "call dmrg_build_ops first");
+  DMRG_REQUIRE(omega && etot && resid2 && iters && converged, DMRG_ERR_INVALID_ARG, "null outputs");
+  DMRG_REQUIRE(p.max_iter >= 1, DMRG_ERR_INVALID_ARG, "max_iter must be >= 1");
+  TdaRunner r(*this, nroots, p);
+  r.run(omega, etot, resid2, iters, converged);
+}
+
+}  // namespace dmrg

@@ -102,3 +102,24 @@ def test_renormalize_call_reproduces_build_ops():
     ctx.renormalize(4, lib.DIR_RIGHT)
     after = ctx.sigma(3, C)
     assert torch.equal(before, after)
+
+
+def test_chunked_workspace_gives_identical_sigma_and_ops(monkeypatch):
+    # a tiny workspace budget splits every contraction into many chunks; the
+    # result must be bit-identical to the unchunked one (same summation order
+    # within each output block is not guaranteed, so compare to 1e-13)
+    import paper_1311_1646_amd as lib
+    L, Na, Nb = 6, 3, 3
+    h, eri, _ = synth.random_integrals(L, seed=12, K=6, diag_lo=-2, diag_hi=0)
+    mps = synth.random_mps(L, Na, Nb, 16, seed=13)
+    outs = []
+    for budget in (None, "300"):
+        if budget:
+            monkeypatch.setenv("DMRG_T_BUDGET_PER_VEC", budget)
+        ctx = lib.Context(L, Na, Nb, h, eri, 0.0, device=0)
+        ctx.import_mps(*mps_arrays(mps))
+        ctx.build_ops()
+        C = torch.tensor(np.random.default_rng(0).normal(size=(3, mps.site_size(2))), device="cuda")
+        outs.append(ctx.sigma(2, C).cpu().numpy())
+        ctx.close()
+    assert np.abs(outs[0] - outs[1]).max() < 1e-13 * np.abs(outs[0]).max()
