@@ -161,7 +161,7 @@ int dmrg_sweep_ground(dmrg_ctx* ctx, const dmrg_sweep_params* p, double* energy,
 
 typedef struct {
   int max_iter;        /* Davidson iterations (one forward+backward sweep each) */
-  int max_space;       /* N: maximum number of trial vectors (0: 3n, >= n+8)     */
+  int max_space;       /* N: maximum number of trial vectors (<= 64; 0: max(3n, n+16)) */
   double tol;          /* convergence: max_mu sum_i |r_i^mu|^2 < tol             */
   int seed;            /* random initial trial vectors                           */
   int prec;            /* contraction precision                                  */

@@ -32,6 +32,11 @@ class DMRGError(RuntimeError):
         self.code = code
 
 
+# torch is imported before the library so that both resolve the HIP runtime
+# (libamdhip64.so.7) to the same loaded copy; two runtimes in one process do
+# not see the same devices.
+import torch  # noqa: E402,F401
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1311_1646_amd.build`")
 

@@ -117,10 +117,11 @@ int dmrg_build_ops(dmrg_ctx* ctx, int prec) {
 
 int dmrg_sigma(dmrg_ctx* ctx, int site, int kind, int nvec, const double* C_in, double* sigma_out, int prec) {
   return guard(ctx, [&](dmrg::Ctx& x) {
-    DMRG_REQUIRE(prec == DMRG_FP64, DMRG_ERR_INVALID_ARG, "unsupported precision");
+    DMRG_REQUIRE(prec == DMRG_FP64 || prec == DMRG_FP32 || prec == DMRG_BF16X3, DMRG_ERR_INVALID_ARG,
+                 "unsupported precision");
     DMRG_REQUIRE(kind == DMRG_SIGMA_ZEROTH_1SITE || kind == DMRG_SIGMA_ZEROTH_2SITE, DMRG_ERR_INVALID_ARG,
                  "TDA sigma kinds are internal to dmrg_tda_roots");
-    x.sigma(site, kind == DMRG_SIGMA_ZEROTH_1SITE ? 1 : 2, nvec, C_in, sigma_out);
+    x.sigma(site, kind == DMRG_SIGMA_ZEROTH_1SITE ? 1 : 2, nvec, C_in, sigma_out, prec);
   });
 }
 

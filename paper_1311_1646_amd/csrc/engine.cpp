@@ -5,6 +5,7 @@
 // block GEMMs addressed relative to base slots, and executed by the kernels
 // in kernels.hip; no arithmetic of the method runs on the host.
 #include "engine.hpp"
+#include "kernels_mfma.hpp"
 
 #include <algorithm>
 #include <cmath>
@@ -58,15 +59,26 @@ void upload(Ctx& x, DBuf& buf, const std::vector<T>& v) {
 }
 }  // namespace
 
-void GemmPlan::launch(Ctx& x, const Bases& b, int batch) const {
+void GemmPlan::launch(Ctx& x, const Bases& b, int batch, int prec, bool out_f64, const Bases* bout) const {
   if (ntiles == 0) return;
-  launch_grouped_gemm_f64(tiles.as<GTile>(), ntiles, jobs.as<GJob>(), con.as<GContrib>(), b, batch, x.stream);
+  if (prec == DMRG_FP64) {
+    launch_grouped_gemm_f64(tiles.as<GTile>(), ntiles, jobs.as<GJob>(), con.as<GContrib>(), b, batch, x.stream);
+    DMRG_HIP(hipGetLastError());
+    return;
+  }
+  launch_grouped_gemm(prec, out_f64, tiles.as<GTile>(), ntiles, jobs.as<GJob>(), con.as<GContrib>(), b,
+                      bout ? *bout : b, batch, x.stream);
   DMRG_HIP(hipGetLastError());
 }
 
-void LinCombPlan::launch(Ctx& x, const Bases& b, int batch) const {
-  if (nt) launch_lincomb_f64(t.as<LCTarget>(), nt, s.as<LCSource>(), max_size, b, batch, x.stream);
-  if (nd) launch_diag_add_f64(d.as<DiagAdd>(), nd, b, batch, x.stream);
+void LinCombPlan::launch(Ctx& x, const Bases& b, int batch, int prec) const {
+  if (prec == 0) {
+    if (nt) launch_lincomb_f64(t.as<LCTarget>(), nt, s.as<LCSource>(), max_size, b, batch, x.stream);
+    if (nd) launch_diag_add_f64(d.as<DiagAdd>(), nd, b, batch, x.stream);
+  } else {
+    if (nt) launch_lincomb_f32(t.as<LCTarget>(), nt, s.as<LCSource>(), max_size, b, batch, x.stream);
+    if (nd) launch_diag_add_f32(d.as<DiagAdd>(), nd, b, batch, x.stream);
+  }
   DMRG_HIP(hipGetLastError());
 }
 
@@ -390,6 +402,7 @@ void Ctx::alloc_opset(OpSet& S, int bond, int side, int nvec, bool first_order) 
   S.bond = bond;
   S.side = side;
   S.nvec = nvec;
+  S.f32_valid = false;
   S.first_order = first_order;
   const uint64_t ident = side == 0 ? chan_key(CH_ID_H, -1, -1) : chan_key(CH_H_ID, -1, -1);
   S.kind.assign(B.ch.size(), REF_OP);
@@ -702,6 +715,7 @@ void Ctx::renorm(int dir, int i, const double* Abra, const double* Aket, long ak
   b.stride[B_BLK] = t_b ? P.blocks_per_vec : 0;
   b.p[B_T] = ws_T.as<double>();
   b.stride[B_T] = t_b ? P.main.t_per_vec : 0;
+  dst.f32_valid = false;
   if (!accumulate) launch_fill_f64(dst.ptr(), long(dst.per_vec) * dst.nvec, 0.0, stream);
   if (P.blocks_per_vec) launch_fill_f64(ws_blk.as<double>(), P.blocks_per_vec * (t_b ? batch : 1), 0.0, stream);
   P.form.launch(*this, b, src_b ? batch : 1);
@@ -920,38 +934,66 @@ ContractionPlan& Ctx::sigma_plan(int i, int width, const OpSet& X, const OpSet& 
   return *(sigma_plans_[key] = std::move(P));
 }
 
+void Ctx::ensure_f32(const OpSet& S) {
+  OpSet& M = const_cast<OpSet&>(S);
+  if (M.f32_valid) return;
+  const long n = long(M.per_vec) * M.nvec;
+  M.data32.ensure(this, std::max<size_t>(size_t(n), 1) * 4);
+  launch_convert_f64_f32(M.ptr(), M.data32.as<float>(), n, stream);
+  DMRG_HIP(hipGetLastError());
+  M.f32_valid = true;
+}
+
 void Ctx::sigma_general(int i, int width, const OpSet& X, const OpSet& Z, const double* C, long cstride, double* Sv,
-                        long sstride, int batch, bool accumulate) {
-  DMRG_REQUIRE(!accumulate, DMRG_ERR_INTERNAL, "accumulating sigma not supported");
+                        long sstride, int batch, int prec) {
   ContractionPlan& P = sigma_plan(i, width, X, Z);
   const bool xb = X.nvec > 1, zb = Z.nvec > 1, cb = cstride != 0;
   const bool dress_b = P.dress_left ? xb : zb;
   const bool t_b = cb || zb;
+  const size_t esz = prec == DMRG_FP64 ? 8 : 4;
   Bases b{};
-  b.p[B_CIN] = const_cast<double*>(C);
   b.stride[B_CIN] = cstride;
   b.p[B_SOUT] = Sv;
   b.stride[B_SOUT] = sstride;
-  b.p[B_LOPS] = X.ptr();
   b.stride[B_LOPS] = xb ? X.per_vec : 0;
-  b.p[B_ROPS] = Z.ptr();
   b.stride[B_ROPS] = zb ? Z.per_vec : 0;
-  ws_dress.ensure(this, std::max<size_t>(size_t(P.dressed_per_vec) * (dress_b ? batch : 1), 1) * 8);
-  ws_T.ensure(this, std::max<size_t>(size_t(P.main.t_per_vec) * (t_b ? batch : 1), 1) * 8);
+  ws_dress.ensure(this, std::max<size_t>(size_t(P.dressed_per_vec) * (dress_b ? batch : 1), 1) * esz);
+  ws_T.ensure(this, std::max<size_t>(size_t(P.main.t_per_vec) * (t_b ? batch : 1), 1) * esz);
   b.p[B_DRESS] = ws_dress.as<double>();
   b.stride[B_DRESS] = dress_b ? P.dressed_per_vec : 0;
   b.p[B_T] = ws_T.as<double>();
   b.stride[B_T] = t_b ? P.main.t_per_vec : 0;
-  P.form.launch(*this, b, dress_b ? batch : 1);
-  for (auto& ch : P.main.chunks) {
-    ch.first.launch(*this, b, t_b ? batch : 1);
-    ch.second.launch(*this, b, batch);
+  if (prec == DMRG_FP64) {
+    b.p[B_CIN] = const_cast<double*>(C);
+    b.p[B_LOPS] = X.ptr();
+    b.p[B_ROPS] = Z.ptr();
+    P.form.launch(*this, b, dress_b ? batch : 1, 0);
+    for (auto& ch : P.main.chunks) {
+      ch.first.launch(*this, b, t_b ? batch : 1, 0);
+      ch.second.launch(*this, b, batch, 0);
+    }
+  } else {
+    ensure_f32(X);
+    ensure_f32(Z);
+    const long cs = layout(i, width).size;
+    const long nc = cb ? cs * batch : cs;
+    ws_c32.ensure(this, std::max<size_t>(size_t(nc), 1) * 4);
+    launch_convert_f64_f32(C, ws_c32.as<float>(), nc, stream);
+    b.p[B_CIN] = reinterpret_cast<double*>(ws_c32.as<float>());
+    b.stride[B_CIN] = cb ? cs : 0;
+    b.p[B_LOPS] = reinterpret_cast<double*>(X.data32.as<float>());
+    b.p[B_ROPS] = reinterpret_cast<double*>(Z.data32.as<float>());
+    P.form.launch(*this, b, dress_b ? batch : 1, prec);
+    for (auto& ch : P.main.chunks) {
+      ch.first.launch(*this, b, t_b ? batch : 1, prec, false, nullptr);
+      ch.second.launch(*this, b, batch, prec, true, &b);
+    }
   }
   stats.sigma_flops = P.main.flops1 * (t_b ? batch : 1) + P.main.flops2 * batch;
   stats.sigma_main_flops = P.main.flops2 * batch;
 }
 
-void Ctx::sigma(int i, int width, int nvec, const double* Cin, double* Sout) {
+void Ctx::sigma(int i, int width, int nvec, const double* Cin, double* Sout, int prec) {
   require_gpu();
   DMRG_REQUIRE(ops_prec >= 0, DMRG_ERR_STATE, "call dmrg_build_ops first");
   DMRG_REQUIRE(nvec >= 1 && Cin && Sout, DMRG_ERR_INVALID_ARG, "bad sigma arguments");
@@ -961,7 +1003,7 @@ void Ctx::sigma(int i, int width, int nvec, const double* Cin, double* Sout) {
   DMRG_HIP(hipEventCreate(&e0));
   DMRG_HIP(hipEventCreate(&e1));
   DMRG_HIP(hipEventRecord(e0, stream));
-  sigma_general(i, width, left[i], right[i + width], Cin, long(S.size), Sout, long(S.size), nvec);
+  sigma_general(i, width, left[i], right[i + width], Cin, long(S.size), Sout, long(S.size), nvec, prec);
   DMRG_HIP(hipEventRecord(e1, stream));
   DMRG_HIP(hipEventSynchronize(e1));
   float ms = 0;

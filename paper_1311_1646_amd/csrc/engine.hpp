@@ -60,6 +60,8 @@ struct OpSet {
   std::vector<const OpLayout*> lay;
   long per_vec = 0;
   DBuf data;
+  DBuf data32;             // FP32 copy for the lower-precision sigma
+  bool f32_valid = false;
   bool valid() const { return bond >= 0; }
   ORef ref(int w, int base) const {
     ORef r;
@@ -78,7 +80,10 @@ struct GemmPlan {
   DBuf tiles, jobs, con;
   int ntiles = 0;
   double flops = 0;  // per batch entry
-  void launch(Ctx& x, const Bases& b, int batch) const;
+  // prec: DMRG_FP64 (FP64 MFMA), DMRG_FP32 or DMRG_BF16X3 (FP32 operands);
+  // outputs go through bout when given (FP64 outputs of a lower-precision run)
+  void launch(Ctx& x, const Bases& b, int batch, int prec = 0, bool out_f64 = true,
+              const Bases* bout = nullptr) const;
 };
 
 void build_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<std::vector<GContrib>>& per);
@@ -87,7 +92,7 @@ struct LinCombPlan {
   DBuf t, s, d;
   int nt = 0, nd = 0;
   long max_size = 0;
-  void launch(Ctx& x, const Bases& b, int batch) const;
+  void launch(Ctx& x, const Bases& b, int batch, int prec = 0) const;
 };
 
 // Host-side builder of a two-stage contraction (stage 1 writes workspace
@@ -156,7 +161,7 @@ class Ctx {
   int ops_prec = -1;
 
   // workspaces
-  DBuf ws_T, ws_dress, ws_blk, ws_aux;
+  DBuf ws_T, ws_dress, ws_blk, ws_aux, ws_c32;
 
   dmrg_stats stats{};
 
@@ -184,8 +189,9 @@ class Ctx {
   // (i, width); C has batch stride cstride (0 = shared), outputs have stride
   // sstride; batch = number of outputs.
   void sigma_general(int i, int width, const OpSet& X, const OpSet& Z, const double* C, long cstride, double* S,
-                     long sstride, int batch, bool accumulate = false);
-  void sigma(int i, int width, int nvec, const double* Cin, double* Sout);
+                     long sstride, int batch, int prec = 0);
+  void sigma(int i, int width, int nvec, const double* Cin, double* Sout, int prec = 0);
+  void ensure_f32(const OpSet& S);
   void diag(int i, int width, double* out);
   void tda_roots(int nroots, const dmrg_davidson_params& p, double* omega, double* etot, double* resid2,
                  int* iters, bool* converged);

@@ -49,13 +49,14 @@ struct HostRng {
   }
 };
 
+
 }  // namespace
 
 class TdaRunner {
  public:
   TdaRunner(Ctx& x, int nroots, const dmrg_davidson_params& p) : x_(x), n_(nroots), p_(p) {
     L_ = x.L;
-    Nmax_ = p.max_space > 0 ? p.max_space : std::max(3 * n_, n_ + 8);
+    Nmax_ = p.max_space > 0 ? p.max_space : std::min(64, std::max(3 * n_, n_ + 16));
     DMRG_REQUIRE(Nmax_ <= 64, DMRG_ERR_INVALID_ARG, "max_space must be <= 64");
     DMRG_REQUIRE(n_ >= 1 && 2 * n_ <= Nmax_, DMRG_ERR_INVALID_ARG, "need 1 <= nroots and 2*nroots <= max_space");
     size_.resize(L_);
@@ -98,6 +99,7 @@ class TdaRunner {
     rank_.alloc(&x, 8);
     negw_.alloc(&x, 64 * 8);
     ones_.alloc(&x, 64 * 8);
+    zscale_.alloc(&x, 64 * 8);
     tmpd_.alloc(&x, 64 * 64 * 8);
     part_.alloc(&x, size_t(gram_parts(maxsize_) + 1) * 64 * 64 * 8);
     std::vector<double> one(64, 1.0);
@@ -121,7 +123,7 @@ class TdaRunner {
   std::vector<long> bm_size_;
   std::vector<DBuf> R1_, G_, Ct_, diag_;
   DBuf Cm_, Cprev_, Cb_, Sg_, S0_, Dl_, Wk_, R1r_, Gr_, bm_;
-  DBuf HR_, SR_, alpha_, w_, rank_, negw_, ones_, tmpd_, part_;
+  DBuf HR_, SR_, alpha_, w_, rank_, negw_, ones_, tmpd_, part_, zscale_;
   OpSet FL_[2], FR_[2];
   double E0_ = 0;
   std::vector<double> hw_;  // host copy of Ritz values
@@ -342,7 +344,7 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
   launch_fill_f64(HR_.as<double>(), long(l) * l, 0.0, x_.stream);
   launch_fill_f64(SR_.as<double>(), long(l) * l, 0.0, x_.stream);
   int cur = 0;
-  x_.alloc_opset(FL_[cur], 0, 0, Nmax_, true);
+  x_.alloc_opset(FL_[cur], 0, 0, l, true);
   HostRng rng(seed);
   std::vector<double> tmp;
   for (int i = 0; i < L_; ++i) {
@@ -375,12 +377,18 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
       launch_axpby_f64(ones_.as<double>(), Gr_.as<double>(), S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
       launch_axpby_f64(negw_.as<double>(), Cm, S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
       DMRG_HIP(hipGetLastError());
+      // residual restricted to the site's tangent directions (orthogonal to
+      // C^(0)); for a stationary reference this projection changes nothing
+      q_c_project(i, Sg, n_);
       gram(Sg, S, n_, Sg, S, n_, S, tmpd_.as<double>(), n_, 1.0, false);
       tmp.resize(size_t(n_) * n_);
       DMRG_HIP(hipMemcpyAsync(tmp.data(), tmpd_.p, tmp.size() * 8, hipMemcpyDeviceToHost, x_.stream));
       x_.sync();
       for (int v = 0; v < n_; ++v) r2[v] += tmp[size_t(v) * n_ + v];
       launch_precond_f64(Sg, diag_[i].as<double>(), w_.as<double>(), Wk, n_, S, 1e-8, x_.stream);
+      // corrections scaled by 1/|r| of the previous iteration so that new
+      // trial vectors keep O(1) norm (S_R stays well conditioned near convergence)
+      launch_axpby_f64(zscale_.as<double>(), Wk, S, nullptr, Wk, S, n_, S, x_.stream);
       DMRG_HIP(hipGetLastError());
     } else {
       tmp.resize(size_t(n_) * S);
@@ -404,7 +412,7 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
     copy(Wk, Ct, long(l) * S);
     scale(i, false, true, Wk, l);
     const int nxt = 1 - cur;
-    x_.alloc_opset(FL_[nxt], i + 1, 0, Nmax_, true);
+    x_.alloc_opset(FL_[nxt], i + 1, 0, l, true);
     const double* Li = x_.site[i].L.as<double>();
     x_.renorm(DMRG_DIR_LEFT, i, Li, Li, 0, FL_[cur], FL_[nxt], false, l);
     x_.renorm(DMRG_DIR_LEFT, i, Li, Wk, S, x_.left[i], FL_[nxt], true, l);
@@ -420,7 +428,7 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
 
 void TdaRunner::backward(int l) {
   int cur = 0;
-  x_.alloc_opset(FR_[cur], L_, 1, Nmax_, true);
+  x_.alloc_opset(FR_[cur], L_, 1, l, true);
   double* Cb = Cb_.as<double>();
   copy(Cb, Ct_[L_ - 1].as<double>(), long(l) * size_[L_ - 1]);
   for (int i = L_ - 1; i >= 0; --i) {
@@ -437,7 +445,7 @@ void TdaRunner::backward(int l) {
     if (i == 0) break;
     // first-order right operators (eq. ropr1st)
     const int nxt = 1 - cur;
-    x_.alloc_opset(FR_[nxt], i, 1, Nmax_, true);
+    x_.alloc_opset(FR_[nxt], i, 1, l, true);
     x_.renorm(DMRG_DIR_RIGHT, i, Ri, Ri, 0, FR_[cur], FR_[nxt], false, l);
     x_.renorm(DMRG_DIR_RIGHT, i, Ri, R1, S, x_.right[i + 1], FR_[nxt], true, l);
     // gauge shift to site i-1 (eq. gauge_bwd): C_{i-1} = C~_{i-1} + L_{i-1} (C_i R_i^T)
@@ -472,6 +480,7 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
   // then the right-gauge objects and the first reduced matrices
   forward(0, 0, true, uint64_t(p_.seed) * 7919 + 1, r2);
   backward(n_);
+  r2.clear();
   int lcur = n_, m = n_;
   bool conv = false;
   int it = 0;
@@ -493,6 +502,9 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
     for (int v = 0; v < n_; ++v) nw[v] = -w[v];
     DMRG_HIP(hipMemcpy(negw_.p, nw.data(), 64 * 8, hipMemcpyHostToDevice));
     for (int v = 0; v < n_; ++v) last_w[v] = w[v];
+    std::vector<double> zs(64, 1.0);
+    for (int v = 0; v < n_; ++v) zs[v] = r2.empty() ? 1.0 : 1.0 / std::sqrt(std::max(r2[v], 1e-300));
+    DMRG_HIP(hipMemcpy(zscale_.p, zs.data(), 64 * 8, hipMemcpyHostToDevice));
     forward(m, lcur, false, 0, r2);
     const int l = m + n_;
     backward(l);
