@@ -22,7 +22,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15}  # dense MI355X peaks
+# dense MI355X peaks; BF16x3 is priced at a third of the BF16 peak (three
+# matrix-core products per algorithmic multiply-add)
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15 / 3}
+PRECS = ("fp64", "fp32", "bf16x3")
+DTYPE = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3-f32acc"}
 HBM_PEAK = 8.0e12
 
 
@@ -69,6 +73,29 @@ def cpu_baseline(nvec):
                       f"in {t_tot:.1f} s; rate = block-sparse algorithmic flops / oracle time"}
 
 
+def time_sigma(ctx, lib, site, C, S, name, steps, warmup):
+    """Warm up, then time `steps` sigmas of all vectors in precision `name`;
+    device times come from the library's events on its stream."""
+    import torch
+    prec = {"fp64": lib.FP64, "fp32": lib.FP32, "bf16x3": lib.BF16X3}[name]
+    for _ in range(warmup):
+        ctx.sigma(site, C, out=S, prec=prec)
+    torch.cuda.synchronize()
+    fl = ms = mms = mfl = 0.0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        ctx.sigma(site, C, out=S, prec=prec)
+        s = ctx.stats()
+        fl += s["sigma_flops"]
+        ms += s["sigma_ms"]
+        mms += s["sigma_main_ms"]
+        mfl += s["sigma_main_flops"]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"gflops": round(fl / (ms * 1e-3) / 1e9, 2), "device_ms": round(ms / steps, 3),
+            "wall_ms": round(wall / steps * 1e3, 3), "main_ms": mms / steps, "main_flops": mfl / steps}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,7 +104,8 @@ def main():
     ap.add_argument("--config", type=int, default=4)
     ap.add_argument("--M", type=int, default=1000)
     ap.add_argument("--nroots", type=int, default=16)
-    ap.add_argument("--prec", default="fp64", choices=["fp64"])
+    ap.add_argument("--prec", default="fp32", choices=list(PRECS))
+    ap.add_argument("--ladder", action="store_true", help="also time the other precisions")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -105,57 +133,40 @@ def main():
         f"ops {st['op_bytes'] / 2**30:.2f} GiB")
     site = p.L // 2
     _, size = ctx.layout(site)
-    C = torch.randn(a.nroots, size, dtype=torch.float64, device="cuda", generator=None)
+    C = torch.randn(a.nroots, size, dtype=torch.float64, device="cuda")
     S = torch.empty_like(C)
-    for w in range(a.warmup):
-        ctx.sigma(site, C, out=S)
-        log(f"[bench] warmup {w} done")
-    torch.cuda.synchronize()
-    fl = ms = mms = 0.0
-    t0 = time.perf_counter()
-    for k in range(a.steps):
-        ctx.sigma(site, C, out=S)
-        s = ctx.stats()
-        fl += s["sigma_flops"]
-        ms += s["sigma_ms"]
-        mms += s["sigma_main_ms"]
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    value = fl / (ms * 1e-3) / 1e9
-    main_flops = None
+    ladder = {}
+    for name in PRECS:
+        if name != a.prec and not a.ladder:
+            continue
+        ladder[name] = time_sigma(ctx, lib, site, C, S, name, a.steps, a.warmup)
+        log(f"[bench] {name}: {ladder[name]}")
+    head = ladder[a.prec]
     out = {
         "metric": "sigma GFLOP/s (TDA sigma, all roots, middle site)",
-        "value": round(value, 2),
+        "value": head["gflops"],
         "unit": "GFLOP/s",
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(wall / a.steps * 1e3, 3),
+        "ms_per_step": head["wall_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": DTYPE[a.prec],
         "data": "synthetic",
         "config": {"workload": f"{p.name} M={p.M} random mixed-canonical MPS, site {site}, "
-                               f"{a.nroots} vectors, zeroth-order sigma",
+                               f"{a.nroots} vectors, zeroth-order sigma, {a.prec} contractions",
                    "L": p.L, "N": p.Na + p.Nb, "M": p.M, "nroots": a.nroots, "site": site,
-                   "sigma_size": size, "sigma_device_ms": round(ms / a.steps, 3)},
-        "roofline": {"bound": "mfma", "achieved": None, "peak": PEAK[a.prec], "unit": "TFLOP/s",
-                     "frac": None, "traffic": None},
+                   "sigma_size": size, "sigma_device_ms": head["device_ms"],
+                   "op_GiB": round(st["op_bytes"] / 2**30, 2),
+                   "precision_ladder": {k: {"GFLOP/s": v["gflops"], "device_ms": v["device_ms"]}
+                                        for k, v in ladder.items()}},
     }
     # dominant kernel: the stage-2 grouped GEMM of the sigma
-    s = ctx.stats()
-    if s["sigma_main_ms"] > 0 and s["sigma_main_flops"] > 0:
-        main_flops = s["sigma_main_flops"]
-        ach = main_flops / (s["sigma_main_ms"] * 1e-3)
-        out["roofline"]["achieved"] = round(ach / 1e12, 3)
-        out["roofline"]["peak"] = PEAK[a.prec] / 1e12
-        out["roofline"]["frac"] = round(ach / PEAK[a.prec], 4)
-    else:
-        ach = fl / (ms * 1e-3)
-        out["roofline"]["achieved"] = round(ach / 1e12, 3)
-        out["roofline"]["peak"] = PEAK[a.prec] / 1e12
-        out["roofline"]["frac"] = round(ach / PEAK[a.prec], 4)
+    ach = head["main_flops"] / (max(head["main_ms"], 1e-9) * 1e-3)
+    out["roofline"] = {"bound": "mfma", "achieved": round(ach / 1e12, 3), "peak": PEAK[a.prec] / 1e12,
+                       "unit": "TFLOP/s", "frac": round(ach / PEAK[a.prec], 4), "traffic": None}
     if not a.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(a.nroots)

@@ -123,6 +123,53 @@ def two_site_basis(mps, dets, i):
     return np.concatenate(cols, axis=1) if cols else np.zeros((len(dets), 0))
 
 
+def _product_blocks(mps, i, width):
+    """(block keys, left states, right states, site shift) of the one- or
+    two-site product basis at site i, in the flat column order."""
+    from synth import two_site_keys  # block order only (data format)
+    left = _left_states(mps, mps.Lt, i)
+    right = _right_states(mps, mps.Rt, i + width)
+    blocks = []
+    if width == 1:
+        for a, n, c in mps.block_keys(i):
+            blocks.append((a, np.int64(n) << (2 * i), c, mps.bonds[i][a][1], mps.bonds[i + 1][c][1]))
+    else:
+        for a, n1, n2, c in two_site_keys(mps, i):
+            nb = (np.int64(n1) << (2 * i)) | (np.int64(n2) << (2 * i + 2))
+            blocks.append((a, nb, c, mps.bonds[i][a][1], mps.bonds[i + 2][c][1]))
+    return blocks, left, right
+
+
+def heff_apply(H, mps, dets, i, C, width=1):
+    """sigma = P^T H P c for each row c of C, without forming P: P c is the
+    FCI vector sum over blocks of |l> c_block <r| (the expansion of the
+    product basis), H acts as a sparse matrix, and P^T v contracts v with
+    the same left and right states block by block."""
+    blocks, left, right = _product_blocks(mps, i, width)
+    C = np.atleast_2d(C)
+    out = np.zeros_like(C, dtype=np.float64)
+    where = []
+    off = 0
+    for a, nb, c, ml, mr in blocks:
+        if a in left and c in right:
+            cl, Ul = left[a]
+            cr, Ur = right[c]
+            cfg = (cl[:, None] | nb | cr[None, :]).ravel()
+            pos = np.searchsorted(dets, cfg)
+            where.append((off, ml, mr, Ul, Ur, pos))
+        off += ml * mr
+    for v in range(C.shape[0]):
+        psi = np.zeros(len(dets))
+        for o, ml, mr, Ul, Ur, pos in where:
+            blk = C[v, o:o + ml * mr].reshape(ml, mr)
+            np.add.at(psi, pos, (Ul @ blk @ Ur.T).ravel())
+        hpsi = H @ psi
+        for o, ml, mr, Ul, Ur, pos in where:
+            V = hpsi[pos].reshape(Ul.shape[0], Ur.shape[0])
+            out[v, o:o + ml * mr] = (Ul.T @ V @ Ur).ravel()
+    return out
+
+
 def heff(H, P):
     """Dense explicit effective Hamiltonian P^T H P."""
     return P.T @ (H @ P)

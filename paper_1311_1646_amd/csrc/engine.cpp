@@ -61,7 +61,7 @@ void upload(Ctx& x, DBuf& buf, const std::vector<T>& v) {
 
 void GemmPlan::launch(Ctx& x, const Bases& b, int batch, int prec, bool out_f64, const Bases* bout) const {
   if (ntiles == 0) return;
-  if (prec == DMRG_FP64) {
+  if (prec == DMRG_FP64 && !x.fp64_mfma) {
     launch_grouped_gemm_f64(tiles.as<GTile>(), ntiles, jobs.as<GJob>(), con.as<GContrib>(), b, batch, x.stream);
     DMRG_HIP(hipGetLastError());
     return;
@@ -219,11 +219,15 @@ Ctx::Ctx(int L_, int na, int nb, const double* h, const double* eri, double ecor
   stream = static_cast<hipStream_t>(s);
   const char* env = std::getenv("DMRG_T_BUDGET_PER_VEC");
   t_budget_per_vec = env ? std::max(1L, std::atol(env)) : (32L << 20);
+  // FP64 contractions: matrix cores (default) or the plain FMA kernel
+  const char* g = std::getenv("DMRG_FP64_GEMM");
+  fp64_mfma = !(g && std::string(g) == "fma");
   if (device >= 0) DMRG_HIP(hipSetDevice(device));
   H.reset(new QCHamiltonian(L, h, eri, ecore));
 }
 
 Ctx::~Ctx() {
+  for (hipEvent_t e : main_events_) (void)hipEventDestroy(e);
   clear_plans();
   left.clear();
   right.clear();
@@ -970,7 +974,9 @@ void Ctx::sigma_general(int i, int width, const OpSet& X, const OpSet& Z, const 
     P.form.launch(*this, b, dress_b ? batch : 1, 0);
     for (auto& ch : P.main.chunks) {
       ch.first.launch(*this, b, t_b ? batch : 1, 0);
+      mark_main(true);
       ch.second.launch(*this, b, batch, 0);
+      mark_main(false);
     }
   } else {
     ensure_f32(X);
@@ -986,7 +992,9 @@ void Ctx::sigma_general(int i, int width, const OpSet& X, const OpSet& Z, const 
     P.form.launch(*this, b, dress_b ? batch : 1, prec);
     for (auto& ch : P.main.chunks) {
       ch.first.launch(*this, b, t_b ? batch : 1, prec, false, nullptr);
+      mark_main(true);
       ch.second.launch(*this, b, batch, prec, true, &b);
+      mark_main(false);
     }
   }
   stats.sigma_flops = P.main.flops1 * (t_b ? batch : 1) + P.main.flops2 * batch;
@@ -1002,8 +1010,16 @@ void Ctx::sigma(int i, int width, int nvec, const double* Cin, double* Sout, int
   hipEvent_t e0, e1;
   DMRG_HIP(hipEventCreate(&e0));
   DMRG_HIP(hipEventCreate(&e1));
+  main_events_used_ = 0;
+  timing_main_ = true;
   DMRG_HIP(hipEventRecord(e0, stream));
-  sigma_general(i, width, left[i], right[i + width], Cin, long(S.size), Sout, long(S.size), nvec, prec);
+  try {
+    sigma_general(i, width, left[i], right[i + width], Cin, long(S.size), Sout, long(S.size), nvec, prec);
+  } catch (...) {
+    timing_main_ = false;
+    throw;
+  }
+  timing_main_ = false;
   DMRG_HIP(hipEventRecord(e1, stream));
   DMRG_HIP(hipEventSynchronize(e1));
   float ms = 0;
@@ -1011,6 +1027,24 @@ void Ctx::sigma(int i, int width, int nvec, const double* Cin, double* Sout, int
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   stats.sigma_ms = ms;
+  double main_ms = 0;
+  for (int k = 0; k + 1 < main_events_used_; k += 2) {
+    float d = 0;
+    DMRG_HIP(hipEventElapsedTime(&d, main_events_[k], main_events_[k + 1]));
+    main_ms += d;
+  }
+  stats.sigma_main_ms = main_ms;
+}
+
+void Ctx::mark_main(bool begin) {
+  if (!timing_main_) return;
+  (void)begin;
+  if (main_events_used_ == int(main_events_.size())) {
+    hipEvent_t e;
+    DMRG_HIP(hipEventCreate(&e));
+    main_events_.push_back(e);
+  }
+  DMRG_HIP(hipEventRecord(main_events_[main_events_used_++], stream));
 }
 
 void Ctx::diag(int i, int width, double* out) {

@@ -145,6 +145,7 @@ class Ctx {
   std::string err;
   std::unique_ptr<QCHamiltonian> H;
   long t_budget_per_vec;  // workspace elements per batch entry
+  bool fp64_mfma = true;   // FP64 grouped GEMM on matrix cores (else FMA kernel)
 
   // MPS
   bool have_mps = false;
@@ -192,6 +193,11 @@ class Ctx {
                      long sstride, int batch, int prec = 0);
   void sigma(int i, int width, int nvec, const double* Cin, double* Sout, int prec = 0);
   void ensure_f32(const OpSet& S);
+  // events bracketing the dominant (stage-2) launches of a timed sigma
+  void mark_main(bool begin);
+  bool timing_main_ = false;
+  std::vector<hipEvent_t> main_events_;
+  int main_events_used_ = 0;
   void diag(int i, int width, double* out);
   void tda_roots(int nroots, const dmrg_davidson_params& p, double* omega, double* etot, double* resid2,
                  int* iters, bool* converged);

@@ -130,3 +130,30 @@ def test_tda_exact_on_exact_ground_state():
     E0, roots = tda.tda_roots(mps, dets, H, 5)
     assert abs(E0 - w[0]) < 1e-11
     np.testing.assert_allclose(roots, w[1:6], atol=1e-10)
+
+
+def test_matrix_free_heff_apply_equals_explicit_heff():
+    # P^T H P c evaluated block by block (no P formed) equals the explicit
+    # product with P from the column construction, one- and two-site; at the
+    # full space the matrix-free map reproduces H's spectrum on its own.
+    h, eri, e0, Na, Nb = _small_problem()
+    mps = synth.random_mps(6, Na, Nb, 12, seed=8)
+    dets, H = fci.hamiltonian(h, eri, e0, Na, Nb)
+    rng = np.random.default_rng(3)
+    for i in range(6):
+        P = mpsvec.site_basis(mps, dets, i)
+        C = rng.normal(size=(2, P.shape[1]))
+        np.testing.assert_allclose(mpsvec.heff_apply(H, mps, dets, i, C), C @ mpsvec.heff(H, P).T, atol=1e-12)
+    for i in range(5):
+        P = mpsvec.two_site_basis(mps, dets, i)
+        C = rng.normal(size=(2, P.shape[1]))
+        np.testing.assert_allclose(mpsvec.heff_apply(H, mps, dets, i, C, width=2), C @ mpsvec.heff(H, P).T,
+                                   atol=1e-12)
+    L, Na, Nb = 4, 2, 2
+    h, eri, e0 = synth.random_integrals(L, seed=22, K=4, diag_lo=-2, diag_hi=0)
+    full = synth.random_mps(L, Na, Nb, 10 ** 6, seed=4)
+    dets, H = fci.hamiltonian(h, eri, e0, Na, Nb)
+    n = full.site_size(1)
+    assert n == len(dets)
+    He = mpsvec.heff_apply(H, full, dets, 1, np.eye(n))
+    np.testing.assert_allclose(np.linalg.eigvalsh(He), np.linalg.eigvalsh(H.toarray()), atol=1e-11)
