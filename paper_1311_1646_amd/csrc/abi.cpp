@@ -79,7 +79,7 @@ const char* dmrg_last_error(const dmrg_ctx* ctx) {
 int dmrg_num_channels(dmrg_ctx* ctx, int bond, int* out) {
   return guard(ctx, [&](dmrg::Ctx& x) {
     DMRG_REQUIRE(bond >= 0 && bond <= x.L && out, DMRG_ERR_INVALID_ARG, "bad bond");
-    *out = int(x.H->channels(bond).ch.size());
+    *out = int(x.H->left_channels(bond).ch.size());
   });
 }
 

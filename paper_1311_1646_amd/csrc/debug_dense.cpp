@@ -56,8 +56,8 @@ int debug_mpo_dense_left(QCHamiltonian& H, int wide_bond, double* out) {
   int b = 0, nsites = 0;
   while (b < L) {
     int width = (b == wide_bond) ? 2 : 1;
-    const SiteOp& W = H.site_op(b, width);
-    const BondChannels& B1 = H.channels(b + width);
+    const SiteOp& W = H.site_op(b, width, H.mode_left(b), H.mode_left(b + width));
+    const BondChannels& B1 = H.left_channels(b + width);
     int d = 1 << (2 * width);
     int n0 = env.empty() ? 1 : env[0].n;
     std::vector<Dense> nxt(B1.ch.size(), Dense(n0 * d));
@@ -82,7 +82,7 @@ int debug_mpo_dense_left(QCHamiltonian& H, int wide_bond, double* out) {
     b += width;
     nsites += width;
   }
-  const BondChannels& BL = H.channels(L);
+  const BondChannels& BL = H.left_channels(L);
   int w = BL.find(chan_key(CH_H_ID, -1, -1));
   const Dense& R = env[w];
   for (size_t k = 0; k < R.a.size(); ++k) out[k] = R.a[k];
@@ -98,9 +98,9 @@ int debug_mpo_dense_right(QCHamiltonian& H, int wide_bond, double* out) {
   while (b > 0) {
     int width = (wide_bond >= 0 && b - 2 == wide_bond) ? 2 : 1;
     int b0 = b - width;
-    const SiteOp& W = H.site_op(b0, width);
-    const BondChannels& B0 = H.channels(b0);
-    const BondChannels& B1 = H.channels(b);
+    const SiteOp& W = H.site_op(b0, width, H.mode_right(b0), H.mode_right(b));
+    const BondChannels& B0 = H.right_channels(b0);
+    const BondChannels& B1 = H.right_channels(b);
     int d = 1 << (2 * width);
     int n0 = env[0].n;
     std::vector<Dense> nxt(B0.ch.size(), Dense(n0 * d));
@@ -125,7 +125,7 @@ int debug_mpo_dense_right(QCHamiltonian& H, int wide_bond, double* out) {
     env.swap(nxt);
     b = b0;
   }
-  const BondChannels& B0 = H.channels(0);
+  const BondChannels& B0 = H.right_channels(0);
   int w = B0.find(chan_key(CH_ID_H, -1, -1));
   const Dense& R = env[w];
   for (size_t k = 0; k < R.a.size(); ++k) out[k] = R.a[k];

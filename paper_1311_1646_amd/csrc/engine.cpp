@@ -66,9 +66,103 @@ void GemmPlan::launch(Ctx& x, const Bases& b, int batch, int prec, bool out_f64,
     DMRG_HIP(hipGetLastError());
     return;
   }
-  launch_grouped_gemm(prec, out_f64, tiles.as<GTile>(), ntiles, jobs.as<GJob>(), con.as<GContrib>(), b,
-                      bout ? *bout : b, batch, x.stream);
+  const Bases& bo = bout ? *bout : b;
+  auto batched = [](const Bases& q, unsigned mask, bool all) {
+    bool any = false, every = true;
+    for (int k = 0; k < kMaxBases; ++k)
+      if (mask >> k & 1u) {
+        any |= q.stride[k] != 0;
+        every &= q.stride[k] != 0;
+      }
+    return all ? (every && mask != 0) : any;
+  };
+  int fold = FOLD_NONE;
+  if (batch > 1 && batched(bo, mask_c, true)) {
+    if (!batched(b, mask_a, false) && batched(b, mask_b, true)) fold = FOLD_N;
+    else if (!batched(b, mask_b, false) && (mask_a == 0 || batched(b, mask_a, true))) fold = FOLD_M;
+  }
+  const FoldTiles& F = fold_lists(x, fold, batch);
+  void* part = nullptr;
+  if (F.nslots > 0) {
+    const size_t esz = prec == DMRG_FP64 ? 8 : 4;
+    x.ws_part.ensure(&x, size_t(F.nslots) * (fold == FOLD_NONE ? batch : 1) * 64 * 64 * esz);
+    part = x.ws_part.p;
+  }
+  launch_grouped_gemm(prec, out_f64, F.tiles.as<GTile>(), F.ntiles, jobs.as<GJob>(), con.as<GContrib>(),
+                      F.segs.as<GSeg>(), F.red.as<GRed>(), F.nred, F.nslots, part, b, bo, fold, batch, x.stream);
   DMRG_HIP(hipGetLastError());
+}
+
+// Tiles of every job for this fold and batch; the contribution list of a
+// job whose work is far above the average share of a workgroup is split into
+// segments (one tile per segment, partial sums reduced afterwards), so that
+// a few long jobs do not leave the rest of the chip idle.
+const GemmPlan::FoldTiles& GemmPlan::fold_lists(Ctx& x, int fold, int batch) const {
+  const auto key = std::make_pair(fold, batch);
+  FoldTiles& F = fold_tiles[key];
+  if (F.ntiles > 0) return F;
+  const long entries = fold == FOLD_NONE ? batch : 1;
+  std::vector<long> tiles_of(shapes.size()), work_of(shapes.size());
+  double total = 0;
+  for (size_t j = 0; j < shapes.size(); ++j) {
+    const long m = fold == FOLD_M ? long(shapes[j].first) * batch : shapes[j].first;
+    const long n = fold == FOLD_N ? long(shapes[j].second) * batch : shapes[j].second;
+    tiles_of[j] = ((m + 63) / 64) * ((n + 63) / 64);
+    long w = 0;
+    for (int c = ranges[j].first; c < ranges[j].second; ++c) w += (con_k[c] + 31) / 32;
+    work_of[j] = w;
+    total += double(tiles_of[j]) * double(w) * double(entries);
+  }
+  // about four workgroups per slot of a full chip (256 CUs x 4 resident)
+  const double target = std::max(8.0, total / 4096.0);
+  std::vector<GTile> tl;
+  std::vector<GSeg> sg;
+  std::vector<GRed> rd;
+  int nslots = 0;
+  for (size_t j = 0; j < shapes.size(); ++j) {
+    const long m = fold == FOLD_M ? long(shapes[j].first) * batch : shapes[j].first;
+    const long n = fold == FOLD_N ? long(shapes[j].second) * batch : shapes[j].second;
+    const int tm = int((m + 63) / 64), tn = int((n + 63) / 64);
+    const int ncon_j = ranges[j].second - ranges[j].first;
+    int nseg = int(std::ceil(double(work_of[j]) / target));
+    nseg = std::max(1, std::min(nseg, ncon_j));
+    std::vector<std::pair<int, int>> cuts;
+    if (nseg > 1) {
+      const double per = double(work_of[j]) / nseg;
+      int c = ranges[j].first;
+      double acc = 0;
+      int start = c;
+      for (; c < ranges[j].second; ++c) {
+        acc += (con_k[c] + 31) / 32;
+        if (acc >= per * double(cuts.size() + 1) && int(cuts.size()) < nseg - 1) {
+          cuts.push_back({start, c + 1});
+          start = c + 1;
+        }
+      }
+      if (start < ranges[j].second) cuts.push_back({start, ranges[j].second});
+      nseg = int(cuts.size());
+    }
+    for (int a = 0; a < tm; ++a)
+      for (int c = 0; c < tn; ++c) {
+        if (nseg <= 1) {
+          tl.push_back({int(j), a, c, -1});
+          continue;
+        }
+        rd.push_back({int(j), a, c, nslots, nseg, 0});
+        for (int q = 0; q < nseg; ++q) {
+          tl.push_back({int(j), a, c, int(sg.size())});
+          sg.push_back({cuts[q].first, cuts[q].second, nslots + q, 0});
+        }
+        nslots += nseg;
+      }
+  }
+  upload(x, F.tiles, tl);
+  upload(x, F.segs, sg);
+  upload(x, F.red, rd);
+  F.ntiles = int(tl.size());
+  F.nred = int(rd.size());
+  F.nslots = nslots;
+  return F;
 }
 
 void LinCombPlan::launch(Ctx& x, const Bases& b, int batch, int prec) const {
@@ -104,6 +198,10 @@ struct LinCombBuilder {
     P.nt = int(t.size());
     P.nd = int(d.size());
     P.max_size = max_size;
+    for (auto& q : t) {
+      P.elems += double(q.size);
+      P.reads += double(q.size) * (q.s1 - q.s0);
+    }
   }
 };
 
@@ -121,6 +219,19 @@ void make_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<st
     const int tm = (jobs[j].m + 63) / 64, tn = (jobs[j].n + 63) / 64;
     for (int a = 0; a < tm; ++a)
       for (int b = 0; b < tn; ++b) tiles.push_back({int(j), a, b, 0});
+    P.shapes.push_back({jobs[j].m, jobs[j].n});
+    P.ranges.push_back({jobs[j].c0, jobs[j].c1});
+    for (int c = jobs[j].c0; c < jobs[j].c1; ++c) P.con_k.push_back(con[c].k);
+    P.mask_c |= 1u << jobs[j].baseC;
+    long kc = 0;
+    for (int c = jobs[j].c0; c < jobs[j].c1; ++c) kc += (con[c].k + 31) / 32;
+    P.ncon += jobs[j].c1 - jobs[j].c0;
+    P.kchunks += kc;
+    P.kchunks_max = std::max(P.kchunks_max, kc);
+    for (int c = jobs[j].c0; c < jobs[j].c1; ++c) {
+      if (!(con[c].flags & GC_A_IDENTITY)) P.mask_a |= 1u << con[c].baseA;
+      P.mask_b |= 1u << con[c].baseB;
+    }
   }
   upload(x, P.tiles, tiles);
   upload(x, P.jobs, jobs);
@@ -205,6 +316,25 @@ void finish_two_stage(Ctx& x, TwoStageBuilder& B, TwoStagePlan& P, bool overwrit
 
 void build_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<std::vector<GContrib>>& per) {
   make_gemm_plan(x, P, jobs, per);
+}
+
+void print_plan_stats(const char* what, int i, int width, const ContractionPlan& P) {
+  long jobs1 = 0, con1 = 0, kc1 = 0, jobs2 = 0, con2 = 0, kc2 = 0, kmax2 = 0;
+  for (auto& ch : P.main.chunks) {
+    jobs1 += long(ch.first.shapes.size());
+    con1 += ch.first.ncon;
+    kc1 += ch.first.kchunks;
+    jobs2 += long(ch.second.shapes.size());
+    con2 += ch.second.ncon;
+    kc2 += ch.second.kchunks;
+    kmax2 = std::max(kmax2, ch.second.kchunks_max);
+  }
+  std::fprintf(stderr,
+               "[plan] %s site %d width %d: form targets %d elems %.3g reads %.3g | chunks %zu | stage1 jobs %ld "
+               "kchunks %ld flops %.3g | stage2 jobs %ld contribs %ld kchunks %ld max/job %ld flops %.3g | post "
+               "targets %d reads %.3g\n",
+               what, i, width, P.form.nt, P.form.elems, P.form.reads, P.main.chunks.size(), jobs1, kc1, P.main.flops1,
+               jobs2, con2, kc2, kmax2, P.main.flops2, P.post.nt, P.post.reads);
 }
 
 // ---------------------------------------------------------------- context
@@ -402,7 +532,7 @@ void Ctx::export_mps(int* nsec_out, int* sectors_out, double* Ld, double* Rd, do
 // ---------------------------------------------------------------- operator sets
 
 void Ctx::alloc_opset(OpSet& S, int bond, int side, int nvec, bool first_order) {
-  const BondChannels& B = H->channels(bond);
+  const BondChannels& B = side == 0 ? H->left_channels(bond) : H->right_channels(bond);
   S.bond = bond;
   S.side = side;
   S.nvec = nvec;
@@ -524,14 +654,15 @@ ContractionPlan& Ctx::renorm_plan(int dir, int i, const OpSet& src, const OpSet&
   if (it != renorm_plans_.end()) return *it->second;
   auto P = std::make_unique<ContractionPlan>();
   const bool leftdir = dir == DMRG_DIR_LEFT;
-  const SiteOp& W = H->site_op(i, 1);
+  const SiteOp& W = leftdir ? H->site_op(i, 1, H->mode_left(i), H->mode_left(i + 1))
+                            : H->site_op(i, 1, H->mode_right(i), H->mode_right(i + 1));
   const SiteLayout& S = layout(i, 1);
   const Bond& bl = bonds[i];
   const Bond& br = bonds[i + 1];
   const int tb = leftdir ? i + 1 : i;  // bond of the targets
   const int db = leftdir ? i : i + 1;  // bond of sources / dressed operators
-  const BondChannels& Bt = H->channels(tb);
-  const BondChannels& Bs = H->channels(db);
+  const BondChannels& Bt = leftdir ? H->left_channels(tb) : H->right_channels(tb);
+  const BondChannels& Bs = leftdir ? H->left_channels(db) : H->right_channels(db);
   const int skip = leftdir ? Bt.find(chan_key(CH_ID_H, -1, -1)) : Bt.find(chan_key(CH_H_ID, -1, -1));
   std::vector<Group> G = group_entries(W, leftdir, skip);
   for (auto& g : G) {
@@ -694,6 +825,7 @@ ContractionPlan& Ctx::renorm_plan(int dir, int i, const OpSet& src, const OpSet&
     for (auto& s : kv.second) post.source(s.first.base, s.first.off, s.second);
   }
   post.finish(*this, P->post);
+  if (std::getenv("DMRG_PLAN_STATS")) print_plan_stats(dir == 0 ? "renorm-L" : "renorm-R", i, 1, *P);
   return *(renorm_plans_[key] = std::move(P));
 }
 
@@ -783,9 +915,9 @@ struct STerm {
 // side that needs fewer formed operators.
 std::vector<STerm> sigma_terms(Ctx& x, int i, int width, const OpSet& X, const OpSet& Z, Pool& pool,
                                LinCombBuilder& form, bool& left_dressed) {
-  const SiteOp& W = x.H->site_op(i, width);
-  const BondChannels& B0 = x.H->channels(i);
-  const BondChannels& B1 = x.H->channels(i + width);
+  const SiteOp& W = x.H->site_op(i, width, x.H->mode_left(i), x.H->mode_right(i + width));
+  const BondChannels& B0 = x.H->left_channels(i);
+  const BondChannels& B1 = x.H->right_channels(i + width);
   std::vector<Group> GL = group_entries(W, true, -1), GR = group_entries(W, false, -1);
   auto prune = [&](std::vector<Group>& G, bool by_dst) {
     std::vector<Group> out;
@@ -935,6 +1067,7 @@ ContractionPlan& Ctx::sigma_plan(int i, int width, const OpSet& X, const OpSet& 
     }
   }
   finish_two_stage(*this, TB, P->main, true);
+  if (std::getenv("DMRG_PLAN_STATS")) print_plan_stats("sigma", i, width, *P);
   return *(sigma_plans_[key] = std::move(P));
 }
 

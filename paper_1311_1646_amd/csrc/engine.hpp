@@ -80,6 +80,21 @@ struct GemmPlan {
   DBuf tiles, jobs, con;
   int ntiles = 0;
   double flops = 0;  // per batch entry
+  // host copies for batch folding: job shapes and the bases each operand
+  // role reads or writes (bit per base slot)
+  std::vector<std::pair<int, int>> shapes;
+  std::vector<std::pair<int, int>> ranges;  // contribution range per job
+  std::vector<int> con_k;                   // inner length per contribution
+  unsigned mask_a = 0, mask_b = 0, mask_c = 0;
+  long ncon = 0, kchunks = 0, kchunks_max = 0;  // plan statistics (K-chunks of 32)
+  // launch lists per (fold, batch): tiles with split contribution lists and
+  // the reductions of their partial sums
+  struct FoldTiles {
+    DBuf tiles, segs, red;
+    int ntiles = 0, nred = 0, nslots = 0;
+  };
+  mutable std::map<std::pair<int, int>, FoldTiles> fold_tiles;
+  const FoldTiles& fold_lists(Ctx& x, int fold, int batch) const;
   // prec: DMRG_FP64 (FP64 MFMA), DMRG_FP32 or DMRG_BF16X3 (FP32 operands);
   // outputs go through bout when given (FP64 outputs of a lower-precision run)
   void launch(Ctx& x, const Bases& b, int batch, int prec = 0, bool out_f64 = true,
@@ -92,6 +107,7 @@ struct LinCombPlan {
   DBuf t, s, d;
   int nt = 0, nd = 0;
   long max_size = 0;
+  double elems = 0, reads = 0;  // plan statistics: target elements, source element reads
   void launch(Ctx& x, const Bases& b, int batch, int prec = 0) const;
 };
 
@@ -162,7 +178,7 @@ class Ctx {
   int ops_prec = -1;
 
   // workspaces
-  DBuf ws_T, ws_dress, ws_blk, ws_aux, ws_c32;
+  DBuf ws_T, ws_dress, ws_blk, ws_aux, ws_c32, ws_part;
 
   dmrg_stats stats{};
 

@@ -1,17 +1,30 @@
 // Grouped block GEMM on the CDNA4 matrix cores (gfx950).
 //
-// Same work lists as the FP64 FMA kernel (tiles / jobs / contributions with
+// Work lists are those of the FMA kernel (tiles / jobs / contributions with
 // base-relative addressing).  A workgroup of four waves owns one 64x64 output
-// tile; each wave owns a 32x32 quarter.  Every contribution of the job is
-// streamed through LDS in K-chunks of 16 with the op() transposition applied
-// while staging, zero-filled outside the block (ragged edges).
-//   FP64 : v_mfma_f64_16x16x4f64, 2x2 per wave, FP64 accumulate
-//          (16x16 result: lane l, register r holds row (l/16) + 4r, column l%16).
-//   FP32 : v_mfma_f32_32x32x2f32, FP32 accumulate (32x32 result: lane l,
-//          register r holds row 8(r/4) + 4(l/32) + r%4, column l%32).
-//   BF16X3 : each FP32 operand split x = hi + lo (bfloat16), three
-//            v_mfma_f32_32x32x16_bf16 products hi*hi + hi*lo + lo*hi, FP32
-//            accumulate (about 2^-16 relative per product).
+// tile, each wave a 32x32 quarter, and streams every contribution of its job
+// through LDS in K-chunks.  The chunks of all contributions form one sequence;
+// chunk q+1 is fetched from global memory into registers while chunk q is
+// multiplied out of LDS, and LDS is double-buffered, so there is a single
+// barrier per chunk.  op() transposition, the contribution's alpha and zero
+// fill outside the block (ragged edges) are applied while staging.
+//
+// Batch folding: when one operand is shared by all batch entries and the
+// other operand and the output are batched, the batch is folded into the
+// free dimension of the batched operand (fold N: columns (v, j) of
+// [B_0 | B_1 | ...]; fold M: rows (v, i) of [A_0; A_1; ...]).  The shared
+// operand is then staged once per tile instead of once per batch entry and
+// the tiles of a narrow block are filled across entries.  Otherwise grid.y
+// enumerates the batch entries.
+//
+//   FP64   : v_mfma_f64_16x16x4f64, 2x2 per wave, FP64 accumulate
+//            (16x16 result: lane l, register r holds row l/16 + 4r, column l%16).
+//   FP32   : v_mfma_f32_32x32x2f32, FP32 accumulate (32x32 result: lane l,
+//            register r holds row 8(r/4) + 4(l/32) + r%4, column l%32).
+//   BF16X3 : each FP32 operand split once, at the LDS store, into
+//            x = hi + lo (bfloat16); three v_mfma_f32_32x32x16_bf16 products
+//            hi*hi + hi*lo + lo*hi with FP32 accumulate (about 2^-16 relative
+//            per product).
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -25,187 +38,364 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int TM = 64, TN = 64, TK = 16, NTH = 256;
+constexpr int TM = 64, TN = 64, NTH = 256;
 
-template <class T>
-__device__ __forceinline__ const T* cptr(const Bases& b, int base, long off, int bz) {
-  return reinterpret_cast<const T*>(b.p[base]) + off + long(bz) * b.stride[base];
-}
-template <class T>
-__device__ __forceinline__ T* mptr(const Bases& b, int base, long off, int bz) {
-  return reinterpret_cast<T*>(b.p[base]) + off + long(bz) * b.stride[base];
-}
+template <int MODE> struct Cfg;
+template <> struct Cfg<0> {  // FP64
+  typedef double T;
+  static constexpr int TK = 16;
+};
+template <> struct Cfg<1> {  // FP32
+  typedef float T;
+  static constexpr int TK = 32;
+};
+template <> struct Cfg<2> {  // BF16x3
+  typedef float T;
+  static constexpr int TK = 32;
+};
 
-// Stage op(A) (TM x TK) and op(B) (TK x TN) of one K-chunk into LDS, both
-// stored row-per-output-index: As[i][k], Bs[j][k].
-template <class T>
-__device__ __forceinline__ void stage(T (*As)[TK + 1], T (*Bs)[TK + 1], const GContrib& c, const T* A,
-                                      const T* B, int m, int n, int row0, int col0, int k0, int tid) {
-  const bool ta = c.flags & GC_TRANS_A, tb = c.flags & GC_TRANS_B, aid = c.flags & GC_A_IDENTITY;
-  const T alpha = T(c.alpha);
+// LDS images of one chunk.  FP64/FP32: a[i][k], b[j][k] (row per output
+// index, padded by one element).  BF16x3: hi and lo parts, rows padded to a
+// multiple of 16 bytes so that eight consecutive k load as one 128-bit read.
+template <int MODE> struct Lds {
+  typedef typename Cfg<MODE>::T T;
+  static constexpr int TK = Cfg<MODE>::TK;
+  T a[2][TM][TK + 1];
+  T b[2][TN][TK + 1];
+};
+template <> struct Lds<2> {
+  static constexpr int TK = 32, LD = TK + 8;
+  alignas(16) __bf16 ah[2][TM][LD];
+  alignas(16) __bf16 al[2][TM][LD];
+  alignas(16) __bf16 bh[2][TN][LD];
+  alignas(16) __bf16 bl[2][TN][LD];
+};
+
+struct TileMap {
+  int v[TM];    // batch entry of each tile row (fold M) or column (fold N)
+  int idx[TM];  // row / column index inside the block, -1 outside
+};
+
+template <int MODE>
+struct Stage {
+  typedef typename Cfg<MODE>::T T;
+  static constexpr int TK = Cfg<MODE>::TK;
+  static constexpr int PER = TM * TK / NTH;  // elements per thread and operand
+  T ra[PER], rb[PER];
+
+  // Fetch op(A) rows x K-chunk and K-chunk x op(B) columns of contribution c.
+  __device__ __forceinline__ void load(const GContrib& c, const Bases& bs, const TileMap& rm, const TileMap& cm,
+                                       int k0, int tid) {
+    const bool ta = c.flags & GC_TRANS_A, tb = c.flags & GC_TRANS_B, aid = c.flags & GC_A_IDENTITY;
+    const T alpha = T(c.alpha);
+    const T* A = aid ? nullptr : reinterpret_cast<const T*>(bs.p[c.baseA]) + c.offA;
+    const T* B = reinterpret_cast<const T*>(bs.p[c.baseB]) + c.offB;
+    const long sa = aid ? 0 : bs.stride[c.baseA], sb = bs.stride[c.baseB];
 #pragma unroll
-  for (int q = 0; q < (TM * TK) / NTH; ++q) {
-    const int e = tid + q * NTH;
-    int i, k;
-    if (ta) { k = e / TM; i = e % TM; } else { i = e / TK; k = e % TK; }
-    const int gi = row0 + i, gk = k0 + k;
-    T v = T(0);
-    if (gi < m && gk < c.k) {
-      if (aid) v = gi == gk ? T(1) : T(0);
-      else v = ta ? A[long(gk) * c.lda + gi] : A[long(gi) * c.lda + gk];
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * NTH;
+      int i, k;
+      if (ta) { k = e / TM; i = e % TM; } else { i = e / TK; k = e % TK; }
+      const int ii = rm.idx[i], gk = k0 + k;
+      T val = T(0);
+      if (ii >= 0 && gk < c.k) {
+        if (aid) {
+          val = ii == gk ? alpha : T(0);
+        } else {
+          const T* Av = A + long(rm.v[i]) * sa;
+          val = (ta ? Av[long(gk) * c.lda + ii] : Av[long(ii) * c.lda + gk]) * alpha;
+        }
+      }
+      ra[q] = val;
     }
-    As[i][k] = v * alpha;
-  }
 #pragma unroll
-  for (int q = 0; q < (TN * TK) / NTH; ++q) {
-    const int e = tid + q * NTH;
-    int j, k;
-    if (tb) { j = e / TK; k = e % TK; } else { k = e / TN; j = e % TN; }
-    const int gj = col0 + j, gk = k0 + k;
-    T v = T(0);
-    if (gk < c.k && gj < n) v = tb ? B[long(gj) * c.ldb + gk] : B[long(gk) * c.ldb + gj];
-    Bs[j][k] = v;
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * NTH;
+      int j, k;
+      if (tb) { j = e / TK; k = e % TK; } else { k = e / TN; j = e % TN; }
+      const int jj = cm.idx[j], gk = k0 + k;
+      T val = T(0);
+      if (jj >= 0 && gk < c.k) {
+        const T* Bv = B + long(cm.v[j]) * sb;
+        val = tb ? Bv[long(jj) * c.ldb + gk] : Bv[long(gk) * c.ldb + jj];
+      }
+      rb[q] = val;
+    }
+  }
+
+  __device__ __forceinline__ void store(Lds<MODE>& s, int buf, bool ta, bool tb, int tid) const {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * NTH;
+      int i, k;
+      if (ta) { k = e / TM; i = e % TM; } else { i = e / TK; k = e % TK; }
+      put_a(s, buf, i, k, ra[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * NTH;
+      int j, k;
+      if (tb) { j = e / TK; k = e % TK; } else { k = e / TN; j = e % TN; }
+      put_b(s, buf, j, k, rb[q]);
+    }
+  }
+
+  __device__ __forceinline__ static void put_a(Lds<MODE>& s, int buf, int i, int k, T v) {
+    if constexpr (MODE == 2) {
+      const __bf16 h = static_cast<__bf16>(v);
+      s.ah[buf][i][k] = h;
+      s.al[buf][i][k] = static_cast<__bf16>(v - static_cast<float>(h));
+    } else {
+      s.a[buf][i][k] = v;
+    }
+  }
+  __device__ __forceinline__ static void put_b(Lds<MODE>& s, int buf, int j, int k, T v) {
+    if constexpr (MODE == 2) {
+      const __bf16 h = static_cast<__bf16>(v);
+      s.bh[buf][j][k] = h;
+      s.bl[buf][j][k] = static_cast<__bf16>(v - static_cast<float>(h));
+    } else {
+      s.b[buf][j][k] = v;
+    }
+  }
+};
+
+template <int MODE> struct Acc;
+template <> struct Acc<0> {
+  doublex4 c[2][2];
+  __device__ void zero() {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) c[a][b] = doublex4{0, 0, 0, 0};
+  }
+};
+template <> struct Acc<1> {
+  floatx16 c;
+  __device__ void zero() { c = floatx16{0}; }
+};
+template <> struct Acc<2> {
+  floatx16 c;
+  __device__ void zero() { c = floatx16{0}; }
+};
+
+// Multiply the first kv (<= TK) K-entries of LDS buffer buf into the wave's
+// accumulator; (wm, wn) is the wave's 32x32 quarter.
+__device__ __forceinline__ void mma(Acc<0>& acc, const Lds<0>& s, int buf, int kv, int wm, int wn, int lane) {
+#pragma unroll
+  for (int st = 0; st < Cfg<0>::TK / 4; ++st) {
+    if (4 * st >= kv) break;
+    const int k = 4 * st + (lane >> 4);
+    double av[2], bv[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) av[a] = s.a[buf][wm + 16 * a + (lane & 15)][k];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) bv[b] = s.b[buf][wn + 16 * b + (lane & 15)][k];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        acc.c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc.c[a][b], 0, 0, 0);
   }
 }
 
-__device__ __forceinline__ void split_bf16(const float* x, bf16x8& hi, bf16x8& lo) {
+__device__ __forceinline__ void mma(Acc<1>& acc, const Lds<1>& s, int buf, int kv, int wm, int wn, int lane) {
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
-    const __bf16 h = static_cast<__bf16>(x[t]);
-    hi[t] = h;
-    lo[t] = static_cast<__bf16>(x[t] - static_cast<float>(h));
+  for (int st = 0; st < Cfg<1>::TK / 2; ++st) {
+    if (2 * st >= kv) break;
+    const int k = 2 * st + (lane >> 5);
+    acc.c = __builtin_amdgcn_mfma_f32_32x32x2f32(s.a[buf][wm + (lane & 31)][k], s.b[buf][wn + (lane & 31)][k], acc.c,
+                                                 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void mma(Acc<2>& acc, const Lds<2>& s, int buf, int kv, int wm, int wn, int lane) {
+#pragma unroll
+  for (int st = 0; st < Lds<2>::TK / 16; ++st) {
+    if (16 * st >= kv) break;
+    const int k = 16 * st + 8 * (lane >> 5);
+    const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&s.ah[buf][wm + (lane & 31)][k]);
+    const bf16x8 al = *reinterpret_cast<const bf16x8*>(&s.al[buf][wm + (lane & 31)][k]);
+    const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&s.bh[buf][wn + (lane & 31)][k]);
+    const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&s.bl[buf][wn + (lane & 31)][k]);
+    acc.c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc.c, 0, 0, 0);
+    acc.c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc.c, 0, 0, 0);
+    acc.c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc.c, 0, 0, 0);
   }
 }
 
 template <class TOut>
-__device__ __forceinline__ void store_out(TOut* C, const GJob& J, int r, int c, float v) {
-  if (r < J.m && c < J.n) {
-    TOut* p = C + long(r) * J.ldc + c;
-    *p = (J.flags & GJ_ACCUMULATE) ? TOut(*p + TOut(v)) : TOut(v);
-  }
+__device__ __forceinline__ void put_out(const Bases& bo, const GJob& J, const TileMap& rm, const TileMap& cm, int fold,
+                                        int i, int j, double v) {
+  const int ii = rm.idx[i], jj = cm.idx[j];
+  if (ii < 0 || jj < 0) return;
+  const int vb = fold == 2 ? rm.v[i] : cm.v[j];
+  TOut* p = reinterpret_cast<TOut*>(bo.p[J.baseC]) + J.offC + long(vb) * bo.stride[J.baseC] + long(ii) * J.ldc + jj;
+  *p = (J.flags & GJ_ACCUMULATE) ? TOut(*p + TOut(v)) : TOut(v);
 }
 
-// MODE 1: FP32 MFMA, MODE 2: BF16x3 MFMA (FP32 data in memory)
-template <int MODE, class TOut>
-__global__ __launch_bounds__(NTH) void ggemm_f32_kernel(const GTile* __restrict__ tiles, const GJob* __restrict__ jobs,
-                                                        const GContrib* __restrict__ con, Bases bs, Bases bout) {
-  __shared__ float As[TM][TK + 1];
-  __shared__ float Bs[TN][TK + 1];
-  const GTile t = tiles[blockIdx.x];
-  const GJob J = jobs[t.job];
-  const int bz = blockIdx.y;
-  const int row0 = t.tm * TM, col0 = t.tn * TN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  floatx16 acc = {0};
-  for (int ci = J.c0; ci < J.c1; ++ci) {
-    const GContrib c = con[ci];
-    const float* A = (c.flags & GC_A_IDENTITY) ? nullptr : cptr<float>(bs, c.baseA, c.offA, bz);
-    const float* B = cptr<float>(bs, c.baseB, c.offB, bz);
-    for (int k0 = 0; k0 < c.k; k0 += TK) {
-      stage<float>(As, Bs, c, A, B, J.m, J.n, row0, col0, k0, tid);
-      __syncthreads();
-      if (MODE == 1) {
-#pragma unroll
-        for (int s = 0; s < TK / 2; ++s) {
-          const int k = 2 * s + (lane >> 5);
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(As[wm + (lane & 31)][k], Bs[wn + (lane & 31)][k], acc, 0, 0, 0);
-        }
-      } else {
-        float av[8], bv[8];
-        const int kb = 8 * (lane >> 5);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          av[q] = As[wm + (lane & 31)][kb + q];
-          bv[q] = Bs[wn + (lane & 31)][kb + q];
-        }
-        bf16x8 ah, al, bh, bl;
-        split_bf16(av, ah, al);
-        split_bf16(bv, bh, bl);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
-      }
-      __syncthreads();
-    }
-  }
-  TOut* C = mptr<TOut>(bout, J.baseC, J.offC, bz);
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-    store_out<TOut>(C, J, row0 + wm + i, col0 + wn + (lane & 31), acc[r]);
-  }
-}
-
-__global__ __launch_bounds__(NTH) void ggemm_f64_mfma_kernel(const GTile* __restrict__ tiles,
-                                                             const GJob* __restrict__ jobs,
-                                                             const GContrib* __restrict__ con, Bases bs) {
-  __shared__ double As[TM][TK + 1];
-  __shared__ double Bs[TN][TK + 1];
-  const GTile t = tiles[blockIdx.x];
-  const GJob J = jobs[t.job];
-  const int bz = blockIdx.y;
-  const int row0 = t.tm * TM, col0 = t.tn * TN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  doublex4 acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = doublex4{0, 0, 0, 0};
-  for (int ci = J.c0; ci < J.c1; ++ci) {
-    const GContrib c = con[ci];
-    const double* A = (c.flags & GC_A_IDENTITY) ? nullptr : cptr<double>(bs, c.baseA, c.offA, bz);
-    const double* B = cptr<double>(bs, c.baseB, c.offB, bz);
-    for (int k0 = 0; k0 < c.k; k0 += TK) {
-      stage<double>(As, Bs, c, A, B, J.m, J.n, row0, col0, k0, tid);
-      __syncthreads();
-#pragma unroll
-      for (int s = 0; s < TK / 4; ++s) {
-        const int k = 4 * s + (lane >> 4);
-        double av[2], bv[2];
-#pragma unroll
-        for (int a = 0; a < 2; ++a) av[a] = As[wm + 16 * a + (lane & 15)][k];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) bv[b] = Bs[wn + 16 * b + (lane & 15)][k];
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
-      }
-      __syncthreads();
-    }
-  }
-  double* C = mptr<double>(bs, J.baseC, J.offC, bz);
+__device__ __forceinline__ void write(const Acc<0>& acc, const Bases& bo, const GJob& J, const TileMap& rm,
+                                      const TileMap& cm, int fold, int wm, int wn, int lane, bool) {
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = row0 + wm + 16 * a + (lane >> 4) + 4 * r;
-        const int j = col0 + wn + 16 * b + (lane & 15);
-        if (i < J.m && j < J.n) {
-          double* p = C + long(i) * J.ldc + j;
-          *p = (J.flags & GJ_ACCUMULATE) ? *p + acc[a][b][r] : acc[a][b][r];
-        }
+      for (int r = 0; r < 4; ++r)
+        put_out<double>(bo, J, rm, cm, fold, wm + 16 * a + (lane >> 4) + 4 * r, wn + 16 * b + (lane & 15),
+                        acc.c[a][b][r]);
+}
+
+template <int MODE>
+__device__ __forceinline__ void write(const Acc<MODE>& acc, const Bases& bo, const GJob& J, const TileMap& rm,
+                                      const TileMap& cm, int fold, int wm, int wn, int lane, bool out_f64) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int i = wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), j = wn + (lane & 31);
+    if (out_f64) put_out<double>(bo, J, rm, cm, fold, i, j, acc.c[r]);
+    else put_out<float>(bo, J, rm, cm, fold, i, j, acc.c[r]);
+  }
+}
+
+// Row and column maps of tile (tm, tn) of job J (threads 0..127 fill them;
+// the caller synchronizes).  fold: 0 = grid.y enumerates batch entries,
+// 1 = batch folded into N, 2 = batch folded into M.
+__device__ __forceinline__ void tile_maps(TileMap& rm, TileMap& cm, const GJob& J, int tm, int tn, int fold,
+                                          int batch, int tid) {
+  if (tid < TM) {
+    const int g = tm * TM + tid;
+    const int mb = fold == 2 ? J.m * batch : J.m;
+    rm.v[tid] = fold == 2 ? g / J.m : (fold == 0 ? int(blockIdx.y) : 0);
+    rm.idx[tid] = g < mb ? (fold == 2 ? g % J.m : g) : -1;
+  } else if (tid < TM + TN) {
+    const int u = tid - TM, g = tn * TN + u;
+    const int nb = fold == 1 ? J.n * batch : J.n;
+    cm.v[u] = fold == 1 ? g / J.n : (fold == 0 ? int(blockIdx.y) : 0);
+    cm.idx[u] = g < nb ? (fold == 1 ? g % J.n : g) : -1;
+  }
+}
+
+template <class PT>
+__device__ __forceinline__ void write_partial(const Acc<0>& acc, PT* P, int wm, int wn, int lane) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        P[(wm + 16 * a + (lane >> 4) + 4 * r) * TN + wn + 16 * b + (lane & 15)] = PT(acc.c[a][b][r]);
+}
+template <int MODE, class PT>
+__device__ __forceinline__ void write_partial(const Acc<MODE>& acc, PT* P, int wm, int wn, int lane) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    P[(wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * TN + wn + (lane & 31)] = PT(acc.c[r]);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(NTH) void ggemm_mfma_kernel(const GTile* __restrict__ tiles,
+                                                         const GJob* __restrict__ jobs,
+                                                         const GContrib* __restrict__ con,
+                                                         const GSeg* __restrict__ segs, int nslots,
+                                                         typename Cfg<MODE>::T* __restrict__ partial, Bases bs,
+                                                         Bases bout, int fold, int batch, int out_f64) {
+  __shared__ Lds<MODE> s;
+  __shared__ TileMap rm, cm;
+  constexpr int TK = Cfg<MODE>::TK;
+  const GTile t = tiles[blockIdx.x];
+  const GJob J = jobs[t.job];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  int c0 = J.c0, c1 = J.c1, slot = -1;
+  if (t.pad >= 0) {
+    const GSeg g = segs[t.pad];
+    c0 = g.c0;
+    c1 = g.c1;
+    slot = g.slot;
+  }
+  tile_maps(rm, cm, J, t.tm, t.tn, fold, batch, tid);
+  __syncthreads();
+  Acc<MODE> acc;
+  acc.zero();
+  if (c0 < c1) {
+    Stage<MODE> st;
+    int ci = c0, k0 = 0, buf = 0;
+    GContrib c = con[ci];
+    st.load(c, bs, rm, cm, 0, tid);
+    for (;;) {
+      st.store(s, buf, c.flags & GC_TRANS_A, c.flags & GC_TRANS_B, tid);
+      __syncthreads();
+      const int kv = c.k - k0 < TK ? c.k - k0 : TK;
+      int nci = ci, nk0 = k0 + TK;
+      if (nk0 >= c.k) {
+        ++nci;
+        nk0 = 0;
       }
+      const bool more = nci < c1;
+      GContrib nc = c;
+      if (more) {
+        nc = con[nci];
+        st.load(nc, bs, rm, cm, nk0, tid);
+      }
+      mma(acc, s, buf, kv, wm, wn, lane);
+      if (!more) break;
+      ci = nci;
+      k0 = nk0;
+      c = nc;
+      buf ^= 1;
+    }
+  }
+  if (slot >= 0) {
+    const long entry = fold == 0 ? long(blockIdx.y) : 0;
+    write_partial(acc, partial + (entry * nslots + slot) * long(TM * TN), wm, wn, lane);
+  } else {
+    write(acc, bout, J, rm, cm, fold, wm, wn, lane, out_f64 != 0);
+  }
+}
+
+// Sum the partial tiles of each reduction item in segment order and write
+// the tile to its output block.
+template <class PT>
+__global__ __launch_bounds__(NTH) void reduce_partials_kernel(const GRed* __restrict__ red,
+                                                              const GJob* __restrict__ jobs,
+                                                              const PT* __restrict__ partial, int nslots, Bases bout,
+                                                              int fold, int batch, int out_f64) {
+  __shared__ TileMap rm, cm;
+  const GRed r = red[blockIdx.x];
+  const GJob J = jobs[r.job];
+  const int tid = threadIdx.x;
+  tile_maps(rm, cm, J, r.tm, r.tn, fold, batch, tid);
+  __syncthreads();
+  const long entry = fold == 0 ? long(blockIdx.y) : 0;
+  const PT* P = partial + (entry * nslots + r.slot0) * long(TM * TN);
+  for (int e = tid; e < TM * TN; e += NTH) {
+    const int i = e / TN, j = e % TN;
+    if (rm.idx[i] < 0 || cm.idx[j] < 0) continue;
+    double sum = 0;
+    for (int q = 0; q < r.nseg; ++q) sum += double(P[long(q) * TM * TN + e]);
+    if (out_f64) put_out<double>(bout, J, rm, cm, fold, i, j, sum);
+    else put_out<float>(bout, J, rm, cm, fold, i, j, sum);
+  }
 }
 
 __global__ void lincomb_f32_kernel(const LCTarget* __restrict__ tg, const LCSource* __restrict__ src, Bases bs) {
   const LCTarget t = tg[blockIdx.y];
   const int bz = blockIdx.z;
-  float* out = mptr<float>(bs, t.base, t.off, bz);
+  float* out = reinterpret_cast<float*>(bs.p[t.base]) + t.off + long(bz) * bs.stride[t.base];
   for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < t.size; e += long(gridDim.x) * blockDim.x) {
-    float s = 0.f;
-    for (int j = t.s0; j < t.s1; ++j) s = fmaf(float(src[j].c), cptr<float>(bs, src[j].base, src[j].off, bz)[e], s);
-    out[e] = t.accumulate ? out[e] + s : s;
+    float acc = 0.f;
+    for (int j = t.s0; j < t.s1; ++j) {
+      const float* p =
+          reinterpret_cast<const float*>(bs.p[src[j].base]) + src[j].off + long(bz) * bs.stride[src[j].base];
+      acc = fmaf(float(src[j].c), p[e], acc);
+    }
+    out[e] = t.accumulate ? out[e] + acc : acc;
   }
 }
 
 __global__ void diag_add_f32_kernel(const DiagAdd* __restrict__ d, Bases bs) {
   const DiagAdd x = d[blockIdx.x];
-  float* o = mptr<float>(bs, x.base, x.off, blockIdx.y);
+  float* o = reinterpret_cast<float*>(bs.p[x.base]) + x.off + long(blockIdx.y) * bs.stride[x.base];
   for (int i = threadIdx.x; i < x.dim; i += blockDim.x) o[long(i) * (x.dim + 1)] += float(x.c);
 }
 
@@ -217,17 +407,30 @@ __global__ void convert_f64_f32_kernel(const double* __restrict__ in, float* __r
 }  // namespace
 
 void launch_grouped_gemm(int prec, bool out_f64, const GTile* tiles, int ntiles, const GJob* jobs, const GContrib* con,
-                         const Bases& b, const Bases& bout, int batch, hipStream_t s) {
+                         const GSeg* segs, const GRed* red, int nred, int nslots, void* partial, const Bases& b,
+                         const Bases& bout, int fold, int batch, hipStream_t s) {
   if (ntiles <= 0 || batch <= 0) return;
-  const dim3 grid(ntiles, batch), block(NTH);
+  const int gy = fold == 0 ? batch : 1;
+  const dim3 grid(ntiles, gy), block(NTH);
+  const int of = out_f64 ? 1 : 0;
   if (prec == 0) {
-    hipLaunchKernelGGL(ggemm_f64_mfma_kernel, grid, block, 0, s, tiles, jobs, con, b);
-  } else if (prec == 1) {
-    if (out_f64) hipLaunchKernelGGL((ggemm_f32_kernel<1, double>), grid, block, 0, s, tiles, jobs, con, b, bout);
-    else hipLaunchKernelGGL((ggemm_f32_kernel<1, float>), grid, block, 0, s, tiles, jobs, con, b, bout);
+    double* P = static_cast<double*>(partial);
+    hipLaunchKernelGGL(ggemm_mfma_kernel<0>, grid, block, 0, s, tiles, jobs, con, segs, nslots, P, b, bout, fold,
+                       batch, 1);
+    if (nred > 0)
+      hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(nred, gy), block, 0, s, red, jobs, P, nslots, bout,
+                         fold, batch, 1);
   } else {
-    if (out_f64) hipLaunchKernelGGL((ggemm_f32_kernel<2, double>), grid, block, 0, s, tiles, jobs, con, b, bout);
-    else hipLaunchKernelGGL((ggemm_f32_kernel<2, float>), grid, block, 0, s, tiles, jobs, con, b, bout);
+    float* P = static_cast<float*>(partial);
+    if (prec == 1)
+      hipLaunchKernelGGL(ggemm_mfma_kernel<1>, grid, block, 0, s, tiles, jobs, con, segs, nslots, P, b, bout, fold,
+                         batch, of);
+    else
+      hipLaunchKernelGGL(ggemm_mfma_kernel<2>, grid, block, 0, s, tiles, jobs, con, segs, nslots, P, b, bout, fold,
+                         batch, of);
+    if (nred > 0)
+      hipLaunchKernelGGL(reduce_partials_kernel<float>, dim3(nred, gy), block, 0, s, red, jobs, P, nslots, bout, fold,
+                         batch, of);
   }
 }
 

@@ -8,9 +8,27 @@ namespace dmrg {
 // data, FP32 accumulate; 2: FP32 data split into bfloat16 hi/lo, three
 // products, FP32 accumulate.  For prec 1/2 the operands are FP32 and the
 // output is FP64 (out_f64) or FP32; bout gives the output base pointers
-// (may equal b).
+// (may equal b).  fold 0: grid.y runs over the batch entries and the tiles
+// are (job, row tile, column tile) of each job's m x n; fold 1 (B and C
+// batched, A shared): tiles cover m x (batch*n); fold 2 (A and C batched, B
+// shared): tiles cover (batch*m) x n.
+//
+// Split contribution lists: a tile whose `pad` field is >= 0 handles only the
+// contribution range of segs[pad] and writes its dense 64x64 partial sum to
+// slot `slot` of the partial buffer (per batch entry when fold is 0: slot +
+// entry * nslots).  A second kernel then sums the nseg partials of each
+// reduction item in order and writes the tile to the output (deterministic,
+// no atomics).
+enum : int { FOLD_NONE = 0, FOLD_N = 1, FOLD_M = 2 };
+struct GSeg {
+  int c0, c1, slot, pad;
+};
+struct GRed {
+  int job, tm, tn, slot0, nseg, pad;
+};
 void launch_grouped_gemm(int prec, bool out_f64, const GTile* tiles, int ntiles, const GJob* jobs,
-                         const GContrib* con, const Bases& b, const Bases& bout, int batch, hipStream_t s);
+                         const GContrib* con, const GSeg* segs, const GRed* red, int nred, int nslots,
+                         void* partial, const Bases& b, const Bases& bout, int fold, int batch, hipStream_t s);
 
 void launch_lincomb_f32(const LCTarget* t, int ntargets, const LCSource* src, long max_size, const Bases& b,
                         int batch, hipStream_t s);

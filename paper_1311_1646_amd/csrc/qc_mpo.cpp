@@ -202,35 +202,47 @@ Channel QCHamiltonian::describe(uint64_t key, int) const {
 
 void QCHamiltonian::build_channels() {
   const int L = L_;
-  std::vector<std::vector<uint64_t>> keys(L + 1);
-  for (int b = 0; b <= L; ++b) {
-    if (b < L) keys[b].push_back(chan_key(CH_ID_H, -1, -1));
-    if (b > 0) keys[b].push_back(chan_key(CH_H_ID, -1, -1));
-  }
-  for (const Term& T : terms_)
-    for (int b = T.smin + 1; b <= T.smax; ++b)
-      keys[b].push_back(classify(T.op, T.n, b, b <= switch_ ? 0 : 1, nullptr));
-  bonds_.assign(L + 1, {});
-  for (int b = 0; b <= L; ++b) {
-    auto& k = keys[b];
-    std::sort(k.begin(), k.end());
-    k.erase(std::unique(k.begin(), k.end()), k.end());
-    BondChannels& B = bonds_[b];
-    B.mode = b <= switch_ ? 0 : 1;
-    for (uint64_t key : k) {
-      B.idx[key] = int(B.ch.size());
-      B.ch.push_back(describe(key, b));
+  for (int mode = 0; mode < 2; ++mode) {
+    // mode 0 serves bonds 0..switch+1, mode 1 bonds switch+1..L
+    const int b0 = mode == 0 ? 0 : std::min(switch_ + 1, L);
+    const int b1 = mode == 0 ? std::min(switch_ + 1, L) : L;
+    std::vector<std::vector<uint64_t>> keys(L + 1);
+    for (int b = b0; b <= b1; ++b) {
+      if (b < L) keys[b].push_back(chan_key(CH_ID_H, -1, -1));
+      if (b > 0) keys[b].push_back(chan_key(CH_H_ID, -1, -1));
+    }
+    for (const Term& T : terms_)
+      for (int b = std::max(T.smin + 1, b0); b <= std::min(T.smax, b1); ++b)
+        keys[b].push_back(classify(T.op, T.n, b, mode, nullptr));
+    bonds_[mode].assign(L + 1, {});
+    for (int b = 0; b <= L; ++b) {
+      BondChannels& B = bonds_[mode][b];
+      B.mode = (b >= b0 && b <= b1) ? mode : -1;
+      if (B.mode < 0) continue;
+      auto& k = keys[b];
+      std::sort(k.begin(), k.end());
+      k.erase(std::unique(k.begin(), k.end()), k.end());
+      for (uint64_t key : k) {
+        B.idx[key] = int(B.ch.size());
+        B.ch.push_back(describe(key, b));
+      }
     }
   }
 }
 
-const SiteOp& QCHamiltonian::site_op(int b, int width) {
-  const int64_t ck = int64_t(b) * 4 + width;
+const BondChannels& QCHamiltonian::channels(int b, int mode) const {
+  if (b < 0 || b > L_ || mode < 0 || mode > 1 || bonds_[mode][b].mode != mode)
+    throw std::invalid_argument("no channel set for this bond and pair mode");
+  return bonds_[mode][b];
+}
+
+const SiteOp& QCHamiltonian::site_op(int b, int width, int m0, int m1) {
+  const int64_t ck = int64_t(b) * 16 + width * 4 + m0 * 2 + m1;
   auto it = cache_.find(ck);
   if (it != cache_.end()) return it->second;
-  if (width < 1 || width > 2 || b < 0 || b + width > L_) throw std::invalid_argument("bad dot");
-  const BondChannels& B0 = bonds_[b];
-  const BondChannels& B1 = bonds_[b + width];
+  if (width < 1 || width > 2 || b < 0 || b + width > L_ || m0 > m1) throw std::invalid_argument("bad dot");
+  const BondChannels& B0 = channels(b, m0);
+  const BondChannels& B1 = channels(b + width, m1);
   const int lo = 2 * b, hi = 2 * (b + width);  // dot modes [lo, hi)
   struct Acc { double c; bool set; };
   std::map<std::tuple<int, int, int>, Acc> acc;

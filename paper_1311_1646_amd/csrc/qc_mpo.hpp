@@ -103,12 +103,22 @@ class QCHamiltonian {
   QCHamiltonian(int L, const double* h, const double* eri, double ecore, double screen = 1e-14);
   int L() const { return L_; }
   int switch_bond() const { return switch_; }
-  const BondChannels& channels(int b) const { return bonds_[b]; }
+  // Pair mode of the operator sets: left operators at bond b keep the pairs
+  // normal up to the switch bond, right operators up to one bond later, so
+  // that the left and right sets met by a one-site dot always share a mode
+  // (the normal -> complementary conversion then happens only inside one
+  // renormalization step per direction, never inside a one-site sigma).
+  int mode_left(int b) const { return b <= switch_ ? 0 : 1; }
+  int mode_right(int b) const { return b <= switch_ + 1 ? 0 : 1; }
+  const BondChannels& channels(int b, int mode) const;
+  const BondChannels& left_channels(int b) const { return channels(b, mode_left(b)); }
+  const BondChannels& right_channels(int b) const { return channels(b, mode_right(b)); }
   // dot strings of a dot with `width` sites (id space shared by all bonds)
   const DotString& dot_string(int width, int sid) const { return strings_[width - 1][sid]; }
   int num_dot_strings(int width) const { return int(strings_[width - 1].size()); }
-  // site tensor for the dot starting at site b with 1 or 2 sites (cached)
-  const SiteOp& site_op(int b, int width);
+  // site tensor for the dot starting at site b with 1 or 2 sites, from the
+  // channels of bond b in mode m0 to those of bond b+width in mode m1 (cached)
+  const SiteOp& site_op(int b, int width, int m0, int m1);
   size_t num_terms() const { return terms_.size(); }
   double ecore() const { return ecore_; }
 
@@ -117,7 +127,7 @@ class QCHamiltonian {
   double ecore_;
   std::vector<Term> terms_;
   std::vector<std::vector<int>> terms_on_site_;
-  std::vector<BondChannels> bonds_;
+  std::vector<BondChannels> bonds_[2];  // per pair mode (built where used)
   std::vector<DotString> strings_[2];
   std::unordered_map<int, int> string_index_[2];
   std::unordered_map<int64_t, SiteOp> cache_;
