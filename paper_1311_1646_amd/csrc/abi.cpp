@@ -111,14 +111,20 @@ int dmrg_get_layout(dmrg_ctx* ctx, int site, int width, int* nblocks_out, int* b
   });
 }
 
+namespace {
+bool valid_prec(int p) { return p == DMRG_FP64 || p == DMRG_FP32 || p == DMRG_BF16X3; }
+}  // namespace
+
 int dmrg_build_ops(dmrg_ctx* ctx, int prec) {
-  return guard(ctx, [&](dmrg::Ctx& x) { x.build_ops(prec); });
+  return guard(ctx, [&](dmrg::Ctx& x) {
+    DMRG_REQUIRE(valid_prec(prec), DMRG_ERR_INVALID_ARG, "unsupported precision");
+    x.build_ops(prec);
+  });
 }
 
 int dmrg_sigma(dmrg_ctx* ctx, int site, int kind, int nvec, const double* C_in, double* sigma_out, int prec) {
   return guard(ctx, [&](dmrg::Ctx& x) {
-    DMRG_REQUIRE(prec == DMRG_FP64 || prec == DMRG_FP32 || prec == DMRG_BF16X3, DMRG_ERR_INVALID_ARG,
-                 "unsupported precision");
+    DMRG_REQUIRE(valid_prec(prec), DMRG_ERR_INVALID_ARG, "unsupported precision");
     DMRG_REQUIRE(kind == DMRG_SIGMA_ZEROTH_1SITE || kind == DMRG_SIGMA_ZEROTH_2SITE, DMRG_ERR_INVALID_ARG,
                  "TDA sigma kinds are internal to dmrg_tda_roots");
     x.sigma(site, kind == DMRG_SIGMA_ZEROTH_1SITE ? 1 : 2, nvec, C_in, sigma_out, prec);
@@ -137,15 +143,15 @@ int dmrg_renormalize(dmrg_ctx* ctx, int site, int dir, int order, int prec) {
   return guard(ctx, [&](dmrg::Ctx& x) {
     x.require_gpu();
     DMRG_REQUIRE(order == 0, DMRG_ERR_INVALID_ARG, "first-order sets are internal to dmrg_tda_roots");
-    DMRG_REQUIRE(prec == DMRG_FP64, DMRG_ERR_INVALID_ARG, "unsupported precision");
+    DMRG_REQUIRE(valid_prec(prec), DMRG_ERR_INVALID_ARG, "unsupported precision");
     DMRG_REQUIRE(x.ops_prec >= 0, DMRG_ERR_STATE, "call dmrg_build_ops first");
     DMRG_REQUIRE(site >= 0 && site < x.L, DMRG_ERR_INVALID_ARG, "bad site");
     if (dir == DMRG_DIR_LEFT) {
       x.renorm(DMRG_DIR_LEFT, site, x.site[site].L.as<double>(), x.site[site].L.as<double>(), 0, x.left[site],
-               x.left[site + 1], false, 1);
+               x.left[site + 1], false, 1, prec);
     } else {
       x.renorm(DMRG_DIR_RIGHT, site, x.site[site].R.as<double>(), x.site[site].R.as<double>(), 0,
-               x.right[site + 1], x.right[site], false, 1);
+               x.right[site + 1], x.right[site], false, 1, prec);
     }
     x.sync();
   });
@@ -160,7 +166,7 @@ int dmrg_tda_roots(dmrg_ctx* ctx, int nroots, const dmrg_davidson_params* p, dou
   bool conv = false;
   int rc = guard(ctx, [&](dmrg::Ctx& x) {
     DMRG_REQUIRE(p, DMRG_ERR_INVALID_ARG, "null parameters");
-    DMRG_REQUIRE(p->prec == DMRG_FP64, DMRG_ERR_INVALID_ARG, "unsupported precision");
+    DMRG_REQUIRE(valid_prec(p->prec), DMRG_ERR_INVALID_ARG, "unsupported precision");
     x.tda_roots(nroots, *p, omega, e_total, resid2, iters, &conv);
   });
   if (rc == DMRG_OK && !conv) {

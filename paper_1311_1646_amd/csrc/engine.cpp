@@ -830,10 +830,11 @@ ContractionPlan& Ctx::renorm_plan(int dir, int i, const OpSet& src, const OpSet&
 }
 
 void Ctx::renorm(int dir, int i, const double* Abra, const double* Aket, long aket_stride, const OpSet& src,
-                 OpSet& dst, bool accumulate, int batch) {
+                 OpSet& dst, bool accumulate, int batch, int prec) {
   ContractionPlan& P = renorm_plan(dir, i, src, dst);
   const bool src_b = src.nvec > 1, ket_b = aket_stride != 0;
   const bool t_b = src_b || ket_b;
+  const size_t esz = prec == DMRG_FP64 ? 8 : 4;
   Bases b{};
   b.p[B_ABRA] = const_cast<double*>(Abra);
   b.p[B_AKET] = const_cast<double*>(Aket);
@@ -842,22 +843,37 @@ void Ctx::renorm(int dir, int i, const double* Abra, const double* Aket, long ak
   b.stride[B_SRC] = src_b ? src.per_vec : 0;
   b.p[B_DST] = dst.ptr();
   b.stride[B_DST] = dst.nvec > 1 ? dst.per_vec : 0;
-  ws_dress.ensure(this, std::max<size_t>(size_t(P.dressed_per_vec) * (src_b ? batch : 1), 1) * 8);
+  ws_dress.ensure(this, std::max<size_t>(size_t(P.dressed_per_vec) * (src_b ? batch : 1), 1) * esz);
   ws_blk.ensure(this, std::max<size_t>(size_t(P.blocks_per_vec) * (t_b ? batch : 1), 1) * 8);
-  ws_T.ensure(this, std::max<size_t>(size_t(P.main.t_per_vec) * (t_b ? batch : 1), 1) * 8);
+  ws_T.ensure(this, std::max<size_t>(size_t(P.main.t_per_vec) * (t_b ? batch : 1), 1) * esz);
   b.p[B_DRESS] = ws_dress.as<double>();
   b.stride[B_DRESS] = src_b ? P.dressed_per_vec : 0;
   b.p[B_BLK] = ws_blk.as<double>();
   b.stride[B_BLK] = t_b ? P.blocks_per_vec : 0;
   b.p[B_T] = ws_T.as<double>();
   b.stride[B_T] = t_b ? P.main.t_per_vec : 0;
+  if (prec != DMRG_FP64) {
+    // FP32 operands: operator shadow, site tensors converted per call
+    ensure_f32(src);
+    b.p[B_SRC] = reinterpret_cast<double*>(src.data32.as<float>());
+    const long S = long(layout(i, 1).size);
+    const long nket = ket_b ? S * batch : S;
+    ws_a32.ensure(this, size_t(S + nket) * 4);
+    float* abra = ws_a32.as<float>();
+    float* aket = abra + S;
+    launch_convert_f64_f32(Abra, abra, S, stream);
+    launch_convert_f64_f32(Aket, aket, nket, stream);
+    b.p[B_ABRA] = reinterpret_cast<double*>(abra);
+    b.p[B_AKET] = reinterpret_cast<double*>(aket);
+    b.stride[B_AKET] = ket_b ? S : 0;
+  }
   dst.f32_valid = false;
   if (!accumulate) launch_fill_f64(dst.ptr(), long(dst.per_vec) * dst.nvec, 0.0, stream);
   if (P.blocks_per_vec) launch_fill_f64(ws_blk.as<double>(), P.blocks_per_vec * (t_b ? batch : 1), 0.0, stream);
-  P.form.launch(*this, b, src_b ? batch : 1);
+  P.form.launch(*this, b, src_b ? batch : 1, prec);
   for (auto& ch : P.main.chunks) {
-    ch.first.launch(*this, b, t_b ? batch : 1);
-    ch.second.launch(*this, b, batch);
+    ch.first.launch(*this, b, t_b ? batch : 1, prec, prec == DMRG_FP64);
+    ch.second.launch(*this, b, batch, prec, true);
   }
   P.post.launch(*this, b, batch);
   stats.renorm_flops += P.main.flops1 * (t_b ? batch : 1) + P.main.flops2 * batch;
@@ -866,7 +882,12 @@ void Ctx::renorm(int dir, int i, const double* Abra, const double* Aket, long ak
 void Ctx::build_ops(int prec) {
   require_gpu();
   DMRG_REQUIRE(have_mps, DMRG_ERR_STATE, "import or compute an MPS first");
-  DMRG_REQUIRE(prec == DMRG_FP64, DMRG_ERR_INVALID_ARG, "operator pools: only FP64 is built in this version");
+  DMRG_REQUIRE(prec == DMRG_FP64 || prec == DMRG_FP32 || prec == DMRG_BF16X3, DMRG_ERR_INVALID_ARG,
+               "unsupported precision");
+  // The zeroth-order pools feed every later contraction and their errors
+  // compound over the bonds, so a BF16x3 request builds them in FP32; the
+  // sigma and the first-order sets of the TDA use BF16x3 as asked.
+  const int rprec = prec == DMRG_BF16X3 ? DMRG_FP32 : prec;
   left.clear();
   right.clear();
   left.resize(L + 1);
@@ -879,12 +900,14 @@ void Ctx::build_ops(int prec) {
   alloc_opset(left[0], 0, 0, 1, false);
   for (int i = 0; i < L; ++i) {
     alloc_opset(left[i + 1], i + 1, 0, 1, false);
-    renorm(DMRG_DIR_LEFT, i, site[i].L.as<double>(), site[i].L.as<double>(), 0, left[i], left[i + 1], false, 1);
+    renorm(DMRG_DIR_LEFT, i, site[i].L.as<double>(), site[i].L.as<double>(), 0, left[i], left[i + 1], false, 1,
+           rprec);
   }
   alloc_opset(right[L], L, 1, 1, false);
   for (int i = L - 1; i >= 0; --i) {
     alloc_opset(right[i], i, 1, 1, false);
-    renorm(DMRG_DIR_RIGHT, i, site[i].R.as<double>(), site[i].R.as<double>(), 0, right[i + 1], right[i], false, 1);
+    renorm(DMRG_DIR_RIGHT, i, site[i].R.as<double>(), site[i].R.as<double>(), 0, right[i + 1], right[i], false, 1,
+           rprec);
   }
   DMRG_HIP(hipEventRecord(e1, stream));
   DMRG_HIP(hipEventSynchronize(e1));

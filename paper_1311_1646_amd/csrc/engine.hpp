@@ -178,7 +178,7 @@ class Ctx {
   int ops_prec = -1;
 
   // workspaces
-  DBuf ws_T, ws_dress, ws_blk, ws_aux, ws_c32, ws_part;
+  DBuf ws_T, ws_dress, ws_blk, ws_aux, ws_c32, ws_part, ws_a32;
 
   dmrg_stats stats{};
 
@@ -201,7 +201,7 @@ class Ctx {
   // carry their own stride).  accumulate: add into dst instead of
   // overwriting it.
   void renorm(int dir, int i, const double* Abra, const double* Aket, long aket_stride, const OpSet& src,
-              OpSet& dst, bool accumulate, int batch);
+              OpSet& dst, bool accumulate, int batch, int prec = 0);
   // sigma = H_eff C with the left set X and the right set Z on the dot
   // (i, width); C has batch stride cstride (0 = shared), outputs have stride
   // sstride; batch = number of outputs.

@@ -54,7 +54,7 @@ struct HostRng {
 
 class TdaRunner {
  public:
-  TdaRunner(Ctx& x, int nroots, const dmrg_davidson_params& p) : x_(x), n_(nroots), p_(p) {
+  TdaRunner(Ctx& x, int nroots, const dmrg_davidson_params& p) : x_(x), n_(nroots), p_(p), prec_(p.prec) {
     L_ = x.L;
     Nmax_ = p.max_space > 0 ? p.max_space : std::min(64, std::max(3 * n_, n_ + 16));
     DMRG_REQUIRE(Nmax_ <= 64, DMRG_ERR_INVALID_ARG, "max_space must be <= 64");
@@ -117,6 +117,7 @@ class TdaRunner {
   Ctx& x_;
   int n_, L_, Nmax_;
   dmrg_davidson_params p_;
+  int prec_;  // contraction precision of sigma and renormalization
   std::vector<long> size_;
   long maxsize_;
   std::vector<std::vector<long>> bm_off_;
@@ -348,6 +349,7 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
   HostRng rng(seed);
   std::vector<double> tmp;
   for (int i = 0; i < L_; ++i) {
+    if (p_.verbose >= 2) std::fprintf(stderr, "[tda] forward site %d (l=%d)\n", i, m + n_);
     const long S = size_[i];
     double* Cm = Cm_.as<double>();
     const double* C0 = x_.site[i].C.as<double>();
@@ -367,12 +369,12 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
     }
     // first-order left part of the sigma for all l vectors (eq. sigv2, first line)
     double* Dl = Dl_.as<double>();
-    x_.sigma_general(i, 1, FL_[cur], x_.right[i + 1], C0, 0, Dl, S, l);
+    x_.sigma_general(i, 1, FL_[cur], x_.right[i + 1], C0, 0, Dl, S, l, prec_);
     double* Wk = Wk_.as<double>();
     if (!init) {
       // sigma (eq. sigv1), residual (eq. rnorm), correction (eqs. error, param)
       double* Sg = Sg_.as<double>();
-      x_.sigma_general(i, 1, x_.left[i], x_.right[i + 1], Cm, S, Sg, S, n_);
+      x_.sigma_general(i, 1, x_.left[i], x_.right[i + 1], Cm, S, Sg, S, n_, prec_);
       launch_axpby_f64(ones_.as<double>(), Dl, S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
       launch_axpby_f64(ones_.as<double>(), Gr_.as<double>(), S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
       launch_axpby_f64(negw_.as<double>(), Cm, S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
@@ -402,7 +404,7 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
     q_l_project(i, Cm, Ct, l);
     // reduced matrices (eqs. hleft2, sleft2)
     double* S0 = S0_.as<double>();
-    x_.sigma_general(i, 1, x_.left[i], x_.right[i + 1], Ct, S, S0, S, l);
+    x_.sigma_general(i, 1, x_.left[i], x_.right[i + 1], Ct, S, S0, S, l, prec_);
     gram(Ct, S, l, Ct, S, l, S, SR_.as<double>(), l, 1.0, true);
     gram(Ct, S, l, S0, S, l, S, HR_.as<double>(), l, 1.0, true);
     gram(Ct, S, l, Dl, S, l, S, HR_.as<double>(), l, 1.0, true);
@@ -414,8 +416,8 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
     const int nxt = 1 - cur;
     x_.alloc_opset(FL_[nxt], i + 1, 0, l, true);
     const double* Li = x_.site[i].L.as<double>();
-    x_.renorm(DMRG_DIR_LEFT, i, Li, Li, 0, FL_[cur], FL_[nxt], false, l);
-    x_.renorm(DMRG_DIR_LEFT, i, Li, Wk, S, x_.left[i], FL_[nxt], true, l);
+    x_.renorm(DMRG_DIR_LEFT, i, Li, Li, 0, FL_[cur], FL_[nxt], false, l, prec_);
+    x_.renorm(DMRG_DIR_LEFT, i, Li, Wk, S, x_.left[i], FL_[nxt], true, l, prec_);
     if (m > 0) copy(Cprev_.as<double>(), Cm, long(m) * S);
     x_.sync();
     FL_[cur].data.release();
@@ -432,6 +434,7 @@ void TdaRunner::backward(int l) {
   double* Cb = Cb_.as<double>();
   copy(Cb, Ct_[L_ - 1].as<double>(), long(l) * size_[L_ - 1]);
   for (int i = L_ - 1; i >= 0; --i) {
+    if (p_.verbose >= 2) std::fprintf(stderr, "[tda] backward site %d (l=%d)\n", i, l);
     const long S = size_[i];
     const double* Ri = x_.site[i].R.as<double>();
     // R^(1) (eq. right1st): Lambda^-1 C (1 - R^T R)
@@ -441,13 +444,13 @@ void TdaRunner::backward(int l) {
     lmul_sub(i, bm_.as<double>(), bm_size_[i], Ri, 0, R1, l);
     scale(i, true, true, R1, l);
     // first-order right part of the sigma contracted with C^(0)
-    x_.sigma_general(i, 1, x_.left[i], FR_[cur], x_.site[i].C.as<double>(), 0, G_[i].as<double>(), S, l);
+    x_.sigma_general(i, 1, x_.left[i], FR_[cur], x_.site[i].C.as<double>(), 0, G_[i].as<double>(), S, l, prec_);
     if (i == 0) break;
     // first-order right operators (eq. ropr1st)
     const int nxt = 1 - cur;
     x_.alloc_opset(FR_[nxt], i, 1, l, true);
-    x_.renorm(DMRG_DIR_RIGHT, i, Ri, Ri, 0, FR_[cur], FR_[nxt], false, l);
-    x_.renorm(DMRG_DIR_RIGHT, i, Ri, R1, S, x_.right[i + 1], FR_[nxt], true, l);
+    x_.renorm(DMRG_DIR_RIGHT, i, Ri, Ri, 0, FR_[cur], FR_[nxt], false, l, prec_);
+    x_.renorm(DMRG_DIR_RIGHT, i, Ri, R1, S, x_.right[i + 1], FR_[nxt], true, l, prec_);
     // gauge shift to site i-1 (eq. gauge_bwd): C_{i-1} = C~_{i-1} + L_{i-1} (C_i R_i^T)
     double* Wk = Wk_.as<double>();
     copy(Wk, Ct_[i - 1].as<double>(), long(l) * size_[i - 1]);
@@ -470,7 +473,7 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
   // reference energy E0 = <Psi0|H|Psi0> at site 0
   {
     const double* C0 = x_.site[0].C.as<double>();
-    x_.sigma_general(0, 1, x_.left[0], x_.right[1], C0, 0, Wk_.as<double>(), size_[0], 1);
+    x_.sigma_general(0, 1, x_.left[0], x_.right[1], C0, 0, Wk_.as<double>(), size_[0], 1, DMRG_FP64);
     gram(C0, size_[0], 1, Wk_.as<double>(), size_[0], 1, size_[0], tmpd_.as<double>(), 1, 1.0, false);
     DMRG_HIP(hipMemcpy(&E0_, tmpd_.p, 8, hipMemcpyDeviceToHost));
   }

@@ -11,14 +11,15 @@ from helpers import mps_arrays
 pytestmark = pytest.mark.gpu
 
 
-def _run(L, Na, Nb, M, seed, nroots, K=6, tol=1e-12, max_iter=60, max_space=0):
+def _run(L, Na, Nb, M, seed, nroots, K=6, tol=1e-12, max_iter=60, max_space=0, prec=0):
     import paper_1311_1646_amd as lib
     h, eri, _ = synth.random_integrals(L, seed=seed, K=K, diag_lo=-2, diag_hi=0)
     mps = synth.random_mps(L, Na, Nb, M, seed=seed + 1)
     ctx = lib.Context(L, Na, Nb, h, eri, 0.0, device=0)
     ctx.import_mps(*mps_arrays(mps))
-    ctx.build_ops()
-    om, et, r2, it, conv = ctx.tda_roots(nroots, max_iter=max_iter, max_space=max_space, tol=tol, seed=3)
+    ctx.build_ops(prec)
+    om, et, r2, it, conv = ctx.tda_roots(nroots, max_iter=max_iter, max_space=max_space, tol=tol, seed=3,
+                                         prec=prec)
     dets, H = fci.hamiltonian(h, eri, 0.0, Na, Nb)
     E0, ref = tda.tda_roots(mps, dets, H, nroots)
     return om, et, r2, it, conv, E0, ref
@@ -38,3 +39,19 @@ def test_tda_config0_shape_four_roots():
     assert conv
     np.testing.assert_allclose(et, ref, atol=1e-8)
     np.testing.assert_allclose(om, ref - E0, atol=1e-8)
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_tda_low_precision_contractions_within_tolerance(prec):
+    # FP32 / BF16x3 sigma and renormalization, FP64 Davidson, projections and
+    # reduced matrices: excitation energies within 1e-5 Eh of the FP64 oracle.
+    # The contractions put a floor under the residual: |r| ~ u |H C| with u
+    # = 6e-8 (FP32) or ~2^-16 (BF16x3), i.e. |r|^2 ~ 1e-12 and ~1e-8 here, so
+    # the iteration stops at 1e-9 and 1e-7; the eigenvalue error is of order
+    # |r|^2 / gap, far inside 1e-5.
+    tol = {1: 1e-9, 2: 1e-7}[prec]
+    om, et, r2, it, conv, E0, ref = _run(8, 4, 4, 24, 0, 4, K=16, tol=tol, max_space=40, max_iter=80, prec=prec)
+    print(f"prec {prec}: |d omega| {np.abs(om - (ref - E0)).max():.2e} |d E| {np.abs(et - ref).max():.2e}")
+    assert conv, (it, r2)
+    np.testing.assert_allclose(om, ref - E0, atol=1e-5)
+    np.testing.assert_allclose(et, ref, atol=1e-5)
