@@ -166,12 +166,12 @@ const GemmPlan::FoldTiles& GemmPlan::fold_lists(Ctx& x, int fold, int batch) con
 }
 
 void LinCombPlan::launch(Ctx& x, const Bases& b, int batch, int prec) const {
-  if (prec == 0) {
-    if (nt) launch_lincomb_f64(t.as<LCTarget>(), nt, s.as<LCSource>(), max_size, b, batch, x.stream);
-    if (nd) launch_diag_add_f64(d.as<DiagAdd>(), nd, b, batch, x.stream);
-  } else {
-    if (nt) launch_lincomb_f32(t.as<LCTarget>(), nt, s.as<LCSource>(), max_size, b, batch, x.stream);
-    if (nd) launch_diag_add_f32(d.as<DiagAdd>(), nd, b, batch, x.stream);
+  if (ng)
+    launch_lincomb_grouped(prec, g.as<LCGroup>(), ng, t.as<LCTarget>(), u.as<LCSource>(), coef.as<double>(), max_size,
+                           b, batch, x.stream);
+  if (nd) {
+    if (prec == 0) launch_diag_add_f64(d.as<DiagAdd>(), nd, b, batch, x.stream);
+    else launch_diag_add_f32(d.as<DiagAdd>(), nd, b, batch, x.stream);
   }
   DMRG_HIP(hipGetLastError());
 }
@@ -191,17 +191,56 @@ struct LinCombBuilder {
     s.push_back({off, base, 0, c});
     t.back().s1 = int(s.size());
   }
+  // Targets of equal size are grouped by similar source lists, kLCGroup at
+  // a time; each group reads the merged source list once.
   void finish(Ctx& x, LinCombPlan& P) {
-    upload(x, P.t, t);
-    upload(x, P.s, s);
+    typedef std::pair<int, long> SrcKey;  // (base, offset)
+    std::vector<std::vector<SrcKey>> keys(t.size());
+    for (size_t k = 0; k < t.size(); ++k) {
+      for (int j = t[k].s0; j < t[k].s1; ++j) keys[k].push_back({s[j].base, s[j].off});
+      std::sort(keys[k].begin(), keys[k].end());
+    }
+    std::map<long, std::vector<int>> by_size;
+    for (size_t k = 0; k < t.size(); ++k) by_size[t[k].size].push_back(int(k));
+    std::vector<LCTarget> tg;
+    std::vector<LCGroup> gr;
+    std::vector<LCSource> us;
+    std::vector<double> cf;
+    for (auto& kv : by_size) {
+      std::vector<int>& v = kv.second;
+      std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return keys[a] < keys[b]; });
+      for (size_t g0 = 0; g0 < v.size(); g0 += kLCGroup) {
+        const int n = int(std::min<size_t>(kLCGroup, v.size() - g0));
+        std::map<SrcKey, std::vector<double>> uni;
+        for (int k = 0; k < n; ++k) {
+          const LCTarget& q = t[v[g0 + k]];
+          for (int j = q.s0; j < q.s1; ++j) {
+            auto& c = uni[{s[j].base, s[j].off}];
+            if (c.empty()) c.assign(kLCGroup, 0.0);
+            c[k] += s[j].c;
+          }
+        }
+        LCGroup G{kv.first, int(tg.size()), n, int(us.size()), 0};
+        for (int k = 0; k < n; ++k) tg.push_back(t[v[g0 + k]]);
+        for (auto& u : uni) {
+          us.push_back({u.first.second, u.first.first, 0, 0.0});
+          cf.insert(cf.end(), u.second.begin(), u.second.end());
+        }
+        G.u1 = int(us.size());
+        gr.push_back(G);
+        P.reads += double(kv.first) * double(uni.size());
+      }
+    }
+    upload(x, P.t, tg);
+    upload(x, P.u, us);
+    upload(x, P.coef, cf);
+    upload(x, P.g, gr);
     upload(x, P.d, d);
-    P.nt = int(t.size());
+    P.nt = int(tg.size());
+    P.ng = int(gr.size());
     P.nd = int(d.size());
     P.max_size = max_size;
-    for (auto& q : t) {
-      P.elems += double(q.size);
-      P.reads += double(q.size) * (q.s1 - q.s0);
-    }
+    for (auto& q : t) P.elems += double(q.size);
   }
 };
 

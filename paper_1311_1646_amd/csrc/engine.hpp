@@ -104,8 +104,8 @@ struct GemmPlan {
 void build_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<std::vector<GContrib>>& per);
 
 struct LinCombPlan {
-  DBuf t, s, d;
-  int nt = 0, nd = 0;
+  DBuf t, s, d, g, u, coef;
+  int nt = 0, nd = 0, ng = 0;
   long max_size = 0;
   double elems = 0, reads = 0;  // plan statistics: target elements, source element reads
   void launch(Ctx& x, const Bases& b, int batch, int prec = 0) const;

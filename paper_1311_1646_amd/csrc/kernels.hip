@@ -378,6 +378,48 @@ void launch_grouped_gemm_f64(const GTile* tiles, int ntiles, const GJob* jobs, c
   hipLaunchKernelGGL(grouped_gemm_f64_kernel, dim3(ntiles, batch), dim3(NT), 0, s, tiles, jobs, con, b);
 }
 
+template <class T>
+__global__ __launch_bounds__(256) void lincomb_grouped_kernel(const LCGroup* __restrict__ groups,
+                                                              const LCTarget* __restrict__ tg,
+                                                              const LCSource* __restrict__ us,
+                                                              const double* __restrict__ coef, Bases bs) {
+  const LCGroup G = groups[blockIdx.y];
+  const long bz = blockIdx.z;
+  for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < G.size; e += long(gridDim.x) * blockDim.x) {
+    T acc[kLCGroup];
+#pragma unroll
+    for (int k = 0; k < kLCGroup; ++k) acc[k] = T(0);
+    for (int u = G.u0; u < G.u1; ++u) {
+      const LCSource q = us[u];
+      const T x = reinterpret_cast<const T*>(bs.p[q.base])[q.off + bz * bs.stride[q.base] + e];
+#pragma unroll
+      for (int k = 0; k < kLCGroup; ++k) acc[k] += T(coef[long(u) * kLCGroup + k]) * x;
+    }
+#pragma unroll
+    for (int k = 0; k < kLCGroup; ++k) {
+      if (k >= G.nt) break;
+      const LCTarget t = tg[G.t0 + k];
+      T* o = reinterpret_cast<T*>(bs.p[t.base]) + t.off + bz * bs.stride[t.base] + e;
+      *o = t.accumulate ? *o + acc[k] : acc[k];
+    }
+  }
+}
+
+void launch_lincomb_grouped(int prec, const LCGroup* g, int ngroups, const LCTarget* t, const LCSource* u,
+                            const double* coef, long max_size, const Bases& b, int batch, hipStream_t s) {
+  if (ngroups <= 0 || max_size <= 0 || batch <= 0) return;
+  long blocks = (max_size + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  for (int g0 = 0; g0 < ngroups; g0 += 65535) {
+    const int ng = ngroups - g0 < 65535 ? ngroups - g0 : 65535;
+    const dim3 grid(unsigned(blocks), ng, batch);
+    if (prec == 0)
+      hipLaunchKernelGGL(lincomb_grouped_kernel<double>, grid, dim3(256), 0, s, g + g0, t, u, coef, b);
+    else
+      hipLaunchKernelGGL(lincomb_grouped_kernel<float>, grid, dim3(256), 0, s, g + g0, t, u, coef, b);
+  }
+}
+
 void launch_lincomb_f64(const LCTarget* t, int ntargets, const LCSource* src, long max_size, const Bases& b,
                         int batch, hipStream_t s) {
   if (ntargets <= 0 || max_size <= 0 || batch <= 0) return;

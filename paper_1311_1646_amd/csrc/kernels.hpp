@@ -62,6 +62,19 @@ struct LCSource {
 void launch_lincomb_f64(const LCTarget* t, int ntargets, const LCSource* src, long max_size, const Bases& b,
                         int batch, hipStream_t s);
 
+// Grouped linear combinations: up to kLCGroup targets of equal size read one
+// merged, sorted list of sources; each source element is loaded once per
+// group and applied to every target of the group with its coefficient
+// (coef[u * kLCGroup + k], zero where target k does not use source u).
+constexpr int kLCGroup = 8;
+struct LCGroup {
+  long size;
+  int t0, nt, u0, u1;
+};
+// prec 0: FP64 data; otherwise FP32 data (coefficients applied in FP32)
+void launch_lincomb_grouped(int prec, const LCGroup* g, int ngroups, const LCTarget* t, const LCSource* u,
+                            const double* coef, long max_size, const Bases& b, int batch, hipStream_t s);
+
 // out[off + i*(dim+1)] += c for i < dim (identity added to a diagonal block)
 struct DiagAdd {
   long off;
