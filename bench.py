@@ -1,15 +1,19 @@
-"""Benchmark: DMRG sigma GFLOP/s (and, when available, the DMRG-TDA sweep
-time) on one MI355X.
+"""Benchmark: DMRG sigma GFLOP/s and DMRG-TDA sweep time on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4] [--M 1000]
-                    [--nroots 16] [--prec fp64] [--no-cpu-baseline]
+                    [--nroots 16] [--prec fp32] [--ladder] [--tda-iters 1]
+                    [--copy-calib] [--no-cpu-baseline]
 
 Workload (synthetic, seeded): the [2Fe-2S]-shaped problem L=36 orbitals,
 N=30 electrons, Sz=0, a 10-orbital near-degenerate block with strong
 exchange (K=108 Cholesky rank), a random mixed-canonical MPS with M=1000.
 A step is one sigma of the one-site effective Hamiltonian at the middle site
-for all TDA roots at once (nroots vectors resident in HBM).  One JSON line is
-printed (rank 0).
+for all TDA roots at once (nroots vectors resident in HBM); `value` is its
+rate.  After the timed steps, one DMRG-TDA Davidson iteration (a forward and
+a backward sweep over all sites with l = 2 nroots trial vectors) is timed
+and reported as `tda_sweep_s`.  --copy-calib first runs one 256 MiB device
+copy, so that a hardware-counter run of this command also measures a
+transfer of known size.  One JSON line is printed.
 """
 from __future__ import annotations
 
@@ -93,7 +97,23 @@ def time_sigma(ctx, lib, site, C, S, name, steps, warmup):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return {"gflops": round(fl / (ms * 1e-3) / 1e9, 2), "device_ms": round(ms / steps, 3),
-            "wall_ms": round(wall / steps * 1e3, 3), "main_ms": mms / steps, "main_flops": mfl / steps}
+            "wall_ms": round(wall / steps * 1e3, 3), "main_ms": mms / steps, "main_flops": mfl / steps,
+            "main_bytes": s["sigma_main_bytes"], "main_launches": s["sigma_main_launches"]}
+
+
+def measured_traffic(prec, M):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when there is none for this precision and workload or
+    the kernel source changed since the counters were taken."""
+    import hashlib
+    f = os.path.join(ROOT, "profiles", "sigma_accumulate_traffic.json")
+    if not os.path.exists(f):
+        return None
+    d = json.load(open(f))
+    src = open(os.path.join(ROOT, "paper_1311_1646_amd", "csrc", "kernels_mfma.hip"), "rb").read()
+    if d.get("kernel_sha256") != hashlib.sha256(src).hexdigest() or d.get("prec") != prec or d.get("M") != M:
+        return None
+    return d["hbm_bytes_per_launch"]
 
 
 def main():
@@ -106,6 +126,8 @@ def main():
     ap.add_argument("--nroots", type=int, default=16)
     ap.add_argument("--prec", default="fp32", choices=list(PRECS))
     ap.add_argument("--ladder", action="store_true", help="also time the other precisions")
+    ap.add_argument("--tda-iters", type=int, default=1, help="TDA Davidson iterations to time (0: none)")
+    ap.add_argument("--copy-calib", action="store_true", help="run one 256 MiB device copy first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
@@ -120,6 +142,12 @@ def main():
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from helpers import mps_arrays
 
+    if a.copy_calib:
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     p = synth.config(a.config, M=a.M)
     t0 = time.perf_counter()
     mps = synth.random_mps(p.L, p.Na, p.Nb, p.M, seed=1000 * a.config + 1)
@@ -143,7 +171,7 @@ def main():
         log(f"[bench] {name}: {ladder[name]}")
     head = ladder[a.prec]
     out = {
-        "metric": "sigma GFLOP/s (TDA sigma, all roots, middle site)",
+        "metric": "sigma GFLOP/s + TDA sweep s at M=1000 (FP32/BF16x3 vs FP64, 1 GPU)",
         "value": head["gflops"],
         "unit": "GFLOP/s",
         "n_gpus": 1,
@@ -163,10 +191,27 @@ def main():
                    "precision_ladder": {k: {"GFLOP/s": v["gflops"], "device_ms": v["device_ms"]}
                                         for k, v in ladder.items()}},
     }
-    # dominant kernel: the stage-2 grouped GEMM of the sigma
+    # dominant kernel: the accumulation stage (grouped GEMM, role 1) of the
+    # sigma; per launch = per sigma / launches, so the ratio is the same
     ach = head["main_flops"] / (max(head["main_ms"], 1e-9) * 1e-3)
+    nl = max(head["main_launches"], 1)
     out["roofline"] = {"bound": "mfma", "achieved": round(ach / 1e12, 3), "peak": PEAK[a.prec] / 1e12,
-                       "unit": "TFLOP/s", "frac": round(ach / PEAK[a.prec], 4), "traffic": None}
+                       "unit": "TFLOP/s", "frac": round(ach / PEAK[a.prec], 4),
+                       "traffic": measured_traffic(a.prec, p.M)}
+    out["config"]["dominant_kernel"] = {
+        "name": "ggemm_mfma_kernel<%d, 1>" % {"fp64": 0, "fp32": 1, "bf16x3": 2}[a.prec],
+        "launches_per_sigma": nl, "avg_launch_ms": round(head["main_ms"] / nl, 4),
+        "flops_per_launch": head["main_flops"] / nl, "algorithmic_bytes_per_launch": head["main_bytes"] / nl}
+    if a.tda_iters > 0:
+        prec = {"fp64": lib.FP64, "fp32": lib.FP32, "bf16x3": lib.BF16X3}[a.prec]
+        t0 = time.perf_counter()
+        _, _, _, its, _ = ctx.tda_roots(a.nroots, max_iter=a.tda_iters, tol=0.0, seed=7, prec=prec, verbose=1)
+        wall = time.perf_counter() - t0
+        s = ctx.stats()
+        out["tda_sweep_s"] = round(s["tda_iter_ms"] / 1e3, 3)
+        out["tda"] = {"iterations": its, "trial_vectors": 2 * a.nroots, "last_iteration_s": round(s["tda_iter_ms"] / 1e3, 3),
+                      "total_s_incl_setup": round(wall, 2), "prec": a.prec}
+        log(f"[bench] TDA: {out['tda']}")
     if not a.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(a.nroots)

@@ -182,12 +182,15 @@ typedef struct {
   double sigma_ms;         /* device time of the last dmrg_sigma call              */
   double sigma_main_ms;    /* device time of its dominant (stage-2) kernel         */
   double sigma_main_flops; /* algorithmic flops of that kernel                     */
-  double sigma_main_bytes; /* algorithmic HBM bytes of that kernel                 */
+  double sigma_main_bytes; /* algorithmic bytes of that kernel: distinct operator
+                              blocks and products read once, results read and
+                              written once                                        */
   double renorm_flops, renorm_ms;
   double op_bytes;         /* device bytes held by zeroth-order operator pools     */
   double tda_iter_ms;      /* wall time of the last TDA Davidson iteration         */
   double tda_sigma_flops;  /* algorithmic flops of that iteration                   */
   int tda_iters;
+  int sigma_main_launches; /* launches of the dominant kernel in the last sigma    */
 } dmrg_stats;
 
 int dmrg_get_stats(dmrg_ctx* ctx, dmrg_stats* out);

@@ -52,7 +52,8 @@ _SP = ctypes.POINTER(ctypes.c_size_t)
 class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in (
         "sigma_flops", "sigma_ms", "sigma_main_ms", "sigma_main_flops", "sigma_main_bytes",
-        "renorm_flops", "renorm_ms", "op_bytes", "tda_iter_ms", "tda_sigma_flops")] + [("tda_iters", ctypes.c_int)]
+        "renorm_flops", "renorm_ms", "op_bytes", "tda_iter_ms", "tda_sigma_flops")] + [
+        ("tda_iters", ctypes.c_int), ("sigma_main_launches", ctypes.c_int)]
 
 
 class SweepParams(ctypes.Structure):

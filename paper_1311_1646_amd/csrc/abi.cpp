@@ -157,8 +157,13 @@ int dmrg_renormalize(dmrg_ctx* ctx, int site, int dir, int order, int prec) {
   });
 }
 
-int dmrg_sweep_ground(dmrg_ctx* ctx, const dmrg_sweep_params*, double*, double*) {
-  return guard(ctx, [&](dmrg::Ctx&) { throw dmrg::Error(DMRG_ERR_STATE, "not available in this build"); });
+int dmrg_sweep_ground(dmrg_ctx* ctx, const dmrg_sweep_params* p, double* energy, double* discarded) {
+  return guard(ctx, [&](dmrg::Ctx& x) {
+    DMRG_REQUIRE(p && energy, DMRG_ERR_INVALID_ARG, "null arguments");
+    DMRG_REQUIRE(valid_prec(p->prec), DMRG_ERR_INVALID_ARG, "unsupported precision");
+    bool conv = true;
+    x.sweep_ground(*p, energy, discarded, &conv);
+  });
 }
 
 int dmrg_tda_roots(dmrg_ctx* ctx, int nroots, const dmrg_davidson_params* p, double* omega, double* e_total,

@@ -59,10 +59,13 @@ void upload(Ctx& x, DBuf& buf, const std::vector<T>& v) {
 }
 }  // namespace
 
-void GemmPlan::launch(Ctx& x, const Bases& b, int batch, int prec, bool out_f64, const Bases* bout) const {
+void GemmPlan::launch(Ctx& x, const Bases& b, int batch, int prec, bool out_f64, const Bases* bout,
+                      int role) const {
   if (ntiles == 0) return;
   if (prec == DMRG_FP64 && !x.fp64_mfma) {
+    if (role == 1) x.mark_main(true);
     launch_grouped_gemm_f64(tiles.as<GTile>(), ntiles, jobs.as<GJob>(), con.as<GContrib>(), b, batch, x.stream);
+    if (role == 1) x.mark_main(false);
     DMRG_HIP(hipGetLastError());
     return;
   }
@@ -88,8 +91,12 @@ void GemmPlan::launch(Ctx& x, const Bases& b, int batch, int prec, bool out_f64,
     x.ws_part.ensure(&x, size_t(F.nslots) * (fold == FOLD_NONE ? batch : 1) * 64 * 64 * esz);
     part = x.ws_part.p;
   }
-  launch_grouped_gemm(prec, out_f64, F.tiles.as<GTile>(), F.ntiles, jobs.as<GJob>(), con.as<GContrib>(),
-                      F.segs.as<GSeg>(), F.red.as<GRed>(), F.nred, F.nslots, part, b, bo, fold, batch, x.stream);
+  if (role == 1) x.mark_main(true);
+  launch_grouped_gemm(prec, out_f64, role, F.tiles.as<GTile>(), F.ntiles, jobs.as<GJob>(), con.as<GContrib>(),
+                      F.segs.as<GSeg>(), F.nslots, part, b, bo, fold, batch, x.stream);
+  if (role == 1) x.mark_main(false);
+  launch_reduce_partials(prec, out_f64, F.red.as<GRed>(), F.nred, jobs.as<GJob>(), F.nslots, part, bo, fold, batch,
+                         x.stream);
   DMRG_HIP(hipGetLastError());
 }
 
@@ -259,6 +266,7 @@ void make_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<st
     for (int a = 0; a < tm; ++a)
       for (int b = 0; b < tn; ++b) tiles.push_back({int(j), a, b, 0});
     P.shapes.push_back({jobs[j].m, jobs[j].n});
+    P.elems_c += double(jobs[j].m) * jobs[j].n;
     P.ranges.push_back({jobs[j].c0, jobs[j].c1});
     for (int c = jobs[j].c0; c < jobs[j].c1; ++c) P.con_k.push_back(con[c].k);
     P.mask_c |= 1u << jobs[j].baseC;
@@ -271,6 +279,15 @@ void make_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<st
       if (!(con[c].flags & GC_A_IDENTITY)) P.mask_a |= 1u << con[c].baseA;
       P.mask_b |= 1u << con[c].baseB;
     }
+  }
+  {
+    std::set<std::pair<int, long>> seen_a, seen_b;
+    for (size_t j = 0; j < jobs.size(); ++j)
+      for (int c = jobs[j].c0; c < jobs[j].c1; ++c) {
+        if (!(con[c].flags & GC_A_IDENTITY) && seen_a.insert({con[c].baseA, con[c].offA}).second)
+          P.elems_a += double(jobs[j].m) * con[c].k;
+        if (seen_b.insert({con[c].baseB, con[c].offB}).second) P.elems_b += double(con[c].k) * jobs[j].n;
+      }
   }
   upload(x, P.tiles, tiles);
   upload(x, P.jobs, jobs);
@@ -521,19 +538,44 @@ void Ctx::upload_lambda() {
   laminv_dev.clear();
   lam_dev.resize(L + 1);
   laminv_dev.resize(L + 1);
-  for (int b = 0; b <= L; ++b) {
-    std::vector<double> v, vi;
-    double mx = 0;
-    for (auto& s : lam[b])
-      for (double x : s) mx = std::max(mx, std::fabs(x));
-    for (auto& s : lam[b])
-      for (double x : s) {
-        v.push_back(x);
-        vi.push_back(std::fabs(x) > 1e-14 * mx ? 1.0 / x : 0.0);
-      }
-    upload(*this, lam_dev[b], v);
-    upload(*this, laminv_dev[b], vi);
-  }
+  for (int b = 0; b <= L; ++b) upload_lambda_bond(b);
+}
+
+void Ctx::upload_lambda_bond(int b) {
+  std::vector<double> v, vi;
+  double mx = 0;
+  for (auto& s : lam[b])
+    for (double x : s) mx = std::max(mx, std::fabs(x));
+  for (auto& s : lam[b])
+    for (double x : s) {
+      v.push_back(x);
+      vi.push_back(std::fabs(x) > 1e-14 * mx ? 1.0 / x : 0.0);
+    }
+  upload(*this, lam_dev[b], v);
+  upload(*this, laminv_dev[b], vi);
+}
+
+void Ctx::invalidate_bond(int b) {
+  auto touches = [b](int i, int w) { return b == i || b == i + w; };
+  for (auto it = sigma_plans_.begin(); it != sigma_plans_.end();)
+    it = touches(std::get<0>(it->first), std::get<1>(it->first)) ? sigma_plans_.erase(it) : std::next(it);
+  for (auto it = diag_plans_.begin(); it != diag_plans_.end();)
+    it = touches(it->first.first, it->first.second) ? diag_plans_.erase(it) : std::next(it);
+  for (auto it = renorm_plans_.begin(); it != renorm_plans_.end();)
+    it = touches(std::get<1>(it->first), 1) ? renorm_plans_.erase(it) : std::next(it);
+  for (auto it = layouts_.begin(); it != layouts_.end();)
+    it = touches(it->first.first, it->first.second) ? layouts_.erase(it) : std::next(it);
+  if (b < int(left.size())) left[b] = OpSet();
+  if (b < int(right.size())) right[b] = OpSet();
+  for (auto it = op_layouts_.begin(); it != op_layouts_.end();)
+    it = std::get<0>(it->first) == b ? op_layouts_.erase(it) : std::next(it);
+}
+
+void Ctx::set_bond(int b, Bond nb, std::vector<std::vector<double>> lam_b) {
+  invalidate_bond(b);
+  bonds[b] = std::move(nb);
+  lam[b] = std::move(lam_b);
+  if (int(lam_dev.size()) == L + 1) upload_lambda_bond(b);
 }
 
 void Ctx::export_mps(int* nsec_out, int* sectors_out, double* Ld, double* Rd, double* Cd, double* lam_out,
@@ -1169,9 +1211,7 @@ void Ctx::sigma_general(int i, int width, const OpSet& X, const OpSet& Z, const 
     P.form.launch(*this, b, dress_b ? batch : 1, 0);
     for (auto& ch : P.main.chunks) {
       ch.first.launch(*this, b, t_b ? batch : 1, 0);
-      mark_main(true);
-      ch.second.launch(*this, b, batch, 0);
-      mark_main(false);
+      ch.second.launch(*this, b, batch, 0, true, nullptr, 1);
     }
   } else {
     ensure_f32(X);
@@ -1187,13 +1227,18 @@ void Ctx::sigma_general(int i, int width, const OpSet& X, const OpSet& Z, const 
     P.form.launch(*this, b, dress_b ? batch : 1, prec);
     for (auto& ch : P.main.chunks) {
       ch.first.launch(*this, b, t_b ? batch : 1, prec, false, nullptr);
-      mark_main(true);
-      ch.second.launch(*this, b, batch, prec, true, &b);
-      mark_main(false);
+      ch.second.launch(*this, b, batch, prec, true, &b, 1);
     }
   }
   stats.sigma_flops = P.main.flops1 * (t_b ? batch : 1) + P.main.flops2 * batch;
   stats.sigma_main_flops = P.main.flops2 * batch;
+  // stage-2 operand bytes: operators once, products and results per entry
+  double by = 0;
+  for (auto& ch : P.main.chunks) {
+    const GemmPlan& G = ch.second;
+    by += G.elems_a * esz * (dress_b ? batch : 1) + G.elems_b * esz * batch + G.elems_c * 8.0 * batch * 2;
+  }
+  stats.sigma_main_bytes = by;
 }
 
 void Ctx::sigma(int i, int width, int nvec, const double* Cin, double* Sout, int prec) {
@@ -1229,6 +1274,7 @@ void Ctx::sigma(int i, int width, int nvec, const double* Cin, double* Sout, int
     main_ms += d;
   }
   stats.sigma_main_ms = main_ms;
+  stats.sigma_main_launches = main_events_used_ / 2;
 }
 
 void Ctx::mark_main(bool begin) {

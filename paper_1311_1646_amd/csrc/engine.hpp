@@ -87,6 +87,9 @@ struct GemmPlan {
   std::vector<int> con_k;                   // inner length per contribution
   unsigned mask_a = 0, mask_b = 0, mask_c = 0;
   long ncon = 0, kchunks = 0, kchunks_max = 0;  // plan statistics (K-chunks of 32)
+  // algorithmic operand elements: distinct A blocks, distinct B blocks, and
+  // output elements (each read once, outputs written once) per batch entry
+  double elems_a = 0, elems_b = 0, elems_c = 0;
   // launch lists per (fold, batch): tiles with split contribution lists and
   // the reductions of their partial sums
   struct FoldTiles {
@@ -97,8 +100,10 @@ struct GemmPlan {
   const FoldTiles& fold_lists(Ctx& x, int fold, int batch) const;
   // prec: DMRG_FP64 (FP64 MFMA), DMRG_FP32 or DMRG_BF16X3 (FP32 operands);
   // outputs go through bout when given (FP64 outputs of a lower-precision run)
+  // role 1 marks the accumulation stage (the dominant kernel of a sigma):
+  // its main kernel is bracketed by the timing events of a timed sigma
   void launch(Ctx& x, const Bases& b, int batch, int prec = 0, bool out_f64 = true,
-              const Bases* bout = nullptr) const;
+              const Bases* bout = nullptr, int role = 0) const;
 };
 
 void build_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<std::vector<GContrib>>& per);
@@ -217,6 +222,13 @@ class Ctx {
   void diag(int i, int width, double* out);
   void tda_roots(int nroots, const dmrg_davidson_params& p, double* omega, double* etot, double* resid2,
                  int* iters, bool* converged);
+  // ground state by two-site sweeps (ground.cpp); returns <Psi|H|Psi>
+  void sweep_ground(const dmrg_sweep_params& p, double* energy, double* discarded, bool* converged);
+  // replace the sectors of bond b (and its Schmidt values); drops every
+  // cached layout, plan and operator set that depends on bond b
+  void set_bond(int b, Bond nb, std::vector<std::vector<double>> lam_b);
+  void invalidate_bond(int b);
+  void upload_lambda_bond(int b);
 
  private:
   std::map<std::pair<int, int>, std::unique_ptr<SiteLayout>> layouts_;

@@ -420,6 +420,25 @@ void launch_lincomb_grouped(int prec, const LCGroup* g, int ngroups, const LCTar
   }
 }
 
+__global__ void copy2d_kernel(const Copy2D* __restrict__ jobs) {
+  const Copy2D J = jobs[blockIdx.y];
+  const long n = long(J.rows) * J.cols;
+  for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += long(gridDim.x) * blockDim.x) {
+    const long r = e / J.cols, c = e % J.cols;
+    double v = J.src[r * J.ss_r + c * J.ss_c];
+    if (J.mode == 1) v *= J.scale[r];
+    else if (J.mode == 2) v *= J.scale[c];
+    J.dst[r * J.ds_r + c * J.ds_c] = v;
+  }
+}
+
+void launch_copy2d_f64(const Copy2D* jobs, int njobs, hipStream_t s) {
+  for (int j0 = 0; j0 < njobs; j0 += 65535) {
+    const int nj = njobs - j0 < 65535 ? njobs - j0 : 65535;
+    hipLaunchKernelGGL(copy2d_kernel, dim3(64, nj), dim3(256), 0, s, jobs + j0);
+  }
+}
+
 void launch_lincomb_f64(const LCTarget* t, int ntargets, const LCSource* src, long max_size, const Bases& b,
                         int batch, hipStream_t s) {
   if (ntargets <= 0 || max_size <= 0 || batch <= 0) return;

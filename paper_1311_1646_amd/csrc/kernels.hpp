@@ -75,6 +75,18 @@ struct LCGroup {
 void launch_lincomb_grouped(int prec, const LCGroup* g, int ngroups, const LCTarget* t, const LCSource* u,
                             const double* coef, long max_size, const Bases& b, int batch, hipStream_t s);
 
+// Strided 2-D copies dst(r, c) = src(r, c) * scale, element (r, c) at
+// r*ss_r + c*ss_c in the source and r*ds_r + c*ds_c in the destination;
+// mode 0: no scale, 1: scale[r], 2: scale[c].  Jobs are independent.
+struct Copy2D {
+  const double* src;
+  double* dst;
+  long ss_r, ss_c, ds_r, ds_c;
+  const double* scale;
+  int rows, cols, mode, pad;
+};
+void launch_copy2d_f64(const Copy2D* jobs, int njobs, hipStream_t s);
+
 // out[off + i*(dim+1)] += c for i < dim (identity added to a diagonal block)
 struct DiagAdd {
   long off;

@@ -292,7 +292,9 @@ __device__ __forceinline__ void write_partial(const Acc<MODE>& acc, PT* P, int w
     P[(wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * TN + wn + (lane & 31)] = PT(acc.c[r]);
 }
 
-template <int MODE>
+// ROLE only tags the instantiation (0: products into a workspace, 1: the
+// accumulation into the result), so that profiles separate the two stages.
+template <int MODE, int ROLE>
 __global__ __launch_bounds__(NTH) void ggemm_mfma_kernel(const GTile* __restrict__ tiles,
                                                          const GJob* __restrict__ jobs,
                                                          const GContrib* __restrict__ con,
@@ -406,32 +408,41 @@ __global__ void convert_f64_f32_kernel(const double* __restrict__ in, float* __r
 
 }  // namespace
 
-void launch_grouped_gemm(int prec, bool out_f64, const GTile* tiles, int ntiles, const GJob* jobs, const GContrib* con,
-                         const GSeg* segs, const GRed* red, int nred, int nslots, void* partial, const Bases& b,
+template <int MODE>
+void launch_mode(int role, dim3 grid, hipStream_t s, const GTile* tiles, const GJob* jobs, const GContrib* con,
+                 const GSeg* segs, int nslots, void* partial, const Bases& b, const Bases& bout, int fold, int batch,
+                 int of) {
+  typedef typename Cfg<MODE>::T T;
+  T* P = static_cast<T*>(partial);
+  if (role == 0)
+    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 0>), grid, dim3(NTH), 0, s, tiles, jobs, con, segs, nslots, P, b, bout,
+                       fold, batch, of);
+  else
+    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 1>), grid, dim3(NTH), 0, s, tiles, jobs, con, segs, nslots, P, b, bout,
+                       fold, batch, of);
+}
+
+void launch_grouped_gemm(int prec, bool out_f64, int role, const GTile* tiles, int ntiles, const GJob* jobs,
+                         const GContrib* con, const GSeg* segs, int nslots, void* partial, const Bases& b,
                          const Bases& bout, int fold, int batch, hipStream_t s) {
   if (ntiles <= 0 || batch <= 0) return;
-  const int gy = fold == 0 ? batch : 1;
-  const dim3 grid(ntiles, gy), block(NTH);
-  const int of = out_f64 ? 1 : 0;
-  if (prec == 0) {
-    double* P = static_cast<double*>(partial);
-    hipLaunchKernelGGL(ggemm_mfma_kernel<0>, grid, block, 0, s, tiles, jobs, con, segs, nslots, P, b, bout, fold,
-                       batch, 1);
-    if (nred > 0)
-      hipLaunchKernelGGL(reduce_partials_kernel<double>, dim3(nred, gy), block, 0, s, red, jobs, P, nslots, bout,
-                         fold, batch, 1);
-  } else {
-    float* P = static_cast<float*>(partial);
-    if (prec == 1)
-      hipLaunchKernelGGL(ggemm_mfma_kernel<1>, grid, block, 0, s, tiles, jobs, con, segs, nslots, P, b, bout, fold,
-                         batch, of);
-    else
-      hipLaunchKernelGGL(ggemm_mfma_kernel<2>, grid, block, 0, s, tiles, jobs, con, segs, nslots, P, b, bout, fold,
-                         batch, of);
-    if (nred > 0)
-      hipLaunchKernelGGL(reduce_partials_kernel<float>, dim3(nred, gy), block, 0, s, red, jobs, P, nslots, bout, fold,
-                         batch, of);
-  }
+  const dim3 grid(ntiles, fold == 0 ? batch : 1);
+  if (prec == 0) launch_mode<0>(role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold, batch, 1);
+  else if (prec == 1)
+    launch_mode<1>(role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold, batch, out_f64 ? 1 : 0);
+  else launch_mode<2>(role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold, batch, out_f64 ? 1 : 0);
+}
+
+void launch_reduce_partials(int prec, bool out_f64, const GRed* red, int nred, const GJob* jobs, int nslots,
+                            const void* partial, const Bases& bout, int fold, int batch, hipStream_t s) {
+  if (nred <= 0 || batch <= 0) return;
+  const dim3 grid(nred, fold == 0 ? batch : 1);
+  if (prec == 0)
+    hipLaunchKernelGGL(reduce_partials_kernel<double>, grid, dim3(NTH), 0, s, red, jobs,
+                       static_cast<const double*>(partial), nslots, bout, fold, batch, 1);
+  else
+    hipLaunchKernelGGL(reduce_partials_kernel<float>, grid, dim3(NTH), 0, s, red, jobs,
+                       static_cast<const float*>(partial), nslots, bout, fold, batch, out_f64 ? 1 : 0);
 }
 
 void launch_lincomb_f32(const LCTarget* t, int ntargets, const LCSource* src, long max_size, const Bases& b, int batch,

@@ -26,9 +26,13 @@ struct GSeg {
 struct GRed {
   int job, tm, tn, slot0, nseg, pad;
 };
-void launch_grouped_gemm(int prec, bool out_f64, const GTile* tiles, int ntiles, const GJob* jobs,
-                         const GContrib* con, const GSeg* segs, const GRed* red, int nred, int nslots,
-                         void* partial, const Bases& b, const Bases& bout, int fold, int batch, hipStream_t s);
+// role 0: products into a workspace, 1: accumulation into the result (the
+// two instantiations are the same code; the tag separates them in profiles)
+void launch_grouped_gemm(int prec, bool out_f64, int role, const GTile* tiles, int ntiles, const GJob* jobs,
+                         const GContrib* con, const GSeg* segs, int nslots, void* partial, const Bases& b,
+                         const Bases& bout, int fold, int batch, hipStream_t s);
+void launch_reduce_partials(int prec, bool out_f64, const GRed* red, int nred, const GJob* jobs, int nslots,
+                            const void* partial, const Bases& bout, int fold, int batch, hipStream_t s);
 
 void launch_lincomb_f32(const LCTarget* t, int ntargets, const LCSource* src, long max_size, const Bases& b,
                         int batch, hipStream_t s);

@@ -525,7 +525,10 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
       break;
     }
     lcur = l;
-    m = (l + n_ <= Nmax_) ? l : n_;
+    // thick restart: when the space is full keep, besides the n wanted Ritz
+    // vectors, up to n/2 (at least 2) of the next ones, so that a root close
+    // to the edge of the window keeps its neighbour
+    m = (l + n_ <= Nmax_) ? l : std::min(l, std::min(Nmax_ - n_, n_ + std::max(2, n_ / 2)));
   }
   for (int v = 0; v < n_; ++v) {
     etot[v] = last_w[v];
