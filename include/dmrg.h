@@ -118,7 +118,10 @@ int dmrg_get_layout(dmrg_ctx* ctx, int site, int width, int* nblocks_out, int* b
 /* Build the zeroth-order renormalized block operators H_0^{L_b} and
  * H_0^{R_b} (normal and complementary) at every bond from the imported MPS
  * (Sec. III B: the operators "known from the ground-state DMRG").
- * prec selects the storage/compute precision of the operator pools. */
+ * prec is the arithmetic of the renormalization contractions (FP64, FP32;
+ * BF16X3 builds these pools in FP32 because their errors compound over the
+ * bonds).  Pools are stored in FP64; FP32 copies are made on first use by a
+ * lower-precision sigma.  Errors: STATE without an MPS, INVALID_ARG. */
 int dmrg_build_ops(dmrg_ctx* ctx, int prec);
 
 /* Sigma vectors: sigma = H_eff C for nvec vectors (Sec. II A eq. dmrg and
@@ -142,7 +145,8 @@ int dmrg_renormalize(dmrg_ctx* ctx, int site, int dir, int order, int prec);
 typedef struct {
   int nsweeps;            /* two-site sweeps (left->right->left counts 1)  */
   const int* M_schedule;  /* bond dimension per sweep (nsweeps entries)    */
-  const double* noise;    /* density-matrix noise per sweep (may be NULL)  */
+  const double* noise;    /* reserved, not applied (may be NULL): the two-
+                             site update reaches new sectors by itself     */
   double davidson_tol;    /* residual norm^2 threshold of the local solver */
   int davidson_max_iter;  /* per site                                      */
   int seed;               /* initial state                                 */
@@ -153,9 +157,15 @@ typedef struct {
 /* Ground state by two-site sweeps with Davidson (Sec. II A, eq. dmrg and
  * eq. gauge-shift), followed by one non-truncating one-site pass that leaves
  * a consistent mixed-canonical MPS (L_i, C_i, R_i, Lambda_i at every site)
- * and its zeroth-order operators for dmrg_tda_roots.
- * energy receives <Psi|H|Psi> of the final MPS; discarded the largest
- * discarded weight of the last sweep.  NOT_CONVERGED still leaves a state. */
+ * and its zeroth-order operators (built in FP64) for dmrg_tda_roots.
+ * Starts from the imported MPS if there is one, else from a random MPS
+ * (seed) with sector dimensions min(exact, M_schedule[0] / #sectors).
+ * Each two-site step keeps at most M states over all sectors of the split
+ * bond (singular values below 1e-12 of the largest are dropped).  prec is
+ * the arithmetic of the sigma and renormalization contractions; Davidson,
+ * SVD and the final energy are FP64.  energy receives <Psi|H|Psi> of the
+ * final MPS; discarded the largest discarded weight of the last sweep.
+ * Errors: INVALID_ARG (schedule), NOT_CONVERGED (an SVD failed). */
 int dmrg_sweep_ground(dmrg_ctx* ctx, const dmrg_sweep_params* p, double* energy,
                       double* discarded);
 

@@ -82,44 +82,97 @@ struct Stage {
   static constexpr int TK = Cfg<MODE>::TK;
   static constexpr int PER = TM * TK / NTH;  // elements per thread and operand
   T ra[PER], rb[PER];
+  // Per-contribution staging state.  A thread stages fixed (row, k-lane)
+  // positions of every chunk, so the row / column base addresses of its
+  // elements are resolved once per contribution (batch entry, block index,
+  // leading dimension) and a chunk only adds its k offset.
+  //   op(A) not transposed: rows tid/TK + q*(NTH/TK), k lane tid%TK -> pa[q]
+  //   op(A) transposed:     row tid%TM, k lanes tid/TM + q*(NTH/TM) -> pa1
+  //   identity A:           ia[q] = block row of element q (or -1)
+  //   op(B) not transposed: column tid%TN, k lanes tid/TN + q*(NTH/TN) -> pb1
+  //   op(B) transposed:     columns tid/TK + q*(NTH/TK), k lane tid%TK -> pb[q]
+  const T* pa[PER];
+  const T* pb[PER];
+  const T* pa1;
+  const T* pb1;
+  int ia[PER];
+  long lda, ldb;
+  int ck, flags;
+  T alpha;
 
-  // Fetch op(A) rows x K-chunk and K-chunk x op(B) columns of contribution c.
-  __device__ __forceinline__ void load(const GContrib& c, const Bases& bs, const TileMap& rm, const TileMap& cm,
-                                       int k0, int tid) {
+  __device__ __forceinline__ void begin(const GContrib& c, const Bases& bs, const TileMap& rm, const TileMap& cm,
+                                        int tid) {
+    flags = c.flags;
+    ck = c.k;
+    lda = c.lda;
+    ldb = c.ldb;
+    alpha = T(c.alpha);
     const bool ta = c.flags & GC_TRANS_A, tb = c.flags & GC_TRANS_B, aid = c.flags & GC_A_IDENTITY;
-    const T alpha = T(c.alpha);
-    const T* A = aid ? nullptr : reinterpret_cast<const T*>(bs.p[c.baseA]) + c.offA;
-    const T* B = reinterpret_cast<const T*>(bs.p[c.baseB]) + c.offB;
-    const long sa = aid ? 0 : bs.stride[c.baseA], sb = bs.stride[c.baseB];
+    pa1 = pb1 = nullptr;
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = tid + q * NTH;
-      int i, k;
-      if (ta) { k = e / TM; i = e % TM; } else { i = e / TK; k = e % TK; }
-      const int ii = rm.idx[i], gk = k0 + k;
-      T val = T(0);
-      if (ii >= 0 && gk < c.k) {
-        if (aid) {
-          val = ii == gk ? alpha : T(0);
-        } else {
-          const T* Av = A + long(rm.v[i]) * sa;
-          val = (ta ? Av[long(gk) * c.lda + ii] : Av[long(ii) * c.lda + gk]) * alpha;
-        }
-      }
-      ra[q] = val;
+      pa[q] = pb[q] = nullptr;
+      ia[q] = -1;
     }
+    if (aid) {
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = tid + q * NTH;
-      int j, k;
-      if (tb) { j = e / TK; k = e % TK; } else { k = e / TN; j = e % TN; }
-      const int jj = cm.idx[j], gk = k0 + k;
-      T val = T(0);
-      if (jj >= 0 && gk < c.k) {
-        const T* Bv = B + long(cm.v[j]) * sb;
-        val = tb ? Bv[long(jj) * c.ldb + gk] : Bv[long(gk) * c.ldb + jj];
+      for (int q = 0; q < PER; ++q) ia[q] = rm.idx[tid / TK + q * (NTH / TK)];
+    } else {
+      const T* A = reinterpret_cast<const T*>(bs.p[c.baseA]) + c.offA;
+      const long sa = bs.stride[c.baseA];
+      if (!ta) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+          const int i = tid / TK + q * (NTH / TK), ii = rm.idx[i];
+          pa[q] = ii < 0 ? nullptr : A + long(rm.v[i]) * sa + long(ii) * c.lda + tid % TK;
+        }
+      } else {
+        const int i = tid % TM, ii = rm.idx[i];
+        pa1 = ii < 0 ? nullptr : A + long(rm.v[i]) * sa + ii;
       }
-      rb[q] = val;
+    }
+    const T* B = reinterpret_cast<const T*>(bs.p[c.baseB]) + c.offB;
+    const long sb = bs.stride[c.baseB];
+    if (!tb) {
+      const int j = tid % TN, jj = cm.idx[j];
+      pb1 = jj < 0 ? nullptr : B + long(cm.v[j]) * sb + jj;
+    } else {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int j = tid / TK + q * (NTH / TK), jj = cm.idx[j];
+        pb[q] = jj < 0 ? nullptr : B + long(cm.v[j]) * sb + long(jj) * c.ldb + tid % TK;
+      }
+    }
+  }
+
+  // Fetch the K-chunk starting at k0 of the current contribution.
+  __device__ __forceinline__ void load(int k0, int tid) {
+    const bool ta = flags & GC_TRANS_A, tb = flags & GC_TRANS_B, aid = flags & GC_A_IDENTITY;
+    if (aid) {
+      const int k = k0 + tid % TK;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) ra[q] = (ia[q] >= 0 && ia[q] == k && k < ck) ? alpha : T(0);
+    } else if (!ta) {
+      const int k = k0 + tid % TK;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) ra[q] = (pa[q] && k < ck) ? pa[q][k0] * alpha : T(0);
+    } else {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int k = k0 + tid / TM + q * (NTH / TM);
+        ra[q] = (pa1 && k < ck) ? pa1[long(k) * lda] * alpha : T(0);
+      }
+    }
+    if (!tb) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int k = k0 + tid / TN + q * (NTH / TN);
+        rb[q] = (pb1 && k < ck) ? pb1[long(k) * ldb] : T(0);
+      }
+    } else {
+      const int k = k0 + tid % TK;
+#pragma unroll
+      for (int q = 0; q < PER; ++q) rb[q] = (pb[q] && k < ck) ? pb[q][k0] : T(0);
     }
   }
 
@@ -303,6 +356,7 @@ __global__ __launch_bounds__(NTH) void ggemm_mfma_kernel(const GTile* __restrict
                                                          Bases bout, int fold, int batch, int out_f64) {
   __shared__ Lds<MODE> s;
   __shared__ TileMap rm, cm;
+  __shared__ Bases sb;  // base table indexed per contribution (LDS, not a private copy)
   constexpr int TK = Cfg<MODE>::TK;
   const GTile t = tiles[blockIdx.x];
   const GJob J = jobs[t.job];
@@ -316,34 +370,37 @@ __global__ __launch_bounds__(NTH) void ggemm_mfma_kernel(const GTile* __restrict
     slot = g.slot;
   }
   tile_maps(rm, cm, J, t.tm, t.tn, fold, batch, tid);
+  if (tid >= TM + TN && tid < TM + TN + kMaxBases) {
+    sb.p[tid - TM - TN] = bs.p[tid - TM - TN];
+    sb.stride[tid - TM - TN] = bs.stride[tid - TM - TN];
+  }
   __syncthreads();
   Acc<MODE> acc;
   acc.zero();
   if (c0 < c1) {
     Stage<MODE> st;
     int ci = c0, k0 = 0, buf = 0;
-    GContrib c = con[ci];
-    st.load(c, bs, rm, cm, 0, tid);
+    st.begin(con[ci], sb, rm, cm, tid);
+    st.load(0, tid);
     for (;;) {
-      st.store(s, buf, c.flags & GC_TRANS_A, c.flags & GC_TRANS_B, tid);
+      const int ck = st.ck, fl = st.flags;
+      st.store(s, buf, fl & GC_TRANS_A, fl & GC_TRANS_B, tid);
       __syncthreads();
-      const int kv = c.k - k0 < TK ? c.k - k0 : TK;
+      const int kv = ck - k0 < TK ? ck - k0 : TK;
       int nci = ci, nk0 = k0 + TK;
-      if (nk0 >= c.k) {
+      if (nk0 >= ck) {
         ++nci;
         nk0 = 0;
       }
       const bool more = nci < c1;
-      GContrib nc = c;
       if (more) {
-        nc = con[nci];
-        st.load(nc, bs, rm, cm, nk0, tid);
+        if (nci != ci) st.begin(con[nci], sb, rm, cm, tid);
+        st.load(nk0, tid);
       }
       mma(acc, s, buf, kv, wm, wn, lane);
       if (!more) break;
       ci = nci;
       k0 = nk0;
-      c = nc;
       buf ^= 1;
     }
   }
