@@ -81,21 +81,23 @@ struct Stage {
   typedef typename Cfg<MODE>::T T;
   static constexpr int TK = Cfg<MODE>::TK;
   static constexpr int PER = TM * TK / NTH;  // elements per thread and operand
+  static constexpr int RUNS = PER / 4;       // runs of 4 elements contiguous in memory
   T ra[PER], rb[PER];
-  // Per-contribution staging state.  A thread stages fixed (row, k-lane)
-  // positions of every chunk, so the row / column base addresses of its
-  // elements are resolved once per contribution (batch entry, block index,
-  // leading dimension) and a chunk only adds its k offset.
-  //   op(A) not transposed: rows tid/TK + q*(NTH/TK), k lane tid%TK -> pa[q]
-  //   op(A) transposed:     row tid%TM, k lanes tid/TM + q*(NTH/TM) -> pa1
-  //   identity A:           ia[q] = block row of element q (or -1)
-  //   op(B) not transposed: column tid%TN, k lanes tid/TN + q*(NTH/TN) -> pb1
-  //   op(B) transposed:     columns tid/TK + q*(NTH/TK), k lane tid%TK -> pb[q]
+  // Each thread stages RUNS runs of four elements that are contiguous in
+  // memory (run r = tid + r*NTH), so one address and one bounds test serve
+  // four loads.  The addresses are resolved once per contribution:
+  //   op(A) not transposed (contiguous in k): row r/(TK/4), k 4*(r%(TK/4))+e
+  //       -> pa[r] points at (row, k) of the run
+  //   op(A) transposed (contiguous in rows): k r/(TM/4), rows 4*(r%(TM/4))+e
+  //       -> pa[4r+e] points at each row
+  //   op(B) not transposed (contiguous in columns): k r/(TN/4), cols 4*(r%(TN/4))+e
+  //       -> pb[4r+e] points at each column
+  //   op(B) transposed (contiguous in k): column r/(TK/4), k 4*(r%(TK/4))+e
+  //       -> pb[r] points at (column, k) of the run
+  //   identity A: ia[r] = block row of the run (or -1)
   const T* pa[PER];
   const T* pb[PER];
-  const T* pa1;
-  const T* pb1;
-  int ia[PER];
+  int ia[RUNS];
   long lda, ldb;
   int ck, flags;
   T alpha;
@@ -108,40 +110,64 @@ struct Stage {
     ldb = c.ldb;
     alpha = T(c.alpha);
     const bool ta = c.flags & GC_TRANS_A, tb = c.flags & GC_TRANS_B, aid = c.flags & GC_A_IDENTITY;
-    pa1 = pb1 = nullptr;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      pa[q] = pb[q] = nullptr;
-      ia[q] = -1;
-    }
+    for (int q = 0; q < PER; ++q) pa[q] = pb[q] = nullptr;
+#pragma unroll
+    for (int r = 0; r < RUNS; ++r) ia[r] = -1;
     if (aid) {
 #pragma unroll
-      for (int q = 0; q < PER; ++q) ia[q] = rm.idx[tid / TK + q * (NTH / TK)];
+      for (int r = 0; r < RUNS; ++r) ia[r] = rm.idx[(tid + r * NTH) / (TK / 4)];
     } else {
       const T* A = reinterpret_cast<const T*>(bs.p[c.baseA]) + c.offA;
       const long sa = bs.stride[c.baseA];
       if (!ta) {
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-          const int i = tid / TK + q * (NTH / TK), ii = rm.idx[i];
-          pa[q] = ii < 0 ? nullptr : A + long(rm.v[i]) * sa + long(ii) * c.lda + tid % TK;
+        for (int r = 0; r < RUNS; ++r) {
+          const int run = tid + r * NTH, i = run / (TK / 4), ii = rm.idx[i];
+          pa[r] = ii < 0 ? nullptr : A + long(rm.v[i]) * sa + long(ii) * c.lda + 4 * (run % (TK / 4));
         }
       } else {
-        const int i = tid % TM, ii = rm.idx[i];
-        pa1 = ii < 0 ? nullptr : A + long(rm.v[i]) * sa + ii;
+#pragma unroll
+        for (int r = 0; r < RUNS; ++r) {
+          const int run = tid + r * NTH;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int i = 4 * (run % (TM / 4)) + e, ii = rm.idx[i];
+            pa[4 * r + e] = ii < 0 ? nullptr : A + long(rm.v[i]) * sa + ii;
+          }
+        }
       }
     }
     const T* B = reinterpret_cast<const T*>(bs.p[c.baseB]) + c.offB;
     const long sb = bs.stride[c.baseB];
     if (!tb) {
-      const int j = tid % TN, jj = cm.idx[j];
-      pb1 = jj < 0 ? nullptr : B + long(cm.v[j]) * sb + jj;
+#pragma unroll
+      for (int r = 0; r < RUNS; ++r) {
+        const int run = tid + r * NTH;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int j = 4 * (run % (TN / 4)) + e, jj = cm.idx[j];
+          pb[4 * r + e] = jj < 0 ? nullptr : B + long(cm.v[j]) * sb + jj;
+        }
+      }
     } else {
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int j = tid / TK + q * (NTH / TK), jj = cm.idx[j];
-        pb[q] = jj < 0 ? nullptr : B + long(cm.v[j]) * sb + long(jj) * c.ldb + tid % TK;
+      for (int r = 0; r < RUNS; ++r) {
+        const int run = tid + r * NTH, j = run / (TK / 4), jj = cm.idx[j];
+        pb[r] = jj < 0 ? nullptr : B + long(cm.v[j]) * sb + long(jj) * c.ldb + 4 * (run % (TK / 4));
       }
+    }
+  }
+
+  // Four contiguous elements starting at p (k indices k..k+3 checked
+  // against the contribution's inner length).
+  __device__ __forceinline__ void run4(T* dst, const T* p, int k, T scale) const {
+    if (p && k + 3 < ck) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) dst[e] = p[e] * scale;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) dst[e] = (p && k + e < ck) ? p[e] * scale : T(0);
     }
   }
 
@@ -149,47 +175,55 @@ struct Stage {
   __device__ __forceinline__ void load(int k0, int tid) {
     const bool ta = flags & GC_TRANS_A, tb = flags & GC_TRANS_B, aid = flags & GC_A_IDENTITY;
     if (aid) {
-      const int k = k0 + tid % TK;
 #pragma unroll
-      for (int q = 0; q < PER; ++q) ra[q] = (ia[q] >= 0 && ia[q] == k && k < ck) ? alpha : T(0);
+      for (int r = 0; r < RUNS; ++r) {
+        const int k = k0 + 4 * ((tid + r * NTH) % (TK / 4));
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ra[4 * r + e] = (ia[r] >= 0 && ia[r] == k + e && k + e < ck) ? alpha : T(0);
+      }
     } else if (!ta) {
-      const int k = k0 + tid % TK;
 #pragma unroll
-      for (int q = 0; q < PER; ++q) ra[q] = (pa[q] && k < ck) ? pa[q][k0] * alpha : T(0);
+      for (int r = 0; r < RUNS; ++r) {
+        const int k = k0 + 4 * ((tid + r * NTH) % (TK / 4));
+        run4(ra + 4 * r, pa[r] ? pa[r] + k0 : nullptr, k, alpha);
+      }
     } else {
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int k = k0 + tid / TM + q * (NTH / TM);
-        ra[q] = (pa1 && k < ck) ? pa1[long(k) * lda] * alpha : T(0);
+      for (int r = 0; r < RUNS; ++r) {
+        const int k = k0 + (tid + r * NTH) / (TM / 4);
+        const long off = long(k) * lda;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ra[4 * r + e] = (pa[4 * r + e] && k < ck) ? pa[4 * r + e][off] * alpha : T(0);
       }
     }
     if (!tb) {
 #pragma unroll
-      for (int q = 0; q < PER; ++q) {
-        const int k = k0 + tid / TN + q * (NTH / TN);
-        rb[q] = (pb1 && k < ck) ? pb1[long(k) * ldb] : T(0);
+      for (int r = 0; r < RUNS; ++r) {
+        const int k = k0 + (tid + r * NTH) / (TN / 4);
+        const long off = long(k) * ldb;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) rb[4 * r + e] = (pb[4 * r + e] && k < ck) ? pb[4 * r + e][off] : T(0);
       }
     } else {
-      const int k = k0 + tid % TK;
 #pragma unroll
-      for (int q = 0; q < PER; ++q) rb[q] = (pb[q] && k < ck) ? pb[q][k0] : T(0);
+      for (int r = 0; r < RUNS; ++r) {
+        const int k = k0 + 4 * ((tid + r * NTH) % (TK / 4));
+        run4(rb + 4 * r, pb[r] ? pb[r] + k0 : nullptr, k, T(1));
+      }
     }
   }
 
   __device__ __forceinline__ void store(Lds<MODE>& s, int buf, bool ta, bool tb, int tid) const {
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = tid + q * NTH;
-      int i, k;
-      if (ta) { k = e / TM; i = e % TM; } else { i = e / TK; k = e % TK; }
-      put_a(s, buf, i, k, ra[q]);
-    }
+    for (int r = 0; r < RUNS; ++r) {
+      const int run = tid + r * NTH;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = tid + q * NTH;
-      int j, k;
-      if (tb) { j = e / TK; k = e % TK; } else { k = e / TN; j = e % TN; }
-      put_b(s, buf, j, k, rb[q]);
+      for (int e = 0; e < 4; ++e) {
+        if (ta) put_a(s, buf, 4 * (run % (TM / 4)) + e, run / (TM / 4), ra[4 * r + e]);
+        else put_a(s, buf, run / (TK / 4), 4 * (run % (TK / 4)) + e, ra[4 * r + e]);
+        if (tb) put_b(s, buf, run / (TK / 4), 4 * (run % (TK / 4)) + e, rb[4 * r + e]);
+        else put_b(s, buf, 4 * (run % (TN / 4)) + e, run / (TN / 4), rb[4 * r + e]);
+      }
     }
   }
 
