@@ -88,15 +88,16 @@ void GemmPlan::launch(Ctx& x, const Bases& b, int batch, int prec, bool out_f64,
   void* part = nullptr;
   if (F.nslots > 0) {
     const size_t esz = prec == DMRG_FP64 ? 8 : 4;
-    x.ws_part.ensure(&x, size_t(F.nslots) * (fold == FOLD_NONE ? batch : 1) * 64 * 64 * esz);
+    const size_t tile = size_t(tile_rows(F.shape)) * tile_cols(F.shape);
+    x.ws_part.ensure(&x, size_t(F.nslots) * (fold == FOLD_NONE ? batch : 1) * tile * esz);
     part = x.ws_part.p;
   }
   if (role == 1) x.mark_main(true);
-  launch_grouped_gemm(prec, out_f64, role, F.tiles.as<GTile>(), F.ntiles, jobs.as<GJob>(), con.as<GContrib>(),
-                      F.segs.as<GSeg>(), F.nslots, part, b, bo, fold, batch, x.stream);
+  launch_grouped_gemm(prec, out_f64, role, F.shape, F.tiles.as<GTile>(), F.ntiles, jobs.as<GJob>(),
+                      con.as<GContrib>(), F.segs.as<GSeg>(), F.nslots, part, b, bo, fold, batch, x.stream);
   if (role == 1) x.mark_main(false);
-  launch_reduce_partials(prec, out_f64, F.red.as<GRed>(), F.nred, jobs.as<GJob>(), F.nslots, part, bo, fold, batch,
-                         x.stream);
+  launch_reduce_partials(prec, out_f64, F.shape, F.red.as<GRed>(), F.nred, jobs.as<GJob>(), F.nslots, part, bo, fold,
+                         batch, x.stream);
   DMRG_HIP(hipGetLastError());
 }
 
@@ -110,15 +111,49 @@ const GemmPlan::FoldTiles& GemmPlan::fold_lists(Ctx& x, int fold, int batch) con
   if (F.ntiles > 0) return F;
   const long entries = fold == FOLD_NONE ? batch : 1;
   std::vector<long> tiles_of(shapes.size()), work_of(shapes.size());
+  for (size_t j = 0; j < shapes.size(); ++j) {
+    long w = 0;
+    for (int c = ranges[j].first; c < ranges[j].second; ++c) w += (con_k[c] + 31) / 32;
+    work_of[j] = w;
+  }
+  // Tile shape: 128 along the unfolded (block) dimension only when it pads
+  // much less than 64-wide tiles (the wider tiles hold more LDS and
+  // registers, so fewer workgroups are resident; measured slower at equal
+  // padding).
+  auto padded = [&](int sh) {
+    const long tr = tile_rows(sh), tc = tile_cols(sh);
+    double w = 0;
+    for (size_t j = 0; j < shapes.size(); ++j) {
+      const long m = fold == FOLD_M ? long(shapes[j].first) * batch : shapes[j].first;
+      const long n = fold == FOLD_N ? long(shapes[j].second) * batch : shapes[j].second;
+      w += double((m + tr - 1) / tr * tr) * double((n + tc - 1) / tc * tc) * double(work_of[j]);
+    }
+    return sh == TILE_64x64 ? w : 1.5 * w;  // the wider tiles run at lower occupancy
+  };
+  int shape = TILE_64x64;
+  double best = padded(TILE_64x64);
+  for (int sh : {TILE_128x64, TILE_64x128}) {
+    if ((fold == FOLD_N && sh == TILE_64x128) || (fold == FOLD_M && sh == TILE_128x64)) continue;
+    const double c = padded(sh);
+    if (c < best) {
+      best = c;
+      shape = sh;
+    }
+  }
+  // DMRG_TILE_SHAPE=64x64|128x64|64x128 fixes the shape where the fold allows it
+  if (const char* e = std::getenv("DMRG_TILE_SHAPE")) {
+    const std::string v(e);
+    const int want = v == "128x64" ? TILE_128x64 : v == "64x128" ? TILE_64x128 : TILE_64x64;
+    if (!((fold == FOLD_N && want == TILE_64x128) || (fold == FOLD_M && want == TILE_128x64))) shape = want;
+  }
+  F.shape = shape;
+  const long TR = tile_rows(shape), TC = tile_cols(shape);
   double total = 0;
   for (size_t j = 0; j < shapes.size(); ++j) {
     const long m = fold == FOLD_M ? long(shapes[j].first) * batch : shapes[j].first;
     const long n = fold == FOLD_N ? long(shapes[j].second) * batch : shapes[j].second;
-    tiles_of[j] = ((m + 63) / 64) * ((n + 63) / 64);
-    long w = 0;
-    for (int c = ranges[j].first; c < ranges[j].second; ++c) w += (con_k[c] + 31) / 32;
-    work_of[j] = w;
-    total += double(tiles_of[j]) * double(w) * double(entries);
+    tiles_of[j] = ((m + TR - 1) / TR) * ((n + TC - 1) / TC);
+    total += double(tiles_of[j]) * double(work_of[j]) * double(entries);
   }
   // about four workgroups per slot of a full chip (256 CUs x 4 resident)
   const double target = std::max(8.0, total / 4096.0);
@@ -129,7 +164,7 @@ const GemmPlan::FoldTiles& GemmPlan::fold_lists(Ctx& x, int fold, int batch) con
   for (size_t j = 0; j < shapes.size(); ++j) {
     const long m = fold == FOLD_M ? long(shapes[j].first) * batch : shapes[j].first;
     const long n = fold == FOLD_N ? long(shapes[j].second) * batch : shapes[j].second;
-    const int tm = int((m + 63) / 64), tn = int((n + 63) / 64);
+    const int tm = int((m + TR - 1) / TR), tn = int((n + TC - 1) / TC);
     const int ncon_j = ranges[j].second - ranges[j].first;
     int nseg = int(std::ceil(double(work_of[j]) / target));
     nseg = std::max(1, std::min(nseg, ncon_j));

@@ -94,7 +94,7 @@ struct GemmPlan {
   // the reductions of their partial sums
   struct FoldTiles {
     DBuf tiles, segs, red;
-    int ntiles = 0, nred = 0, nslots = 0;
+    int ntiles = 0, nred = 0, nslots = 0, shape = 0;
   };
   mutable std::map<std::pair<int, int>, FoldTiles> fold_tiles;
   const FoldTiles& fold_lists(Ctx& x, int fold, int batch) const;

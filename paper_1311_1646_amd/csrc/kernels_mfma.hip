@@ -1,13 +1,14 @@
 // Grouped block GEMM on the CDNA4 matrix cores (gfx950).
 //
 // Work lists are those of the FMA kernel (tiles / jobs / contributions with
-// base-relative addressing).  A workgroup of four waves owns one 64x64 output
-// tile, each wave a 32x32 quarter, and streams every contribution of its job
-// through LDS in K-chunks.  The chunks of all contributions form one sequence;
-// chunk q+1 is fetched from global memory into registers while chunk q is
-// multiplied out of LDS, and LDS is double-buffered, so there is a single
-// barrier per chunk.  op() transposition, the contribution's alpha and zero
-// fill outside the block (ragged edges) are applied while staging.
+// base-relative addressing).  A workgroup of four waves owns one TM x TN
+// output tile (64x64, 128x64 or 64x128), each wave a (TM/2) x (TN/2)
+// quarter, and streams every contribution of its job through LDS in
+// K-chunks.  The chunks of all contributions form one sequence; chunk q+1 is
+// fetched from global memory into registers while chunk q is multiplied out
+// of LDS, and LDS is double-buffered, so there is a single barrier per chunk.
+// op() transposition, the contribution's alpha and zero fill outside the
+// block (ragged edges) are applied while staging.
 //
 // Batch folding: when one operand is shared by all batch entries and the
 // other operand and the output are batched, the batch is folded into the
@@ -15,9 +16,11 @@
 // [B_0 | B_1 | ...]; fold M: rows (v, i) of [A_0; A_1; ...]).  The shared
 // operand is then staged once per tile instead of once per batch entry and
 // the tiles of a narrow block are filled across entries.  Otherwise grid.y
-// enumerates the batch entries.
+// enumerates the batch entries.  The 128-wide tile shapes put 128 along the
+// unfolded (block) dimension, so a symmetry block of up to 128 rows or
+// columns is covered by one tile and the batched operand is read once.
 //
-//   FP64   : v_mfma_f64_16x16x4f64, 2x2 per wave, FP64 accumulate
+//   FP64   : v_mfma_f64_16x16x4f64, FP64 accumulate
 //            (16x16 result: lane l, register r holds row l/16 + 4r, column l%16).
 //   FP32   : v_mfma_f32_32x32x2f32, FP32 accumulate (32x32 result: lane l,
 //            register r holds row 8(r/4) + 4(l/32) + r%4, column l%32).
@@ -38,32 +41,32 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int TM = 64, TN = 64, NTH = 256;
+constexpr int NTH = 256;
 
 template <int MODE> struct Cfg;
 template <> struct Cfg<0> {  // FP64
   typedef double T;
-  static constexpr int TK = 16;
+  static constexpr int TK = 16, MB = 16;  // K-chunk, side of one MFMA result block
 };
 template <> struct Cfg<1> {  // FP32
   typedef float T;
-  static constexpr int TK = 32;
+  static constexpr int TK = 32, MB = 32;
 };
 template <> struct Cfg<2> {  // BF16x3
   typedef float T;
-  static constexpr int TK = 32;
+  static constexpr int TK = 32, MB = 32;
 };
 
 // LDS images of one chunk.  FP64/FP32: a[i][k], b[j][k] (row per output
 // index, padded by one element).  BF16x3: hi and lo parts, rows padded to a
 // multiple of 16 bytes so that eight consecutive k load as one 128-bit read.
-template <int MODE> struct Lds {
+template <int MODE, int TM, int TN> struct Lds {
   typedef typename Cfg<MODE>::T T;
   static constexpr int TK = Cfg<MODE>::TK;
   T a[2][TM][TK + 1];
   T b[2][TN][TK + 1];
 };
-template <> struct Lds<2> {
+template <int TM, int TN> struct Lds<2, TM, TN> {
   static constexpr int TK = 32, LD = TK + 8;
   alignas(16) __bf16 ah[2][TM][LD];
   alignas(16) __bf16 al[2][TM][LD];
@@ -71,21 +74,21 @@ template <> struct Lds<2> {
   alignas(16) __bf16 bl[2][TN][LD];
 };
 
-struct TileMap {
-  int v[TM];    // batch entry of each tile row (fold M) or column (fold N)
-  int idx[TM];  // row / column index inside the block, -1 outside
+template <int TM, int TN> struct TileMap {
+  int rv[TM], ri[TM];  // batch entry / block row of each tile row (-1 outside)
+  int cv[TN], cj[TN];  // batch entry / block column of each tile column
 };
 
-template <int MODE>
+template <int MODE, int TM, int TN>
 struct Stage {
   typedef typename Cfg<MODE>::T T;
   static constexpr int TK = Cfg<MODE>::TK;
-  static constexpr int PER = TM * TK / NTH;  // elements per thread and operand
-  static constexpr int RUNS = PER / 4;       // runs of 4 elements contiguous in memory
-  T ra[PER], rb[PER];
-  // Each thread stages RUNS runs of four elements that are contiguous in
-  // memory (run r = tid + r*NTH), so one address and one bounds test serve
-  // four loads.  The addresses are resolved once per contribution:
+  static constexpr int RA = TM * TK / NTH / 4;  // runs of 4 contiguous elements per thread, op(A)
+  static constexpr int RB = TN * TK / NTH / 4;  // and op(B)
+  T ra[4 * RA], rb[4 * RB];
+  // Each thread stages runs of four elements that are contiguous in memory
+  // (run r = tid + r*NTH), so one address and one bounds test serve four
+  // loads.  The addresses are resolved once per contribution:
   //   op(A) not transposed (contiguous in k): row r/(TK/4), k 4*(r%(TK/4))+e
   //       -> pa[r] points at (row, k) of the run
   //   op(A) transposed (contiguous in rows): k r/(TM/4), rows 4*(r%(TM/4))+e
@@ -95,15 +98,14 @@ struct Stage {
   //   op(B) transposed (contiguous in k): column r/(TK/4), k 4*(r%(TK/4))+e
   //       -> pb[r] points at (column, k) of the run
   //   identity A: ia[r] = block row of the run (or -1)
-  const T* pa[PER];
-  const T* pb[PER];
-  int ia[RUNS];
+  const T* pa[4 * RA];
+  const T* pb[4 * RB];
+  int ia[RA];
   long lda, ldb;
   int ck, flags;
   T alpha;
 
-  __device__ __forceinline__ void begin(const GContrib& c, const Bases& bs, const TileMap& rm, const TileMap& cm,
-                                        int tid) {
+  __device__ __forceinline__ void begin(const GContrib& c, const Bases& bs, const TileMap<TM, TN>& m, int tid) {
     flags = c.flags;
     ck = c.k;
     lda = c.lda;
@@ -111,29 +113,31 @@ struct Stage {
     alpha = T(c.alpha);
     const bool ta = c.flags & GC_TRANS_A, tb = c.flags & GC_TRANS_B, aid = c.flags & GC_A_IDENTITY;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) pa[q] = pb[q] = nullptr;
+    for (int q = 0; q < 4 * RA; ++q) pa[q] = nullptr;
 #pragma unroll
-    for (int r = 0; r < RUNS; ++r) ia[r] = -1;
+    for (int q = 0; q < 4 * RB; ++q) pb[q] = nullptr;
+#pragma unroll
+    for (int r = 0; r < RA; ++r) ia[r] = -1;
     if (aid) {
 #pragma unroll
-      for (int r = 0; r < RUNS; ++r) ia[r] = rm.idx[(tid + r * NTH) / (TK / 4)];
+      for (int r = 0; r < RA; ++r) ia[r] = m.ri[(tid + r * NTH) / (TK / 4)];
     } else {
       const T* A = reinterpret_cast<const T*>(bs.p[c.baseA]) + c.offA;
       const long sa = bs.stride[c.baseA];
       if (!ta) {
 #pragma unroll
-        for (int r = 0; r < RUNS; ++r) {
-          const int run = tid + r * NTH, i = run / (TK / 4), ii = rm.idx[i];
-          pa[r] = ii < 0 ? nullptr : A + long(rm.v[i]) * sa + long(ii) * c.lda + 4 * (run % (TK / 4));
+        for (int r = 0; r < RA; ++r) {
+          const int run = tid + r * NTH, i = run / (TK / 4), ii = m.ri[i];
+          pa[r] = ii < 0 ? nullptr : A + long(m.rv[i]) * sa + long(ii) * c.lda + 4 * (run % (TK / 4));
         }
       } else {
 #pragma unroll
-        for (int r = 0; r < RUNS; ++r) {
+        for (int r = 0; r < RA; ++r) {
           const int run = tid + r * NTH;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            const int i = 4 * (run % (TM / 4)) + e, ii = rm.idx[i];
-            pa[4 * r + e] = ii < 0 ? nullptr : A + long(rm.v[i]) * sa + ii;
+            const int i = 4 * (run % (TM / 4)) + e, ii = m.ri[i];
+            pa[4 * r + e] = ii < 0 ? nullptr : A + long(m.rv[i]) * sa + ii;
           }
         }
       }
@@ -142,19 +146,19 @@ struct Stage {
     const long sb = bs.stride[c.baseB];
     if (!tb) {
 #pragma unroll
-      for (int r = 0; r < RUNS; ++r) {
+      for (int r = 0; r < RB; ++r) {
         const int run = tid + r * NTH;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int j = 4 * (run % (TN / 4)) + e, jj = cm.idx[j];
-          pb[4 * r + e] = jj < 0 ? nullptr : B + long(cm.v[j]) * sb + jj;
+          const int j = 4 * (run % (TN / 4)) + e, jj = m.cj[j];
+          pb[4 * r + e] = jj < 0 ? nullptr : B + long(m.cv[j]) * sb + jj;
         }
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < RUNS; ++r) {
-        const int run = tid + r * NTH, j = run / (TK / 4), jj = cm.idx[j];
-        pb[r] = jj < 0 ? nullptr : B + long(cm.v[j]) * sb + long(jj) * c.ldb + 4 * (run % (TK / 4));
+      for (int r = 0; r < RB; ++r) {
+        const int run = tid + r * NTH, j = run / (TK / 4), jj = m.cj[j];
+        pb[r] = jj < 0 ? nullptr : B + long(m.cv[j]) * sb + long(jj) * c.ldb + 4 * (run % (TK / 4));
       }
     }
   }
@@ -176,20 +180,20 @@ struct Stage {
     const bool ta = flags & GC_TRANS_A, tb = flags & GC_TRANS_B, aid = flags & GC_A_IDENTITY;
     if (aid) {
 #pragma unroll
-      for (int r = 0; r < RUNS; ++r) {
+      for (int r = 0; r < RA; ++r) {
         const int k = k0 + 4 * ((tid + r * NTH) % (TK / 4));
 #pragma unroll
         for (int e = 0; e < 4; ++e) ra[4 * r + e] = (ia[r] >= 0 && ia[r] == k + e && k + e < ck) ? alpha : T(0);
       }
     } else if (!ta) {
 #pragma unroll
-      for (int r = 0; r < RUNS; ++r) {
+      for (int r = 0; r < RA; ++r) {
         const int k = k0 + 4 * ((tid + r * NTH) % (TK / 4));
         run4(ra + 4 * r, pa[r] ? pa[r] + k0 : nullptr, k, alpha);
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < RUNS; ++r) {
+      for (int r = 0; r < RA; ++r) {
         const int k = k0 + (tid + r * NTH) / (TM / 4);
         const long off = long(k) * lda;
 #pragma unroll
@@ -198,7 +202,7 @@ struct Stage {
     }
     if (!tb) {
 #pragma unroll
-      for (int r = 0; r < RUNS; ++r) {
+      for (int r = 0; r < RB; ++r) {
         const int k = k0 + (tid + r * NTH) / (TN / 4);
         const long off = long(k) * ldb;
 #pragma unroll
@@ -206,28 +210,35 @@ struct Stage {
       }
     } else {
 #pragma unroll
-      for (int r = 0; r < RUNS; ++r) {
+      for (int r = 0; r < RB; ++r) {
         const int k = k0 + 4 * ((tid + r * NTH) % (TK / 4));
         run4(rb + 4 * r, pb[r] ? pb[r] + k0 : nullptr, k, T(1));
       }
     }
   }
 
-  __device__ __forceinline__ void store(Lds<MODE>& s, int buf, bool ta, bool tb, int tid) const {
+  __device__ __forceinline__ void store(Lds<MODE, TM, TN>& s, int buf, bool ta, bool tb, int tid) const {
 #pragma unroll
-    for (int r = 0; r < RUNS; ++r) {
+    for (int r = 0; r < RA; ++r) {
       const int run = tid + r * NTH;
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         if (ta) put_a(s, buf, 4 * (run % (TM / 4)) + e, run / (TM / 4), ra[4 * r + e]);
         else put_a(s, buf, run / (TK / 4), 4 * (run % (TK / 4)) + e, ra[4 * r + e]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int run = tid + r * NTH;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
         if (tb) put_b(s, buf, run / (TK / 4), 4 * (run % (TK / 4)) + e, rb[4 * r + e]);
         else put_b(s, buf, 4 * (run % (TN / 4)) + e, run / (TN / 4), rb[4 * r + e]);
       }
     }
   }
 
-  __device__ __forceinline__ static void put_a(Lds<MODE>& s, int buf, int i, int k, T v) {
+  __device__ __forceinline__ static void put_a(Lds<MODE, TM, TN>& s, int buf, int i, int k, T v) {
     if constexpr (MODE == 2) {
       const __bf16 h = static_cast<__bf16>(v);
       s.ah[buf][i][k] = h;
@@ -236,7 +247,7 @@ struct Stage {
       s.a[buf][i][k] = v;
     }
   }
-  __device__ __forceinline__ static void put_b(Lds<MODE>& s, int buf, int j, int k, T v) {
+  __device__ __forceinline__ static void put_b(Lds<MODE, TM, TN>& s, int buf, int j, int k, T v) {
     if constexpr (MODE == 2) {
       const __bf16 h = static_cast<__bf16>(v);
       s.bh[buf][j][k] = h;
@@ -247,155 +258,181 @@ struct Stage {
   }
 };
 
-template <int MODE> struct Acc;
-template <> struct Acc<0> {
-  doublex4 c[2][2];
+// Accumulators of one wave: BM x BN result blocks of MB x MB.
+template <int MODE, int BM, int BN> struct Acc {
+  floatx16 c[BM][BN];
   __device__ void zero() {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < BM; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) c[a][b] = doublex4{0, 0, 0, 0};
+      for (int b = 0; b < BN; ++b) c[a][b] = floatx16{0};
   }
+  // row / column (inside the block) of register r of lane l
+  __device__ static int row(int l, int r) { return 8 * (r >> 2) + 4 * (l >> 5) + (r & 3); }
+  __device__ static int col(int l, int) { return l & 31; }
+  static constexpr int R = 16;
 };
-template <> struct Acc<1> {
-  floatx16 c;
-  __device__ void zero() { c = floatx16{0}; }
-};
-template <> struct Acc<2> {
-  floatx16 c;
-  __device__ void zero() { c = floatx16{0}; }
+template <int BM, int BN> struct Acc<0, BM, BN> {
+  doublex4 c[BM][BN];
+  __device__ void zero() {
+#pragma unroll
+    for (int a = 0; a < BM; ++a)
+#pragma unroll
+      for (int b = 0; b < BN; ++b) c[a][b] = doublex4{0, 0, 0, 0};
+  }
+  __device__ static int row(int l, int r) { return (l >> 4) + 4 * r; }
+  __device__ static int col(int l, int) { return l & 15; }
+  static constexpr int R = 4;
 };
 
 // Multiply the first kv (<= TK) K-entries of LDS buffer buf into the wave's
-// accumulator; (wm, wn) is the wave's 32x32 quarter.
-__device__ __forceinline__ void mma(Acc<0>& acc, const Lds<0>& s, int buf, int kv, int wm, int wn, int lane) {
+// accumulators; (wm, wn) is the corner of the wave's part of the tile.
+template <int TM, int TN, int BM, int BN>
+__device__ __forceinline__ void mma(Acc<0, BM, BN>& acc, const Lds<0, TM, TN>& s, int buf, int kv, int wm, int wn,
+                                    int lane) {
 #pragma unroll
   for (int st = 0; st < Cfg<0>::TK / 4; ++st) {
     if (4 * st >= kv) break;
     const int k = 4 * st + (lane >> 4);
-    double av[2], bv[2];
+    double av[BM], bv[BN];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) av[a] = s.a[buf][wm + 16 * a + (lane & 15)][k];
+    for (int a = 0; a < BM; ++a) av[a] = s.a[buf][wm + 16 * a + (lane & 15)][k];
 #pragma unroll
-    for (int b = 0; b < 2; ++b) bv[b] = s.b[buf][wn + 16 * b + (lane & 15)][k];
+    for (int b = 0; b < BN; ++b) bv[b] = s.b[buf][wn + 16 * b + (lane & 15)][k];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < BM; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < BN; ++b)
         acc.c[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc.c[a][b], 0, 0, 0);
   }
 }
 
-__device__ __forceinline__ void mma(Acc<1>& acc, const Lds<1>& s, int buf, int kv, int wm, int wn, int lane) {
+template <int TM, int TN, int BM, int BN>
+__device__ __forceinline__ void mma(Acc<1, BM, BN>& acc, const Lds<1, TM, TN>& s, int buf, int kv, int wm, int wn,
+                                    int lane) {
 #pragma unroll
   for (int st = 0; st < Cfg<1>::TK / 2; ++st) {
     if (2 * st >= kv) break;
     const int k = 2 * st + (lane >> 5);
-    acc.c = __builtin_amdgcn_mfma_f32_32x32x2f32(s.a[buf][wm + (lane & 31)][k], s.b[buf][wn + (lane & 31)][k], acc.c,
-                                                 0, 0, 0);
+    float av[BM], bv[BN];
+#pragma unroll
+    for (int a = 0; a < BM; ++a) av[a] = s.a[buf][wm + 32 * a + (lane & 31)][k];
+#pragma unroll
+    for (int b = 0; b < BN; ++b) bv[b] = s.b[buf][wn + 32 * b + (lane & 31)][k];
+#pragma unroll
+    for (int a = 0; a < BM; ++a)
+#pragma unroll
+      for (int b = 0; b < BN; ++b)
+        acc.c[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a], bv[b], acc.c[a][b], 0, 0, 0);
   }
 }
 
-__device__ __forceinline__ void mma(Acc<2>& acc, const Lds<2>& s, int buf, int kv, int wm, int wn, int lane) {
+template <int TM, int TN, int BM, int BN>
+__device__ __forceinline__ void mma(Acc<2, BM, BN>& acc, const Lds<2, TM, TN>& s, int buf, int kv, int wm, int wn,
+                                    int lane) {
 #pragma unroll
-  for (int st = 0; st < Lds<2>::TK / 16; ++st) {
+  for (int st = 0; st < Cfg<2>::TK / 16; ++st) {
     if (16 * st >= kv) break;
     const int k = 16 * st + 8 * (lane >> 5);
-    const bf16x8 ah = *reinterpret_cast<const bf16x8*>(&s.ah[buf][wm + (lane & 31)][k]);
-    const bf16x8 al = *reinterpret_cast<const bf16x8*>(&s.al[buf][wm + (lane & 31)][k]);
-    const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&s.bh[buf][wn + (lane & 31)][k]);
-    const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&s.bl[buf][wn + (lane & 31)][k]);
-    acc.c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc.c, 0, 0, 0);
-    acc.c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc.c, 0, 0, 0);
-    acc.c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc.c, 0, 0, 0);
+    bf16x8 ah[BM], al[BM], bh[BN], bl[BN];
+#pragma unroll
+    for (int a = 0; a < BM; ++a) {
+      ah[a] = *reinterpret_cast<const bf16x8*>(&s.ah[buf][wm + 32 * a + (lane & 31)][k]);
+      al[a] = *reinterpret_cast<const bf16x8*>(&s.al[buf][wm + 32 * a + (lane & 31)][k]);
+    }
+#pragma unroll
+    for (int b = 0; b < BN; ++b) {
+      bh[b] = *reinterpret_cast<const bf16x8*>(&s.bh[buf][wn + 32 * b + (lane & 31)][k]);
+      bl[b] = *reinterpret_cast<const bf16x8*>(&s.bl[buf][wn + 32 * b + (lane & 31)][k]);
+    }
+#pragma unroll
+    for (int a = 0; a < BM; ++a)
+#pragma unroll
+      for (int b = 0; b < BN; ++b) {
+        acc.c[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc.c[a][b], 0, 0, 0);
+        acc.c[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc.c[a][b], 0, 0, 0);
+        acc.c[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc.c[a][b], 0, 0, 0);
+      }
   }
 }
 
-template <class TOut>
-__device__ __forceinline__ void put_out(const Bases& bo, const GJob& J, const TileMap& rm, const TileMap& cm, int fold,
-                                        int i, int j, double v) {
-  const int ii = rm.idx[i], jj = cm.idx[j];
+template <class TOut, int TM, int TN>
+__device__ __forceinline__ void put_out(const Bases& bo, const GJob& J, const TileMap<TM, TN>& m, int fold, int i,
+                                        int j, double v) {
+  const int ii = m.ri[i], jj = m.cj[j];
   if (ii < 0 || jj < 0) return;
-  const int vb = fold == 2 ? rm.v[i] : cm.v[j];
+  const int vb = fold == 2 ? m.rv[i] : m.cv[j];
   TOut* p = reinterpret_cast<TOut*>(bo.p[J.baseC]) + J.offC + long(vb) * bo.stride[J.baseC] + long(ii) * J.ldc + jj;
   *p = (J.flags & GJ_ACCUMULATE) ? TOut(*p + TOut(v)) : TOut(v);
 }
 
-__device__ __forceinline__ void write(const Acc<0>& acc, const Bases& bo, const GJob& J, const TileMap& rm,
-                                      const TileMap& cm, int fold, int wm, int wn, int lane, bool) {
+template <int MODE, int TM, int TN, int BM, int BN>
+__device__ __forceinline__ void write(const Acc<MODE, BM, BN>& acc, const Bases& bo, const GJob& J,
+                                      const TileMap<TM, TN>& m, int fold, int wm, int wn, int lane, bool out_f64) {
+  typedef Acc<MODE, BM, BN> A;
+  constexpr int MB = Cfg<MODE>::MB;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int a = 0; a < BM; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < BN; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        put_out<double>(bo, J, rm, cm, fold, wm + 16 * a + (lane >> 4) + 4 * r, wn + 16 * b + (lane & 15),
-                        acc.c[a][b][r]);
+      for (int r = 0; r < A::R; ++r) {
+        const int i = wm + MB * a + A::row(lane, r), j = wn + MB * b + A::col(lane, r);
+        if (MODE == 0 || out_f64) put_out<double>(bo, J, m, fold, i, j, acc.c[a][b][r]);
+        else put_out<float>(bo, J, m, fold, i, j, acc.c[a][b][r]);
+      }
 }
 
-template <int MODE>
-__device__ __forceinline__ void write(const Acc<MODE>& acc, const Bases& bo, const GJob& J, const TileMap& rm,
-                                      const TileMap& cm, int fold, int wm, int wn, int lane, bool out_f64) {
+template <int MODE, int TN, int BM, int BN, class PT>
+__device__ __forceinline__ void write_partial(const Acc<MODE, BM, BN>& acc, PT* P, int wm, int wn, int lane) {
+  typedef Acc<MODE, BM, BN> A;
+  constexpr int MB = Cfg<MODE>::MB;
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int i = wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), j = wn + (lane & 31);
-    if (out_f64) put_out<double>(bo, J, rm, cm, fold, i, j, acc.c[r]);
-    else put_out<float>(bo, J, rm, cm, fold, i, j, acc.c[r]);
-  }
+  for (int a = 0; a < BM; ++a)
+#pragma unroll
+    for (int b = 0; b < BN; ++b)
+#pragma unroll
+      for (int r = 0; r < A::R; ++r)
+        P[(wm + MB * a + A::row(lane, r)) * TN + wn + MB * b + A::col(lane, r)] = PT(acc.c[a][b][r]);
 }
 
-// Row and column maps of tile (tm, tn) of job J (threads 0..127 fill them;
-// the caller synchronizes).  fold: 0 = grid.y enumerates batch entries,
-// 1 = batch folded into N, 2 = batch folded into M.
-__device__ __forceinline__ void tile_maps(TileMap& rm, TileMap& cm, const GJob& J, int tm, int tn, int fold,
-                                          int batch, int tid) {
+// Row and column maps of tile (tm, tn) of job J (threads 0..TM+TN-1 fill
+// them; the caller synchronizes).  fold: 0 = grid.y enumerates batch
+// entries, 1 = batch folded into N, 2 = batch folded into M.
+template <int TM, int TN>
+__device__ __forceinline__ void tile_maps(TileMap<TM, TN>& m, const GJob& J, int tm, int tn, int fold, int batch,
+                                          int tid) {
   if (tid < TM) {
     const int g = tm * TM + tid;
     const int mb = fold == 2 ? J.m * batch : J.m;
-    rm.v[tid] = fold == 2 ? g / J.m : (fold == 0 ? int(blockIdx.y) : 0);
-    rm.idx[tid] = g < mb ? (fold == 2 ? g % J.m : g) : -1;
+    m.rv[tid] = fold == 2 ? g / J.m : (fold == 0 ? int(blockIdx.y) : 0);
+    m.ri[tid] = g < mb ? (fold == 2 ? g % J.m : g) : -1;
   } else if (tid < TM + TN) {
     const int u = tid - TM, g = tn * TN + u;
     const int nb = fold == 1 ? J.n * batch : J.n;
-    cm.v[u] = fold == 1 ? g / J.n : (fold == 0 ? int(blockIdx.y) : 0);
-    cm.idx[u] = g < nb ? (fold == 1 ? g % J.n : g) : -1;
+    m.cv[u] = fold == 1 ? g / J.n : (fold == 0 ? int(blockIdx.y) : 0);
+    m.cj[u] = g < nb ? (fold == 1 ? g % J.n : g) : -1;
   }
-}
-
-template <class PT>
-__device__ __forceinline__ void write_partial(const Acc<0>& acc, PT* P, int wm, int wn, int lane) {
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        P[(wm + 16 * a + (lane >> 4) + 4 * r) * TN + wn + 16 * b + (lane & 15)] = PT(acc.c[a][b][r]);
-}
-template <int MODE, class PT>
-__device__ __forceinline__ void write_partial(const Acc<MODE>& acc, PT* P, int wm, int wn, int lane) {
-#pragma unroll
-  for (int r = 0; r < 16; ++r)
-    P[(wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * TN + wn + (lane & 31)] = PT(acc.c[r]);
 }
 
 // ROLE only tags the instantiation (0: products into a workspace, 1: the
 // accumulation into the result), so that profiles separate the two stages.
-template <int MODE, int ROLE>
+template <int MODE, int ROLE, int TM, int TN>
 __global__ __launch_bounds__(NTH) void ggemm_mfma_kernel(const GTile* __restrict__ tiles,
                                                          const GJob* __restrict__ jobs,
                                                          const GContrib* __restrict__ con,
                                                          const GSeg* __restrict__ segs, int nslots,
                                                          typename Cfg<MODE>::T* __restrict__ partial, Bases bs,
                                                          Bases bout, int fold, int batch, int out_f64) {
-  __shared__ Lds<MODE> s;
-  __shared__ TileMap rm, cm;
+  constexpr int TK = Cfg<MODE>::TK, MB = Cfg<MODE>::MB;
+  constexpr int BM = TM / 2 / MB, BN = TN / 2 / MB;
+  __shared__ Lds<MODE, TM, TN> s;
+  __shared__ TileMap<TM, TN> m;
   __shared__ Bases sb;  // base table indexed per contribution (LDS, not a private copy)
-  constexpr int TK = Cfg<MODE>::TK;
   const GTile t = tiles[blockIdx.x];
   const GJob J = jobs[t.job];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * (TN / 2);
   int c0 = J.c0, c1 = J.c1, slot = -1;
   if (t.pad >= 0) {
     const GSeg g = segs[t.pad];
@@ -403,18 +440,18 @@ __global__ __launch_bounds__(NTH) void ggemm_mfma_kernel(const GTile* __restrict
     c1 = g.c1;
     slot = g.slot;
   }
-  tile_maps(rm, cm, J, t.tm, t.tn, fold, batch, tid);
+  tile_maps<TM, TN>(m, J, t.tm, t.tn, fold, batch, tid);
   if (tid >= TM + TN && tid < TM + TN + kMaxBases) {
     sb.p[tid - TM - TN] = bs.p[tid - TM - TN];
     sb.stride[tid - TM - TN] = bs.stride[tid - TM - TN];
   }
   __syncthreads();
-  Acc<MODE> acc;
+  Acc<MODE, BM, BN> acc;
   acc.zero();
   if (c0 < c1) {
-    Stage<MODE> st;
+    Stage<MODE, TM, TN> st;
     int ci = c0, k0 = 0, buf = 0;
-    st.begin(con[ci], sb, rm, cm, tid);
+    st.begin(con[ci], sb, m, tid);
     st.load(0, tid);
     for (;;) {
       const int ck = st.ck, fl = st.flags;
@@ -428,10 +465,10 @@ __global__ __launch_bounds__(NTH) void ggemm_mfma_kernel(const GTile* __restrict
       }
       const bool more = nci < c1;
       if (more) {
-        if (nci != ci) st.begin(con[nci], sb, rm, cm, tid);
+        if (nci != ci) st.begin(con[nci], sb, m, tid);
         st.load(nk0, tid);
       }
-      mma(acc, s, buf, kv, wm, wn, lane);
+      mma<TM, TN, BM, BN>(acc, s, buf, kv, wm, wn, lane);
       if (!more) break;
       ci = nci;
       k0 = nk0;
@@ -440,49 +477,34 @@ __global__ __launch_bounds__(NTH) void ggemm_mfma_kernel(const GTile* __restrict
   }
   if (slot >= 0) {
     const long entry = fold == 0 ? long(blockIdx.y) : 0;
-    write_partial(acc, partial + (entry * nslots + slot) * long(TM * TN), wm, wn, lane);
+    write_partial<MODE, TN>(acc, partial + (entry * nslots + slot) * long(TM * TN), wm, wn, lane);
   } else {
-    write(acc, bout, J, rm, cm, fold, wm, wn, lane, out_f64 != 0);
+    write<MODE, TM, TN>(acc, bout, J, m, fold, wm, wn, lane, out_f64 != 0);
   }
 }
 
 // Sum the partial tiles of each reduction item in segment order and write
 // the tile to its output block.
-template <class PT>
+template <class PT, int TM, int TN>
 __global__ __launch_bounds__(NTH) void reduce_partials_kernel(const GRed* __restrict__ red,
                                                               const GJob* __restrict__ jobs,
                                                               const PT* __restrict__ partial, int nslots, Bases bout,
                                                               int fold, int batch, int out_f64) {
-  __shared__ TileMap rm, cm;
+  __shared__ TileMap<TM, TN> m;
   const GRed r = red[blockIdx.x];
   const GJob J = jobs[r.job];
   const int tid = threadIdx.x;
-  tile_maps(rm, cm, J, r.tm, r.tn, fold, batch, tid);
+  tile_maps<TM, TN>(m, J, r.tm, r.tn, fold, batch, tid);
   __syncthreads();
   const long entry = fold == 0 ? long(blockIdx.y) : 0;
   const PT* P = partial + (entry * nslots + r.slot0) * long(TM * TN);
   for (int e = tid; e < TM * TN; e += NTH) {
     const int i = e / TN, j = e % TN;
-    if (rm.idx[i] < 0 || cm.idx[j] < 0) continue;
+    if (m.ri[i] < 0 || m.cj[j] < 0) continue;
     double sum = 0;
     for (int q = 0; q < r.nseg; ++q) sum += double(P[long(q) * TM * TN + e]);
-    if (out_f64) put_out<double>(bout, J, rm, cm, fold, i, j, sum);
-    else put_out<float>(bout, J, rm, cm, fold, i, j, sum);
-  }
-}
-
-__global__ void lincomb_f32_kernel(const LCTarget* __restrict__ tg, const LCSource* __restrict__ src, Bases bs) {
-  const LCTarget t = tg[blockIdx.y];
-  const int bz = blockIdx.z;
-  float* out = reinterpret_cast<float*>(bs.p[t.base]) + t.off + long(bz) * bs.stride[t.base];
-  for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < t.size; e += long(gridDim.x) * blockDim.x) {
-    float acc = 0.f;
-    for (int j = t.s0; j < t.s1; ++j) {
-      const float* p =
-          reinterpret_cast<const float*>(bs.p[src[j].base]) + src[j].off + long(bz) * bs.stride[src[j].base];
-      acc = fmaf(float(src[j].c), p[e], acc);
-    }
-    out[e] = t.accumulate ? out[e] + acc : acc;
+    if (out_f64) put_out<double>(bout, J, m, fold, i, j, sum);
+    else put_out<float>(bout, J, m, fold, i, j, sum);
   }
 }
 
@@ -497,53 +519,79 @@ __global__ void convert_f64_f32_kernel(const double* __restrict__ in, float* __r
     out[e] = float(in[e]);
 }
 
-}  // namespace
-
-template <int MODE>
-void launch_mode(int role, dim3 grid, hipStream_t s, const GTile* tiles, const GJob* jobs, const GContrib* con,
-                 const GSeg* segs, int nslots, void* partial, const Bases& b, const Bases& bout, int fold, int batch,
-                 int of) {
+template <int MODE, int TM, int TN>
+void launch_shape(int role, dim3 grid, hipStream_t s, const GTile* tiles, const GJob* jobs, const GContrib* con,
+                  const GSeg* segs, int nslots, void* partial, const Bases& b, const Bases& bout, int fold, int batch,
+                  int of) {
   typedef typename Cfg<MODE>::T T;
   T* P = static_cast<T*>(partial);
   if (role == 0)
-    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 0>), grid, dim3(NTH), 0, s, tiles, jobs, con, segs, nslots, P, b, bout,
-                       fold, batch, of);
+    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 0, TM, TN>), grid, dim3(NTH), 0, s, tiles, jobs, con, segs, nslots, P,
+                       b, bout, fold, batch, of);
   else
-    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 1>), grid, dim3(NTH), 0, s, tiles, jobs, con, segs, nslots, P, b, bout,
-                       fold, batch, of);
+    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 1, TM, TN>), grid, dim3(NTH), 0, s, tiles, jobs, con, segs, nslots, P,
+                       b, bout, fold, batch, of);
 }
 
-void launch_grouped_gemm(int prec, bool out_f64, int role, const GTile* tiles, int ntiles, const GJob* jobs,
-                         const GContrib* con, const GSeg* segs, int nslots, void* partial, const Bases& b,
-                         const Bases& bout, int fold, int batch, hipStream_t s) {
+template <int MODE>
+void launch_mode(int shape, int role, dim3 grid, hipStream_t s, const GTile* tiles, const GJob* jobs,
+                 const GContrib* con, const GSeg* segs, int nslots, void* partial, const Bases& b, const Bases& bout,
+                 int fold, int batch, int of) {
+  if (shape == TILE_128x64)
+    launch_shape<MODE, 128, 64>(role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold,
+                                batch, of);
+  else if (shape == TILE_64x128)
+    launch_shape<MODE, 64, 128>(role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold,
+                                batch, of);
+  else
+    launch_shape<MODE, 64, 64>(role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold,
+                               batch, of);
+}
+
+template <class PT, int TM, int TN>
+void launch_reduce(dim3 grid, hipStream_t s, const GRed* red, const GJob* jobs, const void* partial, int nslots,
+                   const Bases& bout, int fold, int batch, int of) {
+  hipLaunchKernelGGL((reduce_partials_kernel<PT, TM, TN>), grid, dim3(NTH), 0, s, red, jobs,
+                     static_cast<const PT*>(partial), nslots, bout, fold, batch, of);
+}
+
+}  // namespace
+
+int tile_rows(int shape) { return shape == TILE_128x64 ? 128 : 64; }
+int tile_cols(int shape) { return shape == TILE_64x128 ? 128 : 64; }
+
+void launch_grouped_gemm(int prec, bool out_f64, int role, int shape, const GTile* tiles, int ntiles,
+                         const GJob* jobs, const GContrib* con, const GSeg* segs, int nslots, void* partial,
+                         const Bases& b, const Bases& bout, int fold, int batch, hipStream_t s) {
   if (ntiles <= 0 || batch <= 0) return;
   const dim3 grid(ntiles, fold == 0 ? batch : 1);
-  if (prec == 0) launch_mode<0>(role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold, batch, 1);
+  const int of = out_f64 ? 1 : 0;
+  if (prec == 0)
+    launch_mode<0>(shape, role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold, batch,
+                   1);
   else if (prec == 1)
-    launch_mode<1>(role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold, batch, out_f64 ? 1 : 0);
-  else launch_mode<2>(role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold, batch, out_f64 ? 1 : 0);
+    launch_mode<1>(shape, role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold, batch,
+                   of);
+  else
+    launch_mode<2>(shape, role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold, batch,
+                   of);
 }
 
-void launch_reduce_partials(int prec, bool out_f64, const GRed* red, int nred, const GJob* jobs, int nslots,
-                            const void* partial, const Bases& bout, int fold, int batch, hipStream_t s) {
+void launch_reduce_partials(int prec, bool out_f64, int shape, const GRed* red, int nred, const GJob* jobs,
+                            int nslots, const void* partial, const Bases& bout, int fold, int batch, hipStream_t s) {
   if (nred <= 0 || batch <= 0) return;
   const dim3 grid(nred, fold == 0 ? batch : 1);
-  if (prec == 0)
-    hipLaunchKernelGGL(reduce_partials_kernel<double>, grid, dim3(NTH), 0, s, red, jobs,
-                       static_cast<const double*>(partial), nslots, bout, fold, batch, 1);
-  else
-    hipLaunchKernelGGL(reduce_partials_kernel<float>, grid, dim3(NTH), 0, s, red, jobs,
-                       static_cast<const float*>(partial), nslots, bout, fold, batch, out_f64 ? 1 : 0);
-}
-
-void launch_lincomb_f32(const LCTarget* t, int ntargets, const LCSource* src, long max_size, const Bases& b, int batch,
-                        hipStream_t s) {
-  if (ntargets <= 0 || max_size <= 0 || batch <= 0) return;
-  long blocks = (max_size + 255) / 256;
-  if (blocks > 2048) blocks = 2048;
-  for (int t0 = 0; t0 < ntargets; t0 += 65535) {
-    const int nt = ntargets - t0 < 65535 ? ntargets - t0 : 65535;
-    hipLaunchKernelGGL(lincomb_f32_kernel, dim3(unsigned(blocks), nt, batch), dim3(256), 0, s, t + t0, src, b);
+  const int of = (prec == 0 || out_f64) ? 1 : 0;
+  if (prec == 0) {
+    if (shape == TILE_128x64) launch_reduce<double, 128, 64>(grid, s, red, jobs, partial, nslots, bout, fold, batch, 1);
+    else if (shape == TILE_64x128)
+      launch_reduce<double, 64, 128>(grid, s, red, jobs, partial, nslots, bout, fold, batch, 1);
+    else launch_reduce<double, 64, 64>(grid, s, red, jobs, partial, nslots, bout, fold, batch, 1);
+  } else {
+    if (shape == TILE_128x64) launch_reduce<float, 128, 64>(grid, s, red, jobs, partial, nslots, bout, fold, batch, of);
+    else if (shape == TILE_64x128)
+      launch_reduce<float, 64, 128>(grid, s, red, jobs, partial, nslots, bout, fold, batch, of);
+    else launch_reduce<float, 64, 64>(grid, s, red, jobs, partial, nslots, bout, fold, batch, of);
   }
 }
 

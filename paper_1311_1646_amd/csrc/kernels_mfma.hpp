@@ -26,16 +26,21 @@ struct GSeg {
 struct GRed {
   int job, tm, tn, slot0, nseg, pad;
 };
-// role 0: products into a workspace, 1: accumulation into the result (the
-// two instantiations are the same code; the tag separates them in profiles)
-void launch_grouped_gemm(int prec, bool out_f64, int role, const GTile* tiles, int ntiles, const GJob* jobs,
-                         const GContrib* con, const GSeg* segs, int nslots, void* partial, const Bases& b,
-                         const Bases& bout, int fold, int batch, hipStream_t s);
-void launch_reduce_partials(int prec, bool out_f64, const GRed* red, int nred, const GJob* jobs, int nslots,
-                            const void* partial, const Bases& bout, int fold, int batch, hipStream_t s);
+// Output tile shapes of the matrix-core kernel (rows x columns).
+enum : int { TILE_64x64 = 0, TILE_128x64 = 1, TILE_64x128 = 2 };
+int tile_rows(int shape);
+int tile_cols(int shape);
 
-void launch_lincomb_f32(const LCTarget* t, int ntargets, const LCSource* src, long max_size, const Bases& b,
-                        int batch, hipStream_t s);
+// role 0: products into a workspace, 1: accumulation into the result (the
+// two instantiations are the same code; the tag separates them in profiles).
+// Tiles index shape-sized tiles; partial slots hold dense rows x columns
+// tiles of the operand type.
+void launch_grouped_gemm(int prec, bool out_f64, int role, int shape, const GTile* tiles, int ntiles,
+                         const GJob* jobs, const GContrib* con, const GSeg* segs, int nslots, void* partial,
+                         const Bases& b, const Bases& bout, int fold, int batch, hipStream_t s);
+void launch_reduce_partials(int prec, bool out_f64, int shape, const GRed* red, int nred, const GJob* jobs,
+                            int nslots, const void* partial, const Bases& bout, int fold, int batch, hipStream_t s);
+
 void launch_diag_add_f32(const DiagAdd* d, int n, const Bases& b, int batch, hipStream_t s);
 void launch_convert_f64_f32(const double* in, float* out, long n, hipStream_t s);
 

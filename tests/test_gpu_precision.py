@@ -92,3 +92,24 @@ def test_multi_tile_sigma(ppp12, prec, fp64_gemm, monkeypatch):
             print(f"  w={w} site={i} n={n} rel={err:.3e}", flush=True)
             assert err < TOL[prec], (w, i, err)
     ctx.close()
+
+
+@pytest.mark.parametrize("shape", ["64x64", "128x64", "64x128"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_every_tile_shape(ppp12, prec, shape, monkeypatch):
+    # each matrix-core tile shape (where the batch folding allows it) on
+    # blocks wider than 64 with a ragged edge
+    import paper_1311_1646_amd as lib
+    L, Na, Nb, h, eri, mps, dets, H = ppp12
+    monkeypatch.setenv("DMRG_TILE_SHAPE", shape)
+    ctx = _ctx(lib, L, Na, Nb, h, eri, mps)
+    rng = np.random.default_rng(29)
+    for w, i in ((1, 5), (1, 6), (2, 5)):
+        kind = lib.SIGMA_ZEROTH_1SITE if w == 1 else lib.SIGMA_ZEROTH_2SITE
+        _, n = ctx.layout(i, w)
+        C = rng.normal(size=(3, n))
+        ref = mpsvec.heff_apply(H, mps, dets, i, C, width=w)
+        out = ctx.sigma(i, torch.tensor(C, device="cuda"), kind=kind, prec=_prec(lib, prec)).cpu().numpy()
+        err = _rel(out, ref)
+        assert err < TOL[prec], (shape, w, i, err)
+    ctx.close()
