@@ -79,6 +79,11 @@ template <int TM, int TN> struct TileMap {
   int cv[TN], cj[TN];  // batch entry / block column of each tile column
 };
 
+// Global-memory pointers: loads through them are global loads (counted by
+// vmcnt only), not flat loads that would also hold up the LDS waits of the
+// multiply while the next chunk is in flight.
+template <class T> using gptr = const __attribute__((address_space(1))) T*;
+
 template <int MODE, int TM, int TN>
 struct Stage {
   typedef typename Cfg<MODE>::T T;
@@ -98,8 +103,8 @@ struct Stage {
   //   op(B) transposed (contiguous in k): column r/(TK/4), k 4*(r%(TK/4))+e
   //       -> pb[r] points at (column, k) of the run
   //   identity A: ia[r] = block row of the run (or -1)
-  const T* pa[4 * RA];
-  const T* pb[4 * RB];
+  gptr<T> pa[4 * RA];
+  gptr<T> pb[4 * RB];
   int ia[RA];
   long lda, ldb;
   int ck, flags;
@@ -122,7 +127,7 @@ struct Stage {
 #pragma unroll
       for (int r = 0; r < RA; ++r) ia[r] = m.ri[(tid + r * NTH) / (TK / 4)];
     } else {
-      const T* A = reinterpret_cast<const T*>(bs.p[c.baseA]) + c.offA;
+      const gptr<T> A = (gptr<T>)(bs.p[c.baseA]) + c.offA;
       const long sa = bs.stride[c.baseA];
       if (!ta) {
 #pragma unroll
@@ -142,7 +147,7 @@ struct Stage {
         }
       }
     }
-    const T* B = reinterpret_cast<const T*>(bs.p[c.baseB]) + c.offB;
+    const gptr<T> B = (gptr<T>)(bs.p[c.baseB]) + c.offB;
     const long sb = bs.stride[c.baseB];
     if (!tb) {
 #pragma unroll
@@ -165,7 +170,7 @@ struct Stage {
 
   // Four contiguous elements starting at p (k indices k..k+3 checked
   // against the contribution's inner length).
-  __device__ __forceinline__ void run4(T* dst, const T* p, int k, T scale) const {
+  __device__ __forceinline__ void run4(T* dst, gptr<T> p, int k, T scale) const {
     if (p && k + 3 < ck) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) dst[e] = p[e] * scale;
