@@ -420,24 +420,20 @@ __device__ __forceinline__ void tile_maps(TileMap<TM, TN>& m, const GJob& J, int
   }
 }
 
-// ROLE only tags the instantiation (0: products into a workspace, 1: the
-// accumulation into the result), so that profiles separate the two stages.
-template <int MODE, int ROLE, int TM, int TN>
-__global__ __launch_bounds__(NTH) void ggemm_mfma_kernel(const GTile* __restrict__ tiles,
-                                                         const GJob* __restrict__ jobs,
-                                                         const GContrib* __restrict__ con,
-                                                         const GSeg* __restrict__ segs, int nslots,
-                                                         typename Cfg<MODE>::T* __restrict__ partial, Bases bs,
-                                                         Bases bout, int fold, int batch, int out_f64) {
+// One output tile: all contributions of its job (or of its segment) through
+// the double-buffered LDS pipeline, then the result or the partial sum.
+template <int MODE, int TM, int TN>
+__device__ __forceinline__ void do_tile(int ti, const GTile* __restrict__ tiles, const GJob* __restrict__ jobs,
+                                        const GContrib* __restrict__ con, const GSeg* __restrict__ segs, int nslots,
+                                        typename Cfg<MODE>::T* __restrict__ partial, const Bases& bout, int fold,
+                                        int batch, int out_f64, Lds<MODE, TM, TN>& s, TileMap<TM, TN>& m,
+                                        const Bases& sb) {
   constexpr int TK = Cfg<MODE>::TK, MB = Cfg<MODE>::MB;
   constexpr int BM = TM / 2 / MB, BN = TN / 2 / MB;
-  __shared__ Lds<MODE, TM, TN> s;
-  __shared__ TileMap<TM, TN> m;
-  __shared__ Bases sb;  // base table indexed per contribution (LDS, not a private copy)
-  const GTile t = tiles[blockIdx.x];
-  const GJob J = jobs[t.job];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * (TN / 2);
+  const GTile t = tiles[ti];
+  const GJob J = jobs[t.job];
   int c0 = J.c0, c1 = J.c1, slot = -1;
   if (t.pad >= 0) {
     const GSeg g = segs[t.pad];
@@ -446,10 +442,6 @@ __global__ __launch_bounds__(NTH) void ggemm_mfma_kernel(const GTile* __restrict
     slot = g.slot;
   }
   tile_maps<TM, TN>(m, J, t.tm, t.tn, fold, batch, tid);
-  if (tid >= TM + TN && tid < TM + TN + kMaxBases) {
-    sb.p[tid - TM - TN] = bs.p[tid - TM - TN];
-    sb.stride[tid - TM - TN] = bs.stride[tid - TM - TN];
-  }
   __syncthreads();
   Acc<MODE, BM, BN> acc;
   acc.zero();
@@ -485,6 +477,39 @@ __global__ __launch_bounds__(NTH) void ggemm_mfma_kernel(const GTile* __restrict
     write_partial<MODE, TN>(acc, partial + (entry * nslots + slot) * long(TM * TN), wm, wn, lane);
   } else {
     write<MODE, TM, TN>(acc, bout, J, m, fold, wm, wn, lane, out_f64 != 0);
+  }
+}
+
+// Persistent workgroups (a grid of a few rounds of the resident capacity,
+// each looping over tiles) pay the launch of a workgroup once; they are used
+// where the loop does not cost registers (FP64, capped at 4 waves per SIMD).
+template <int MODE> struct Persist {
+  static constexpr bool on = MODE == 0;
+  static constexpr int waves = MODE == 0 ? 4 : 1;
+};
+
+// ROLE only tags the instantiation (0: products into a workspace, 1: the
+// accumulation into the result), so that profiles separate the two stages.
+template <int MODE, int ROLE, int TM, int TN>
+__global__ __launch_bounds__(NTH, Persist<MODE>::waves) void ggemm_mfma_kernel(
+    const GTile* __restrict__ tiles, int ntiles, const GJob* __restrict__ jobs, const GContrib* __restrict__ con,
+    const GSeg* __restrict__ segs, int nslots, typename Cfg<MODE>::T* __restrict__ partial, Bases bs, Bases bout,
+    int fold, int batch, int out_f64) {
+  __shared__ Lds<MODE, TM, TN> s;
+  __shared__ TileMap<TM, TN> m;
+  __shared__ Bases sb;  // base table indexed per contribution (LDS, not a private copy)
+  const int tid = threadIdx.x;
+  if (tid < kMaxBases) {
+    sb.p[tid] = bs.p[tid];
+    sb.stride[tid] = bs.stride[tid];
+  }
+  if constexpr (Persist<MODE>::on) {
+    for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+      __syncthreads();  // the previous tile is done with the maps
+      do_tile<MODE, TM, TN>(ti, tiles, jobs, con, segs, nslots, partial, bout, fold, batch, out_f64, s, m, sb);
+    }
+  } else {
+    do_tile<MODE, TM, TN>(blockIdx.x, tiles, jobs, con, segs, nslots, partial, bout, fold, batch, out_f64, s, m, sb);
   }
 }
 
@@ -525,31 +550,32 @@ __global__ void convert_f64_f32_kernel(const double* __restrict__ in, float* __r
 }
 
 template <int MODE, int TM, int TN>
-void launch_shape(int role, dim3 grid, hipStream_t s, const GTile* tiles, const GJob* jobs, const GContrib* con,
+void launch_shape(int role, dim3 grid, hipStream_t s, const GTile* tiles, int ntiles, const GJob* jobs,
+                  const GContrib* con,
                   const GSeg* segs, int nslots, void* partial, const Bases& b, const Bases& bout, int fold, int batch,
                   int of) {
   typedef typename Cfg<MODE>::T T;
   T* P = static_cast<T*>(partial);
   if (role == 0)
-    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 0, TM, TN>), grid, dim3(NTH), 0, s, tiles, jobs, con, segs, nslots, P,
-                       b, bout, fold, batch, of);
+    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 0, TM, TN>), grid, dim3(NTH), 0, s, tiles, ntiles, jobs, con, segs,
+                       nslots, P, b, bout, fold, batch, of);
   else
-    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 1, TM, TN>), grid, dim3(NTH), 0, s, tiles, jobs, con, segs, nslots, P,
-                       b, bout, fold, batch, of);
+    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 1, TM, TN>), grid, dim3(NTH), 0, s, tiles, ntiles, jobs, con, segs,
+                       nslots, P, b, bout, fold, batch, of);
 }
 
 template <int MODE>
-void launch_mode(int shape, int role, dim3 grid, hipStream_t s, const GTile* tiles, const GJob* jobs,
+void launch_mode(int shape, int role, dim3 grid, hipStream_t s, const GTile* tiles, int ntiles, const GJob* jobs,
                  const GContrib* con, const GSeg* segs, int nslots, void* partial, const Bases& b, const Bases& bout,
                  int fold, int batch, int of) {
   if (shape == TILE_128x64)
-    launch_shape<MODE, 128, 64>(role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold,
+    launch_shape<MODE, 128, 64>(role, grid, s, tiles, ntiles, jobs, con, segs, nslots, partial, b, bout, fold,
                                 batch, of);
   else if (shape == TILE_64x128)
-    launch_shape<MODE, 64, 128>(role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold,
+    launch_shape<MODE, 64, 128>(role, grid, s, tiles, ntiles, jobs, con, segs, nslots, partial, b, bout, fold,
                                 batch, of);
   else
-    launch_shape<MODE, 64, 64>(role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold,
+    launch_shape<MODE, 64, 64>(role, grid, s, tiles, ntiles, jobs, con, segs, nslots, partial, b, bout, fold,
                                batch, of);
 }
 
@@ -569,16 +595,21 @@ void launch_grouped_gemm(int prec, bool out_f64, int role, int shape, const GTil
                          const GJob* jobs, const GContrib* con, const GSeg* segs, int nslots, void* partial,
                          const Bases& b, const Bases& bout, int fold, int batch, hipStream_t s) {
   if (ntiles <= 0 || batch <= 0) return;
-  const dim3 grid(ntiles, fold == 0 ? batch : 1);
+  // FP64 runs persistent workgroups (at most 16 per CU of the 256, a few
+  // rounds of the resident capacity); the others one workgroup per tile
+  const int per = fold == 0 ? batch : 1;
+  const int cap = 4096 * 16 / per > 0 ? 4096 * 16 / per : 1;
+  const int gx = (prec == 0 && ntiles > cap) ? cap : ntiles;
+  const dim3 grid(gx, per);
   const int of = out_f64 ? 1 : 0;
   if (prec == 0)
-    launch_mode<0>(shape, role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold, batch,
+    launch_mode<0>(shape, role, grid, s, tiles, ntiles, jobs, con, segs, nslots, partial, b, bout, fold, batch,
                    1);
   else if (prec == 1)
-    launch_mode<1>(shape, role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold, batch,
+    launch_mode<1>(shape, role, grid, s, tiles, ntiles, jobs, con, segs, nslots, partial, b, bout, fold, batch,
                    of);
   else
-    launch_mode<2>(shape, role, grid, s, tiles, jobs, con, segs, nslots, partial, b, bout, fold, batch,
+    launch_mode<2>(shape, role, grid, s, tiles, ntiles, jobs, con, segs, nslots, partial, b, bout, fold, batch,
                    of);
 }
 
