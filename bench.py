@@ -199,7 +199,7 @@ def main():
                        "unit": "TFLOP/s", "frac": round(ach / PEAK[a.prec], 4),
                        "traffic": measured_traffic(a.prec, p.M)}
     out["config"]["dominant_kernel"] = {
-        "name": "ggemm_mfma_kernel<%d, 1>" % {"fp64": 0, "fp32": 1, "bf16x3": 2}[a.prec],
+        "name": "ggemm_mfma_kernel<%d, 1, TM, TN>" % {"fp64": 0, "fp32": 1, "bf16x3": 2}[a.prec],
         "launches_per_sigma": nl, "avg_launch_ms": round(head["main_ms"] / nl, 4),
         "flops_per_launch": head["main_flops"] / nl, "algorithmic_bytes_per_launch": head["main_bytes"] / nl}
     if a.tda_iters > 0:
