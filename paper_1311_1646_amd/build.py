@@ -19,7 +19,7 @@ ARCH = os.environ.get("DMRG_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(HERE, "..", "include")]
-# Packed FP32 instructions are disabled for all device code (see DESIGN.md).
+# Packed FP32 instructions are disabled for all device code.
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
 LIBS = ["-lrocsolver", "-lrocblas"]

@@ -64,7 +64,8 @@ void GemmPlan::launch(Ctx& x, const Bases& b, int batch, int prec, bool out_f64,
   if (ntiles == 0) return;
   if (prec == DMRG_FP64 && !x.fp64_mfma) {
     if (role == 1) x.mark_main(true);
-    launch_grouped_gemm_f64(tiles.as<GTile>(), ntiles, jobs.as<GJob>(), con.as<GContrib>(), b, batch, x.stream);
+    launch_grouped_gemm_f64(tiles.as<GTile>(), ntiles, jobs.as<GJob>(), con.as<GContrib>(), gat.as<int>(), b, batch,
+                            x.stream);
     if (role == 1) x.mark_main(false);
     DMRG_HIP(hipGetLastError());
     return;
@@ -94,7 +95,7 @@ void GemmPlan::launch(Ctx& x, const Bases& b, int batch, int prec, bool out_f64,
   }
   if (role == 1) x.mark_main(true);
   launch_grouped_gemm(prec, out_f64, role, F.shape, F.tiles.as<GTile>(), F.ntiles, jobs.as<GJob>(),
-                      con.as<GContrib>(), F.segs.as<GSeg>(), F.nslots, part, b, bo, fold, batch, x.stream);
+                      con.as<GContrib>(), gat.as<int>(), F.segs.as<GSeg>(), F.nslots, part, b, bo, fold, batch, x.stream);
   if (role == 1) x.mark_main(false);
   launch_reduce_partials(prec, out_f64, F.shape, F.red.as<GRed>(), F.nred, jobs.as<GJob>(), F.nslots, part, bo, fold,
                          batch, x.stream);
@@ -286,7 +287,8 @@ struct LinCombBuilder {
   }
 };
 
-void make_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<std::vector<GContrib>>& per) {
+void make_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<std::vector<GContrib>>& per,
+                    const std::vector<int>& gather = {}) {
   std::vector<GContrib> con;
   std::vector<GTile> tiles;
   double fl = 0;
@@ -314,39 +316,126 @@ void make_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<st
       if (!(con[c].flags & GC_A_IDENTITY)) P.mask_a |= 1u << con[c].baseA;
       P.mask_b |= 1u << con[c].baseB;
     }
+    const int gf = jobs[j].flags & (GJ_GATHER_A | GJ_GATHER_B);
+    if (gf) {
+      // a gathered operand: one contribution, rows of A contiguous in k
+      // (gather A) or columns of B contiguous in k (gather B)
+      DMRG_REQUIRE(gf != (GJ_GATHER_A | GJ_GATHER_B) && jobs[j].c1 - jobs[j].c0 == 1, DMRG_ERR_INTERNAL,
+                   "gathered job with several contributions");
+      const GContrib& c = con[jobs[j].c0];
+      const long len = gf == GJ_GATHER_A ? jobs[j].m : jobs[j].n;
+      DMRG_REQUIRE(gf == GJ_GATHER_A ? !(c.flags & (GC_TRANS_A | GC_A_IDENTITY)) : (c.flags & GC_TRANS_B) != 0,
+                   DMRG_ERR_INTERNAL, "gathered operand not contiguous in k");
+      DMRG_REQUIRE(jobs[j].pad >= 0 && long(jobs[j].pad) + len <= long(gather.size()), DMRG_ERR_INTERNAL,
+                   "gather entries out of range");
+    }
   }
   {
     std::set<std::pair<int, long>> seen_a, seen_b;
     for (size_t j = 0; j < jobs.size(); ++j)
       for (int c = jobs[j].c0; c < jobs[j].c1; ++c) {
-        if (!(con[c].flags & GC_A_IDENTITY) && seen_a.insert({con[c].baseA, con[c].offA}).second)
+        // a gathered operand has its own rows / columns (offset 0 is not a key)
+        const bool ga = jobs[j].flags & GJ_GATHER_A, gb = jobs[j].flags & GJ_GATHER_B;
+        if (!(con[c].flags & GC_A_IDENTITY) && (ga || seen_a.insert({con[c].baseA, con[c].offA}).second))
           P.elems_a += double(jobs[j].m) * con[c].k;
-        if (seen_b.insert({con[c].baseB, con[c].offB}).second) P.elems_b += double(con[c].k) * jobs[j].n;
+        if (gb || seen_b.insert({con[c].baseB, con[c].offB}).second) P.elems_b += double(con[c].k) * jobs[j].n;
       }
   }
   upload(x, P.tiles, tiles);
   upload(x, P.jobs, jobs);
   upload(x, P.con, con);
+  upload(x, P.gat, gather);
   P.ntiles = int(tiles.size());
   P.flops = fl;
 }
+
+// Stage-1 items that share one operand are merged into one job whose other
+// operand is gathered: rows stacked (merge 1, the products sit one below the
+// other with their own leading dimension) or columns side by side (merge 2,
+// the products become column ranges of one matrix whose leading dimension is
+// the total width).  A merged job fills its tiles across many small products
+// instead of padding each to a tile.  Merged groups are capped at an eighth
+// of the workspace budget so that chunks stay well packed.
+namespace {
+struct T1Group {
+  int merge = 0;
+  std::vector<int> items;
+  long elems = 0, len = 0;  // workspace elements; stacked rows / total columns
+};
+
+bool mergeable(const TwoStageBuilder::T1& t) {
+  const GContrib& c = t.con;
+  if (t.merge == 1) {
+    if (c.flags & (GC_TRANS_A | GC_A_IDENTITY)) return false;
+    return c.offA >= 0 && c.offA + long(t.job.m - 1) * c.lda + c.k <= 0x7fffffffL;
+  }
+  if (t.merge == 2) {
+    if (!(c.flags & GC_TRANS_B)) return false;
+    return c.offB >= 0 && c.offB + long(t.job.n - 1) * c.ldb + c.k <= 0x7fffffffL;
+  }
+  return false;
+}
+}  // namespace
 
 // Split the stage-1 items into chunks whose workspace fits the budget and
 // build the two device lists of each chunk.
 void finish_two_stage(Ctx& x, TwoStageBuilder& B, TwoStagePlan& P, bool overwrite) {
   const long budget = x.t_budget_per_vec;
-  std::vector<int> chunk_of(B.t1.size());
-  std::vector<long> toff(B.t1.size());
+  const long cap = std::max(1L, budget / 8);
+  // group the items: key = the shared operand and everything a merged job
+  // has in common (flags, inner length, leading dimensions, the unmerged
+  // output dimension, alpha)
+  typedef std::tuple<int, int, int, int, long, int, int, int, int, double> GKey;
+  std::map<GKey, int> open;
+  std::vector<T1Group> groups;
+  for (size_t k = 0; k < B.t1.size(); ++k) {
+    const TwoStageBuilder::T1& t = B.t1[k];
+    const int mg = mergeable(t) ? t.merge : 0;
+    int gi = -1;
+    GKey key;
+    if (mg) {
+      const GContrib& c = t.con;
+      key = mg == 1 ? GKey(1, c.flags, c.k, c.baseB, c.offB, c.ldb, c.baseA, c.lda, t.job.n, c.alpha)
+                    : GKey(2, c.flags, c.k, c.baseA, c.offA, c.lda, c.baseB, c.ldb, t.job.m, c.alpha);
+      auto it = open.find(key);
+      if (it != open.end() && groups[it->second].elems + t.elems <= cap) gi = it->second;
+    }
+    if (gi < 0) {
+      groups.emplace_back();
+      gi = int(groups.size()) - 1;
+      groups[gi].merge = mg;
+      if (mg) open[key] = gi;
+    }
+    T1Group& g = groups[gi];
+    g.items.push_back(int(k));
+    g.elems += t.elems;
+    g.len += mg == 1 ? t.job.m : t.job.n;
+  }
+  std::vector<int> chunk_of(B.t1.size()), gchunk(groups.size());
+  std::vector<long> toff(B.t1.size()), ldt(B.t1.size(), 0), goff(groups.size());
   long used = 0;
   int nch = 0;
-  for (size_t k = 0; k < B.t1.size(); ++k) {
-    if (k == 0 || (used + B.t1[k].elems > budget && used > 0)) {
+  for (size_t q = 0; q < groups.size(); ++q) {
+    if (q == 0 || (used + groups[q].elems > budget && used > 0)) {
       ++nch;
       used = 0;
     }
-    chunk_of[k] = nch - 1;
-    toff[k] = used;
-    used += B.t1[k].elems;
+    gchunk[q] = nch - 1;
+    goff[q] = used;
+    long pos = 0;  // row (merge 1) or column (merge 2) of each item in its group
+    for (int k : groups[q].items) {
+      const TwoStageBuilder::T1& t = B.t1[k];
+      chunk_of[k] = nch - 1;
+      if (groups[q].merge == 2) {
+        toff[k] = used + pos;
+        ldt[k] = groups[q].len;
+        pos += t.job.n;
+      } else {
+        toff[k] = used + pos * t.job.ldc;
+        pos += t.job.m;
+      }
+    }
+    used += groups[q].elems;
     P.t_per_vec = std::max(P.t_per_vec, used);
   }
   if (nch == 0) nch = 1;
@@ -356,16 +445,49 @@ void finish_two_stage(Ctx& x, TwoStageBuilder& B, TwoStagePlan& P, bool overwrit
   for (int c = 0; c < nch; ++c) {
     std::vector<GJob> j1;
     std::vector<std::vector<GContrib>> p1;
-    for (size_t k = 0; k < B.t1.size(); ++k) {
-      if (chunk_of[k] != c) continue;
-      GJob j = B.t1[k].job;
-      j.offC = toff[k];
+    std::vector<int> gat;
+    for (size_t q = 0; q < groups.size(); ++q) {
+      if (gchunk[q] != c) continue;
+      const T1Group& g = groups[q];
+      if (g.merge == 0 || g.items.size() == 1) {
+        for (int k : g.items) {
+          GJob j = B.t1[k].job;
+          j.offC = toff[k];
+          j.baseC = B_T;
+          j.flags = 0;
+          j1.push_back(j);
+          p1.push_back({B.t1[k].con});
+        }
+        continue;
+      }
+      const TwoStageBuilder::T1& f = B.t1[g.items.front()];
+      GJob j = f.job;
+      GContrib con = f.con;
+      j.offC = goff[q];
       j.baseC = B_T;
-      j.flags = 0;
+      j.pad = int(gat.size());
+      if (g.merge == 1) {
+        j.m = int(g.len);
+        j.flags = GJ_GATHER_A;
+        con.offA = 0;
+        for (int k : g.items) {
+          const TwoStageBuilder::T1& t = B.t1[k];
+          for (int r = 0; r < t.job.m; ++r) gat.push_back(int(t.con.offA + long(r) * t.con.lda));
+        }
+      } else {
+        j.n = int(g.len);
+        j.ldc = int(g.len);
+        j.flags = GJ_GATHER_B;
+        con.offB = 0;
+        for (int k : g.items) {
+          const TwoStageBuilder::T1& t = B.t1[k];
+          for (int r = 0; r < t.job.n; ++r) gat.push_back(int(t.con.offB + long(r) * t.con.ldb));
+        }
+      }
       j1.push_back(j);
-      p1.push_back({B.t1[k].con});
+      p1.push_back({con});
     }
-    make_gemm_plan(x, P.chunks[c].first, j1, p1);
+    make_gemm_plan(x, P.chunks[c].first, j1, p1, gat);
     std::vector<GJob> j2;
     std::vector<std::vector<GContrib>> p2;
     std::map<std::pair<int, long>, int> job_of;
@@ -394,6 +516,7 @@ void finish_two_stage(Ctx& x, TwoStageBuilder& B, TwoStagePlan& P, bool overwrit
       if (s.t1 >= 0) {
         g.offB += toff[s.t1];
         g.baseB = B_T;
+        if (ldt[s.t1]) g.ldb = int(ldt[s.t1]);
       }
       p2[job(s.baseC, s.offC, s.ldc, s.m, s.n)].push_back(g);
     }
@@ -405,8 +528,9 @@ void finish_two_stage(Ctx& x, TwoStageBuilder& B, TwoStagePlan& P, bool overwrit
 
 }  // namespace
 
-void build_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<std::vector<GContrib>>& per) {
-  make_gemm_plan(x, P, jobs, per);
+void build_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<std::vector<GContrib>>& per,
+                     const std::vector<int>& gather) {
+  make_gemm_plan(x, P, jobs, per, gather);
 }
 
 void print_plan_stats(const char* what, int i, int width, const ContractionPlan& P) {
@@ -872,6 +996,7 @@ ContractionPlan& Ctx::renorm_plan(int dir, int i, const OpSet& src, const OpSet&
             auto f = TB.t1_of.find(tk);
             if (f == TB.t1_of.end()) {
               TwoStageBuilder::T1 t{};
+              t.merge = 1;  // X blocks share A_ket: stack their rows
               t.elems = long(bl.dim[ap]) * S.blk[b].cols;
               t.job.ldc = S.blk[b].cols;
               t.job.m = bl.dim[ap];
@@ -912,6 +1037,7 @@ ContractionPlan& Ctx::renorm_plan(int dir, int i, const OpSet& src, const OpSet&
             auto f = TB.t1_of.find(tk);
             if (f == TB.t1_of.end()) {
               TwoStageBuilder::T1 t{};
+              t.merge = 1;  // Z blocks share R_ket: stack their rows
               t.elems = long(br.dim[cp]) * S.blk[b].rows;
               t.job.ldc = S.blk[b].rows;
               t.job.m = br.dim[cp];
@@ -1186,6 +1312,7 @@ ContractionPlan& Ctx::sigma_plan(int i, int width, const OpSet& X, const OpSet& 
           if (f == TB.t1_of.end()) {
             // T(Z, a, n, c) = C(a,n,c) Z(c'<-c)^T  (m_a x m_c')
             TwoStageBuilder::T1 t1{};
+            t1.merge = 2;  // the Z blocks share C: their products side by side
             t1.elems = long(S.blk[b].rows) * br.dim[cp];
             t1.job.ldc = br.dim[cp];
             t1.job.m = S.blk[b].rows;

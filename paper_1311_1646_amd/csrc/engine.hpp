@@ -77,7 +77,7 @@ struct OpSet {
 
 // Device-resident grouped-GEMM list.
 struct GemmPlan {
-  DBuf tiles, jobs, con;
+  DBuf tiles, jobs, con, gat;  // gat: gather entries of jobs with a gathered operand
   int ntiles = 0;
   double flops = 0;  // per batch entry
   // host copies for batch folding: job shapes and the bases each operand
@@ -106,7 +106,8 @@ struct GemmPlan {
               const Bases* bout = nullptr, int role = 0) const;
 };
 
-void build_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<std::vector<GContrib>>& per);
+void build_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<std::vector<GContrib>>& per,
+                     const std::vector<int>& gather = {});
 
 struct LinCombPlan {
   DBuf t, s, d, g, u, coef;
@@ -119,7 +120,10 @@ struct LinCombPlan {
 // Host-side builder of a two-stage contraction (stage 1 writes workspace
 // blocks T, stage 2 consumes them), chunked so that T fits a budget.
 struct TwoStageBuilder {
-  struct T1 { long elems; GJob job; GContrib con; };
+  // merge: 0 alone; 1 rows may be stacked with other items sharing op(B)
+  // (gathered A rows); 2 columns may be placed side by side with other
+  // items sharing op(A) (gathered B columns)
+  struct T1 { long elems; GJob job; GContrib con; int merge; };
   struct S2 { int t1; long offC; int baseC, ldc, m, n; GContrib con; };
   std::vector<T1> t1;
   std::map<std::tuple<int, long, int>, int> t1_of;  // (base, offset, block) -> item

@@ -20,7 +20,8 @@ __device__ __forceinline__ double* bptr(const Bases& b, int base, long off, int 
 // of the job is streamed through LDS in K-chunks of 16.
 __global__ __launch_bounds__(NT) void grouped_gemm_f64_kernel(const GTile* __restrict__ tiles,
                                                                 const GJob* __restrict__ jobs,
-                                                                const GContrib* __restrict__ con, Bases bs) {
+                                                                const GContrib* __restrict__ con,
+                                                                const int* __restrict__ gather, Bases bs) {
   __shared__ double As[BK][BM + 1];
   __shared__ double Bs[BK][BN + 1];
   const GTile t = tiles[blockIdx.x];
@@ -28,6 +29,7 @@ __global__ __launch_bounds__(NT) void grouped_gemm_f64_kernel(const GTile* __res
   const int bz = blockIdx.y;
   const int row0 = t.tm * BM, col0 = t.tn * BN;
   const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  const bool ga = J.flags & GJ_GATHER_A, gb = J.flags & GJ_GATHER_B;
   double acc[4][4];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -47,6 +49,7 @@ __global__ __launch_bounds__(NT) void grouped_gemm_f64_kernel(const GTile* __res
         double v = 0.0;
         if (gr < J.m && gk < c.k) {
           if (aid) v = (gr == gk) ? 1.0 : 0.0;
+          else if (ga) v = A[long(gather[J.pad + gr]) + gk];
           else v = ta ? A[long(gk) * c.lda + gr] : A[long(gr) * c.lda + gk];
         }
         As[kk][r] = v * c.alpha;
@@ -56,7 +59,8 @@ __global__ __launch_bounds__(NT) void grouped_gemm_f64_kernel(const GTile* __res
         if (tb) { cc = e / BK; kk = e % BK; } else { kk = e / BN; cc = e % BN; }
         const int gk = k0 + kk, gc = col0 + cc;
         double v = 0.0;
-        if (gk < c.k && gc < J.n) v = tb ? B[long(gc) * c.ldb + gk] : B[long(gk) * c.ldb + gc];
+        if (gk < c.k && gc < J.n)
+          v = gb ? B[long(gather[J.pad + gc]) + gk] : (tb ? B[long(gc) * c.ldb + gk] : B[long(gk) * c.ldb + gc]);
         Bs[kk][cc] = v;
       }
       __syncthreads();
@@ -372,10 +376,10 @@ __global__ __launch_bounds__(256) void gep_kernel(const double* H, const double*
 
 }  // namespace
 
-void launch_grouped_gemm_f64(const GTile* tiles, int ntiles, const GJob* jobs, const GContrib* con, const Bases& b,
-                             int batch, hipStream_t s) {
+void launch_grouped_gemm_f64(const GTile* tiles, int ntiles, const GJob* jobs, const GContrib* con,
+                             const int* gather, const Bases& b, int batch, hipStream_t s) {
   if (ntiles <= 0 || batch <= 0) return;
-  hipLaunchKernelGGL(grouped_gemm_f64_kernel, dim3(ntiles, batch), dim3(NT), 0, s, tiles, jobs, con, b);
+  hipLaunchKernelGGL(grouped_gemm_f64_kernel, dim3(ntiles, batch), dim3(NT), 0, s, tiles, jobs, con, gather, b);
 }
 
 template <class T>

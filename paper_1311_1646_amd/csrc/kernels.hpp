@@ -32,12 +32,19 @@ struct GContrib {
   double alpha;
 };
 
-enum : int { GJ_ACCUMULATE = 1 };
+// Gathered operands: with GJ_GATHER_A row i of op(A) (A not transposed,
+// rows contiguous in k) starts at element gather[pad + i] of A's base; with
+// GJ_GATHER_B column j of op(B) (B transposed, columns contiguous in k)
+// starts at gather[pad + j] of B's base.  The contribution's own offset of
+// that operand is then unused (zero).  A job with a gathered operand has one
+// contribution: it stacks many small products that share the other operand
+// into one matrix, so its tiles are filled across them.
+enum : int { GJ_ACCUMULATE = 1, GJ_GATHER_A = 2, GJ_GATHER_B = 4 };
 struct GJob {
   long offC;
   int baseC, ldc, m, n;
   int c0, c1;  // contribution range
-  int flags, pad;
+  int flags, pad;  // pad: start of the job's gather entries
 };
 struct GTile {
   int job, tm, tn, pad;
@@ -47,7 +54,7 @@ struct GTile {
 // contributions of its job in order (deterministic, no atomics).  grid.y =
 // batch entries.
 void launch_grouped_gemm_f64(const GTile* tiles, int ntiles, const GJob* jobs, const GContrib* con,
-                             const Bases& b, int batch, hipStream_t s);
+                             const int* gather, const Bases& b, int batch, hipStream_t s);
 
 // Linear combinations out = [out +] sum_j c_j src_j.
 struct LCTarget {

@@ -77,6 +77,7 @@ template <int TM, int TN> struct Lds<2, TM, TN> {
 template <int TM, int TN> struct TileMap {
   int rv[TM], ri[TM];  // batch entry / block row of each tile row (-1 outside)
   int cv[TN], cj[TN];  // batch entry / block column of each tile column
+  int ga[TM], gb[TN];  // gathered row / column offsets (jobs with a gathered operand)
 };
 
 // Global-memory pointers: loads through them are global loads (counted by
@@ -110,7 +111,8 @@ struct Stage {
   int ck, flags;
   T alpha;
 
-  __device__ __forceinline__ void begin(const GContrib& c, const Bases& bs, const TileMap<TM, TN>& m, int tid) {
+  __device__ __forceinline__ void begin(const GContrib& c, const Bases& bs, const TileMap<TM, TN>& m, int tid,
+                                        int jflags) {
     flags = c.flags;
     ck = c.k;
     lda = c.lda;
@@ -133,7 +135,8 @@ struct Stage {
 #pragma unroll
         for (int r = 0; r < RA; ++r) {
           const int run = tid + r * NTH, i = run / (TK / 4), ii = m.ri[i];
-          pa[r] = ii < 0 ? nullptr : A + long(m.rv[i]) * sa + long(ii) * c.lda + 4 * (run % (TK / 4));
+          const long ro = (jflags & GJ_GATHER_A) ? long(m.ga[i]) : long(ii) * c.lda;
+          pa[r] = ii < 0 ? nullptr : A + long(m.rv[i]) * sa + ro + 4 * (run % (TK / 4));
         }
       } else {
 #pragma unroll
@@ -163,7 +166,8 @@ struct Stage {
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         const int run = tid + r * NTH, j = run / (TK / 4), jj = m.cj[j];
-        pb[r] = jj < 0 ? nullptr : B + long(m.cv[j]) * sb + long(jj) * c.ldb + 4 * (run % (TK / 4));
+        const long co = (jflags & GJ_GATHER_B) ? long(m.gb[j]) : long(jj) * c.ldb;
+        pb[r] = jj < 0 ? nullptr : B + long(m.cv[j]) * sb + co + 4 * (run % (TK / 4));
       }
     }
   }
@@ -406,17 +410,21 @@ __device__ __forceinline__ void write_partial(const Acc<MODE, BM, BN>& acc, PT* 
 // entries, 1 = batch folded into N, 2 = batch folded into M.
 template <int TM, int TN>
 __device__ __forceinline__ void tile_maps(TileMap<TM, TN>& m, const GJob& J, int tm, int tn, int fold, int batch,
-                                          int tid) {
+                                          int tid, const int* __restrict__ gather) {
   if (tid < TM) {
     const int g = tm * TM + tid;
     const int mb = fold == 2 ? J.m * batch : J.m;
+    const int ri = g < mb ? (fold == 2 ? g % J.m : g) : -1;
     m.rv[tid] = fold == 2 ? g / J.m : (fold == 0 ? int(blockIdx.y) : 0);
-    m.ri[tid] = g < mb ? (fold == 2 ? g % J.m : g) : -1;
+    m.ri[tid] = ri;
+    m.ga[tid] = (gather && (J.flags & GJ_GATHER_A) && ri >= 0) ? gather[J.pad + ri] : 0;
   } else if (tid < TM + TN) {
     const int u = tid - TM, g = tn * TN + u;
     const int nb = fold == 1 ? J.n * batch : J.n;
+    const int cj = g < nb ? (fold == 1 ? g % J.n : g) : -1;
     m.cv[u] = fold == 1 ? g / J.n : (fold == 0 ? int(blockIdx.y) : 0);
-    m.cj[u] = g < nb ? (fold == 1 ? g % J.n : g) : -1;
+    m.cj[u] = cj;
+    m.gb[u] = (gather && (J.flags & GJ_GATHER_B) && cj >= 0) ? gather[J.pad + cj] : 0;
   }
 }
 
@@ -424,7 +432,8 @@ __device__ __forceinline__ void tile_maps(TileMap<TM, TN>& m, const GJob& J, int
 // the double-buffered LDS pipeline, then the result or the partial sum.
 template <int MODE, int TM, int TN>
 __device__ __forceinline__ void do_tile(int ti, const GTile* __restrict__ tiles, const GJob* __restrict__ jobs,
-                                        const GContrib* __restrict__ con, const GSeg* __restrict__ segs, int nslots,
+                                        const GContrib* __restrict__ con, const int* __restrict__ gather,
+                                        const GSeg* __restrict__ segs, int nslots,
                                         typename Cfg<MODE>::T* __restrict__ partial, const Bases& bout, int fold,
                                         int batch, int out_f64, Lds<MODE, TM, TN>& s, TileMap<TM, TN>& m,
                                         const Bases& sb) {
@@ -441,14 +450,14 @@ __device__ __forceinline__ void do_tile(int ti, const GTile* __restrict__ tiles,
     c1 = g.c1;
     slot = g.slot;
   }
-  tile_maps<TM, TN>(m, J, t.tm, t.tn, fold, batch, tid);
+  tile_maps<TM, TN>(m, J, t.tm, t.tn, fold, batch, tid, gather);
   __syncthreads();
   Acc<MODE, BM, BN> acc;
   acc.zero();
   if (c0 < c1) {
     Stage<MODE, TM, TN> st;
     int ci = c0, k0 = 0, buf = 0;
-    st.begin(con[ci], sb, m, tid);
+    st.begin(con[ci], sb, m, tid, J.flags);
     st.load(0, tid);
     for (;;) {
       const int ck = st.ck, fl = st.flags;
@@ -462,7 +471,7 @@ __device__ __forceinline__ void do_tile(int ti, const GTile* __restrict__ tiles,
       }
       const bool more = nci < c1;
       if (more) {
-        if (nci != ci) st.begin(con[nci], sb, m, tid);
+        if (nci != ci) st.begin(con[nci], sb, m, tid, J.flags);
         st.load(nk0, tid);
       }
       mma<TM, TN, BM, BN>(acc, s, buf, kv, wm, wn, lane);
@@ -493,7 +502,7 @@ template <int MODE> struct Persist {
 template <int MODE, int ROLE, int TM, int TN>
 __global__ __launch_bounds__(NTH, Persist<MODE>::waves) void ggemm_mfma_kernel(
     const GTile* __restrict__ tiles, int ntiles, const GJob* __restrict__ jobs, const GContrib* __restrict__ con,
-    const GSeg* __restrict__ segs, int nslots, typename Cfg<MODE>::T* __restrict__ partial, Bases bs, Bases bout,
+    const int* __restrict__ gather, const GSeg* __restrict__ segs, int nslots, typename Cfg<MODE>::T* __restrict__ partial, Bases bs, Bases bout,
     int fold, int batch, int out_f64) {
   __shared__ Lds<MODE, TM, TN> s;
   __shared__ TileMap<TM, TN> m;
@@ -506,10 +515,12 @@ __global__ __launch_bounds__(NTH, Persist<MODE>::waves) void ggemm_mfma_kernel(
   if constexpr (Persist<MODE>::on) {
     for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
       __syncthreads();  // the previous tile is done with the maps
-      do_tile<MODE, TM, TN>(ti, tiles, jobs, con, segs, nslots, partial, bout, fold, batch, out_f64, s, m, sb);
+      do_tile<MODE, TM, TN>(ti, tiles, jobs, con, gather, segs, nslots, partial, bout, fold, batch, out_f64, s, m,
+                            sb);
     }
   } else {
-    do_tile<MODE, TM, TN>(blockIdx.x, tiles, jobs, con, segs, nslots, partial, bout, fold, batch, out_f64, s, m, sb);
+    do_tile<MODE, TM, TN>(blockIdx.x, tiles, jobs, con, gather, segs, nslots, partial, bout, fold, batch, out_f64, s,
+                          m, sb);
   }
 }
 
@@ -524,7 +535,7 @@ __global__ __launch_bounds__(NTH) void reduce_partials_kernel(const GRed* __rest
   const GRed r = red[blockIdx.x];
   const GJob J = jobs[r.job];
   const int tid = threadIdx.x;
-  tile_maps<TM, TN>(m, J, r.tm, r.tn, fold, batch, tid);
+  tile_maps<TM, TN>(m, J, r.tm, r.tn, fold, batch, tid, nullptr);
   __syncthreads();
   const long entry = fold == 0 ? long(blockIdx.y) : 0;
   const PT* P = partial + (entry * nslots + r.slot0) * long(TM * TN);
@@ -551,31 +562,30 @@ __global__ void convert_f64_f32_kernel(const double* __restrict__ in, float* __r
 
 template <int MODE, int TM, int TN>
 void launch_shape(int role, dim3 grid, hipStream_t s, const GTile* tiles, int ntiles, const GJob* jobs,
-                  const GContrib* con,
-                  const GSeg* segs, int nslots, void* partial, const Bases& b, const Bases& bout, int fold, int batch,
+                  const GContrib* con, const int* gather, const GSeg* segs, int nslots, void* partial, const Bases& b, const Bases& bout, int fold, int batch,
                   int of) {
   typedef typename Cfg<MODE>::T T;
   T* P = static_cast<T*>(partial);
   if (role == 0)
-    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 0, TM, TN>), grid, dim3(NTH), 0, s, tiles, ntiles, jobs, con, segs,
-                       nslots, P, b, bout, fold, batch, of);
+    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 0, TM, TN>), grid, dim3(NTH), 0, s, tiles, ntiles, jobs, con,
+                       gather, segs, nslots, P, b, bout, fold, batch, of);
   else
-    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 1, TM, TN>), grid, dim3(NTH), 0, s, tiles, ntiles, jobs, con, segs,
-                       nslots, P, b, bout, fold, batch, of);
+    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 1, TM, TN>), grid, dim3(NTH), 0, s, tiles, ntiles, jobs, con,
+                       gather, segs, nslots, P, b, bout, fold, batch, of);
 }
 
 template <int MODE>
 void launch_mode(int shape, int role, dim3 grid, hipStream_t s, const GTile* tiles, int ntiles, const GJob* jobs,
-                 const GContrib* con, const GSeg* segs, int nslots, void* partial, const Bases& b, const Bases& bout,
+                 const GContrib* con, const int* gather, const GSeg* segs, int nslots, void* partial, const Bases& b, const Bases& bout,
                  int fold, int batch, int of) {
   if (shape == TILE_128x64)
-    launch_shape<MODE, 128, 64>(role, grid, s, tiles, ntiles, jobs, con, segs, nslots, partial, b, bout, fold,
+    launch_shape<MODE, 128, 64>(role, grid, s, tiles, ntiles, jobs, con, gather, segs, nslots, partial, b, bout, fold,
                                 batch, of);
   else if (shape == TILE_64x128)
-    launch_shape<MODE, 64, 128>(role, grid, s, tiles, ntiles, jobs, con, segs, nslots, partial, b, bout, fold,
+    launch_shape<MODE, 64, 128>(role, grid, s, tiles, ntiles, jobs, con, gather, segs, nslots, partial, b, bout, fold,
                                 batch, of);
   else
-    launch_shape<MODE, 64, 64>(role, grid, s, tiles, ntiles, jobs, con, segs, nslots, partial, b, bout, fold,
+    launch_shape<MODE, 64, 64>(role, grid, s, tiles, ntiles, jobs, con, gather, segs, nslots, partial, b, bout, fold,
                                batch, of);
 }
 
@@ -592,8 +602,8 @@ int tile_rows(int shape) { return shape == TILE_128x64 ? 128 : 64; }
 int tile_cols(int shape) { return shape == TILE_64x128 ? 128 : 64; }
 
 void launch_grouped_gemm(int prec, bool out_f64, int role, int shape, const GTile* tiles, int ntiles,
-                         const GJob* jobs, const GContrib* con, const GSeg* segs, int nslots, void* partial,
-                         const Bases& b, const Bases& bout, int fold, int batch, hipStream_t s) {
+                         const GJob* jobs, const GContrib* con, const int* gather, const GSeg* segs, int nslots,
+                         void* partial, const Bases& b, const Bases& bout, int fold, int batch, hipStream_t s) {
   if (ntiles <= 0 || batch <= 0) return;
   // FP64 runs persistent workgroups (at most 16 per CU of the 256, a few
   // rounds of the resident capacity); the others one workgroup per tile
@@ -603,13 +613,13 @@ void launch_grouped_gemm(int prec, bool out_f64, int role, int shape, const GTil
   const dim3 grid(gx, per);
   const int of = out_f64 ? 1 : 0;
   if (prec == 0)
-    launch_mode<0>(shape, role, grid, s, tiles, ntiles, jobs, con, segs, nslots, partial, b, bout, fold, batch,
+    launch_mode<0>(shape, role, grid, s, tiles, ntiles, jobs, con, gather, segs, nslots, partial, b, bout, fold, batch,
                    1);
   else if (prec == 1)
-    launch_mode<1>(shape, role, grid, s, tiles, ntiles, jobs, con, segs, nslots, partial, b, bout, fold, batch,
+    launch_mode<1>(shape, role, grid, s, tiles, ntiles, jobs, con, gather, segs, nslots, partial, b, bout, fold, batch,
                    of);
   else
-    launch_mode<2>(shape, role, grid, s, tiles, ntiles, jobs, con, segs, nslots, partial, b, bout, fold, batch,
+    launch_mode<2>(shape, role, grid, s, tiles, ntiles, jobs, con, gather, segs, nslots, partial, b, bout, fold, batch,
                    of);
 }
 

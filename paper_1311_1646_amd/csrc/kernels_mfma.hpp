@@ -35,9 +35,11 @@ int tile_cols(int shape);
 // two instantiations are the same code; the tag separates them in profiles).
 // Tiles index shape-sized tiles; partial slots hold dense rows x columns
 // tiles of the operand type.
+// gather: entries of the jobs with a gathered operand (may be null when no
+// job has one).
 void launch_grouped_gemm(int prec, bool out_f64, int role, int shape, const GTile* tiles, int ntiles,
-                         const GJob* jobs, const GContrib* con, const GSeg* segs, int nslots, void* partial,
-                         const Bases& b, const Bases& bout, int fold, int batch, hipStream_t s);
+                         const GJob* jobs, const GContrib* con, const int* gather, const GSeg* segs, int nslots,
+                         void* partial, const Bases& b, const Bases& bout, int fold, int batch, hipStream_t s);
 void launch_reduce_partials(int prec, bool out_f64, int shape, const GRed* red, int nred, const GJob* jobs,
                             int nslots, const void* partial, const Bases& bout, int fold, int batch, hipStream_t s);
 
