@@ -20,8 +20,10 @@ ARCH = os.environ.get("DMRG_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(HERE, "..", "include")]
 # Packed FP32 instructions are disabled for all device code.
+# Matrix-core results are kept in ordinary VGPRs (no AGPR copies of the
+# accumulators around every K-chunk, and fewer registers per wave).
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-          "-munsafe-fp-atomics"]
+          "-munsafe-fp-atomics", "-mllvm", "-amdgpu-mfma-vgpr-form"]
 LIBS = ["-lrocsolver", "-lrocblas"]
 
 

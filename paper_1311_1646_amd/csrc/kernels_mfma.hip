@@ -57,14 +57,25 @@ template <> struct Cfg<2> {  // BF16x3
   static constexpr int TK = 32, MB = 32;
 };
 
-// LDS images of one chunk.  FP64/FP32: a[i][k], b[j][k] (row per output
-// index, padded by one element).  BF16x3: hi and lo parts, rows padded to a
-// multiple of 16 bytes so that eight consecutive k load as one 128-bit read.
+// LDS images of one chunk, one row per output index (tile row of op(A),
+// tile column of op(B)), written four consecutive k at a time.
+//   FP64  : a[i][k], rows padded by one element.
+//   FP32  : a[i][p(k)] with p(k) = 16 (k & 1) + (k >> 1): the 32x32x2 product
+//           at step s takes k = 2s + h in lane half h, so the sixteen values
+//           a lane needs over a chunk are contiguous (four 128-bit reads);
+//           rows padded to 36 elements (16-byte aligned).
+//   BF16x3: hi and lo parts, k contiguous, rows padded to a multiple of 16
+//           bytes so that eight consecutive k load as one 128-bit read.
 template <int MODE, int TM, int TN> struct Lds {
   typedef typename Cfg<MODE>::T T;
   static constexpr int TK = Cfg<MODE>::TK;
   T a[2][TM][TK + 1];
   T b[2][TN][TK + 1];
+};
+template <int TM, int TN> struct Lds<1, TM, TN> {
+  static constexpr int TK = 32, LD = TK + 4;
+  alignas(16) float a[2][TM][LD];
+  alignas(16) float b[2][TN][LD];
 };
 template <int TM, int TN> struct Lds<2, TM, TN> {
   static constexpr int TK = 32, LD = TK + 8;
@@ -85,27 +96,46 @@ template <int TM, int TN> struct TileMap {
 // multiply while the next chunk is in flight.
 template <class T> using gptr = const __attribute__((address_space(1))) T*;
 
+// Four consecutive k (k0 a multiple of 4) of one LDS row.
+__device__ __forceinline__ void put4_f32(float* rowp, int k0, const float* v) {
+  // p(k0) = k0/2 (even k), p(k0 + 1) = 16 + k0/2 (odd k)
+  *reinterpret_cast<float2*>(rowp + (k0 >> 1)) = float2{v[0], v[2]};
+  *reinterpret_cast<float2*>(rowp + 16 + (k0 >> 1)) = float2{v[1], v[3]};
+}
+__device__ __forceinline__ void put4_bf16(__bf16* hip, __bf16* lop, int k0, const float* v) {
+  typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+  bf16x4 h, l;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    h[e] = static_cast<__bf16>(v[e]);
+    l[e] = static_cast<__bf16>(v[e] - static_cast<float>(h[e]));
+  }
+  *reinterpret_cast<bf16x4*>(hip + k0) = h;
+  *reinterpret_cast<bf16x4*>(lop + k0) = l;
+}
+
+// Staging of one K-chunk of op(A) (TM x TK) and op(B) (TK x TN).  Each
+// thread holds TM*TK/NTH (resp. TN*TK/NTH) elements as runs of four
+// consecutive k of one row, in one of two maps:
+//   k-map   (operand contiguous in k: A not transposed, B transposed,
+//            identity A): run q = tid + q*NTH covers row q/(TK/4),
+//            k 4*(q%(TK/4)) .. +3; one pointer per run, one wide load.
+//   row-map (operand contiguous along the tile: A transposed, B not
+//            transposed): the thread owns row u = tid % T and the runs
+//            k = 4g + 4Gq .. +3 with g = tid / T, G = NTH / T; one pointer
+//            per thread, lanes of a wave read consecutive addresses.
+// op() transposition, alpha and the zero fill outside the block are applied
+// here; rows outside the block have a null pointer.
 template <int MODE, int TM, int TN>
 struct Stage {
   typedef typename Cfg<MODE>::T T;
   static constexpr int TK = Cfg<MODE>::TK;
-  static constexpr int RA = TM * TK / NTH / 4;  // runs of 4 contiguous elements per thread, op(A)
+  static constexpr int RA = TM * TK / NTH / 4;  // runs per thread, op(A)
   static constexpr int RB = TN * TK / NTH / 4;  // and op(B)
+  static constexpr int GA = NTH / TM, GB = NTH / TN;
   T ra[4 * RA], rb[4 * RB];
-  // Each thread stages runs of four elements that are contiguous in memory
-  // (run r = tid + r*NTH), so one address and one bounds test serve four
-  // loads.  The addresses are resolved once per contribution:
-  //   op(A) not transposed (contiguous in k): row r/(TK/4), k 4*(r%(TK/4))+e
-  //       -> pa[r] points at (row, k) of the run
-  //   op(A) transposed (contiguous in rows): k r/(TM/4), rows 4*(r%(TM/4))+e
-  //       -> pa[4r+e] points at each row
-  //   op(B) not transposed (contiguous in columns): k r/(TN/4), cols 4*(r%(TN/4))+e
-  //       -> pb[4r+e] points at each column
-  //   op(B) transposed (contiguous in k): column r/(TK/4), k 4*(r%(TK/4))+e
-  //       -> pb[r] points at (column, k) of the run
-  //   identity A: ia[r] = block row of the run (or -1)
-  gptr<T> pa[4 * RA];
-  gptr<T> pb[4 * RB];
+  gptr<T> pa[RA];
+  gptr<T> pb[RB];
   int ia[RA];
   long lda, ldb;
   int ck, flags;
@@ -120,60 +150,47 @@ struct Stage {
     alpha = T(c.alpha);
     const bool ta = c.flags & GC_TRANS_A, tb = c.flags & GC_TRANS_B, aid = c.flags & GC_A_IDENTITY;
 #pragma unroll
-    for (int q = 0; q < 4 * RA; ++q) pa[q] = nullptr;
+    for (int q = 0; q < RA; ++q) {
+      pa[q] = nullptr;
+      ia[q] = -1;
+    }
 #pragma unroll
-    for (int q = 0; q < 4 * RB; ++q) pb[q] = nullptr;
-#pragma unroll
-    for (int r = 0; r < RA; ++r) ia[r] = -1;
+    for (int q = 0; q < RB; ++q) pb[q] = nullptr;
     if (aid) {
 #pragma unroll
-      for (int r = 0; r < RA; ++r) ia[r] = m.ri[(tid + r * NTH) / (TK / 4)];
+      for (int q = 0; q < RA; ++q) ia[q] = m.ri[(tid + q * NTH) / (TK / 4)];
     } else {
       const gptr<T> A = (gptr<T>)(bs.p[c.baseA]) + c.offA;
       const long sa = bs.stride[c.baseA];
       if (!ta) {
 #pragma unroll
-        for (int r = 0; r < RA; ++r) {
-          const int run = tid + r * NTH, i = run / (TK / 4), ii = m.ri[i];
+        for (int q = 0; q < RA; ++q) {
+          const int run = tid + q * NTH, i = run / (TK / 4), ii = m.ri[i];
           const long ro = (jflags & GJ_GATHER_A) ? long(m.ga[i]) : long(ii) * c.lda;
-          pa[r] = ii < 0 ? nullptr : A + long(m.rv[i]) * sa + ro + 4 * (run % (TK / 4));
+          pa[q] = ii < 0 ? nullptr : A + long(m.rv[i]) * sa + ro + 4 * (run % (TK / 4));
         }
       } else {
-#pragma unroll
-        for (int r = 0; r < RA; ++r) {
-          const int run = tid + r * NTH;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int i = 4 * (run % (TM / 4)) + e, ii = m.ri[i];
-            pa[4 * r + e] = ii < 0 ? nullptr : A + long(m.rv[i]) * sa + ii;
-          }
-        }
+        const int u = tid % TM, ii = m.ri[u];
+        pa[0] = ii < 0 ? nullptr : A + long(m.rv[u]) * sa + ii;
       }
     }
     const gptr<T> B = (gptr<T>)(bs.p[c.baseB]) + c.offB;
     const long sb = bs.stride[c.baseB];
     if (!tb) {
-#pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const int run = tid + r * NTH;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int j = 4 * (run % (TN / 4)) + e, jj = m.cj[j];
-          pb[4 * r + e] = jj < 0 ? nullptr : B + long(m.cv[j]) * sb + jj;
-        }
-      }
+      const int u = tid % TN, jj = m.cj[u];
+      pb[0] = jj < 0 ? nullptr : B + long(m.cv[u]) * sb + jj;
     } else {
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const int run = tid + r * NTH, j = run / (TK / 4), jj = m.cj[j];
+      for (int q = 0; q < RB; ++q) {
+        const int run = tid + q * NTH, j = run / (TK / 4), jj = m.cj[j];
         const long co = (jflags & GJ_GATHER_B) ? long(m.gb[j]) : long(jj) * c.ldb;
-        pb[r] = jj < 0 ? nullptr : B + long(m.cv[j]) * sb + co + 4 * (run % (TK / 4));
+        pb[q] = jj < 0 ? nullptr : B + long(m.cv[j]) * sb + co + 4 * (run % (TK / 4));
       }
     }
   }
 
-  // Four contiguous elements starting at p (k indices k..k+3 checked
-  // against the contribution's inner length).
+  // k-map run: four contiguous elements at p (k .. k+3 checked against the
+  // inner length).
   __device__ __forceinline__ void run4(T* dst, gptr<T> p, int k, T scale) const {
     if (p && k + 3 < ck) {
 #pragma unroll
@@ -183,86 +200,91 @@ struct Stage {
       for (int e = 0; e < 4; ++e) dst[e] = (p && k + e < ck) ? p[e] * scale : T(0);
     }
   }
+  // row-map run: elements k .. k+3 of the row at p (stride ld between k);
+  // k is the same for every lane of a wave.
+  __device__ __forceinline__ void col4(T* dst, gptr<T> p, int k, long ld, T scale) const {
+    if (p) {
+      const gptr<T> q = p + long(k) * ld;
+      if (k + 3 < ck) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[e] = q[long(e) * ld] * scale;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) dst[e] = k + e < ck ? q[long(e) * ld] * scale : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) dst[e] = T(0);
+    }
+  }
 
   // Fetch the K-chunk starting at k0 of the current contribution.
   __device__ __forceinline__ void load(int k0, int tid) {
     const bool ta = flags & GC_TRANS_A, tb = flags & GC_TRANS_B, aid = flags & GC_A_IDENTITY;
     if (aid) {
 #pragma unroll
-      for (int r = 0; r < RA; ++r) {
-        const int k = k0 + 4 * ((tid + r * NTH) % (TK / 4));
+      for (int q = 0; q < RA; ++q) {
+        const int k = k0 + 4 * ((tid + q * NTH) % (TK / 4));
 #pragma unroll
-        for (int e = 0; e < 4; ++e) ra[4 * r + e] = (ia[r] >= 0 && ia[r] == k + e && k + e < ck) ? alpha : T(0);
+        for (int e = 0; e < 4; ++e) ra[4 * q + e] = (ia[q] >= 0 && ia[q] == k + e && k + e < ck) ? alpha : T(0);
       }
     } else if (!ta) {
 #pragma unroll
-      for (int r = 0; r < RA; ++r) {
-        const int k = k0 + 4 * ((tid + r * NTH) % (TK / 4));
-        run4(ra + 4 * r, pa[r] ? pa[r] + k0 : nullptr, k, alpha);
+      for (int q = 0; q < RA; ++q) {
+        const int k = k0 + 4 * ((tid + q * NTH) % (TK / 4));
+        run4(ra + 4 * q, pa[q] ? pa[q] + k0 : nullptr, k, alpha);
       }
     } else {
+      // tid / TM is the same for all lanes of a wave (TM is a multiple of 64)
+      const int g = __builtin_amdgcn_readfirstlane(tid / TM);
 #pragma unroll
-      for (int r = 0; r < RA; ++r) {
-        const int k = k0 + (tid + r * NTH) / (TM / 4);
-        const long off = long(k) * lda;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) ra[4 * r + e] = (pa[4 * r + e] && k < ck) ? pa[4 * r + e][off] * alpha : T(0);
-      }
+      for (int q = 0; q < RA; ++q) col4(ra + 4 * q, pa[0], k0 + 4 * g + 4 * GA * q, lda, alpha);
     }
     if (!tb) {
+      const int g = __builtin_amdgcn_readfirstlane(tid / TN);
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const int k = k0 + (tid + r * NTH) / (TN / 4);
-        const long off = long(k) * ldb;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) rb[4 * r + e] = (pb[4 * r + e] && k < ck) ? pb[4 * r + e][off] : T(0);
-      }
+      for (int q = 0; q < RB; ++q) col4(rb + 4 * q, pb[0], k0 + 4 * g + 4 * GB * q, ldb, T(1));
     } else {
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const int k = k0 + 4 * ((tid + r * NTH) % (TK / 4));
-        run4(rb + 4 * r, pb[r] ? pb[r] + k0 : nullptr, k, T(1));
+      for (int q = 0; q < RB; ++q) {
+        const int k = k0 + 4 * ((tid + q * NTH) % (TK / 4));
+        run4(rb + 4 * q, pb[q] ? pb[q] + k0 : nullptr, k, T(1));
       }
     }
   }
 
   __device__ __forceinline__ void store(Lds<MODE, TM, TN>& s, int buf, bool ta, bool tb, int tid) const {
+    const bool arow = ta && !(flags & GC_A_IDENTITY);
 #pragma unroll
-    for (int r = 0; r < RA; ++r) {
-      const int run = tid + r * NTH;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (ta) put_a(s, buf, 4 * (run % (TM / 4)) + e, run / (TM / 4), ra[4 * r + e]);
-        else put_a(s, buf, run / (TK / 4), 4 * (run % (TK / 4)) + e, ra[4 * r + e]);
-      }
+    for (int q = 0; q < RA; ++q) {
+      const int run = tid + q * NTH;
+      const int row = arow ? tid % TM : run / (TK / 4);
+      const int k0 = arow ? 4 * (tid / TM) + 4 * GA * q : 4 * (run % (TK / 4));
+      put_a(s, buf, row, k0, ra + 4 * q);
     }
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      const int run = tid + r * NTH;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        if (tb) put_b(s, buf, run / (TK / 4), 4 * (run % (TK / 4)) + e, rb[4 * r + e]);
-        else put_b(s, buf, 4 * (run % (TN / 4)) + e, run / (TN / 4), rb[4 * r + e]);
-      }
+    for (int q = 0; q < RB; ++q) {
+      const int run = tid + q * NTH;
+      const int row = tb ? run / (TK / 4) : tid % TN;
+      const int k0 = tb ? 4 * (run % (TK / 4)) : 4 * (tid / TN) + 4 * GB * q;
+      put_b(s, buf, row, k0, rb + 4 * q);
     }
   }
 
-  __device__ __forceinline__ static void put_a(Lds<MODE, TM, TN>& s, int buf, int i, int k, T v) {
-    if constexpr (MODE == 2) {
-      const __bf16 h = static_cast<__bf16>(v);
-      s.ah[buf][i][k] = h;
-      s.al[buf][i][k] = static_cast<__bf16>(v - static_cast<float>(h));
-    } else {
-      s.a[buf][i][k] = v;
+  __device__ __forceinline__ static void put_a(Lds<MODE, TM, TN>& s, int buf, int row, int k0, const T* v) {
+    if constexpr (MODE == 2) put4_bf16(&s.ah[buf][row][0], &s.al[buf][row][0], k0, v);
+    else if constexpr (MODE == 1) put4_f32(&s.a[buf][row][0], k0, v);
+    else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) s.a[buf][row][k0 + e] = v[e];
     }
   }
-  __device__ __forceinline__ static void put_b(Lds<MODE, TM, TN>& s, int buf, int j, int k, T v) {
-    if constexpr (MODE == 2) {
-      const __bf16 h = static_cast<__bf16>(v);
-      s.bh[buf][j][k] = h;
-      s.bl[buf][j][k] = static_cast<__bf16>(v - static_cast<float>(h));
-    } else {
-      s.b[buf][j][k] = v;
+  __device__ __forceinline__ static void put_b(Lds<MODE, TM, TN>& s, int buf, int row, int k0, const T* v) {
+    if constexpr (MODE == 2) put4_bf16(&s.bh[buf][row][0], &s.bl[buf][row][0], k0, v);
+    else if constexpr (MODE == 1) put4_f32(&s.b[buf][row][0], k0, v);
+    else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) s.b[buf][row][k0 + e] = v[e];
     }
   }
 };
@@ -319,20 +341,33 @@ __device__ __forceinline__ void mma(Acc<0, BM, BN>& acc, const Lds<0, TM, TN>& s
 template <int TM, int TN, int BM, int BN>
 __device__ __forceinline__ void mma(Acc<1, BM, BN>& acc, const Lds<1, TM, TN>& s, int buf, int kv, int wm, int wn,
                                     int lane) {
+  typedef float floatx4 __attribute__((ext_vector_type(4)));
+  // all sixteen steps of the chunk are read first (lane half h holds
+  // k = 2s + h at position 16h + s), then the products run back to back
+  const int h = 16 * (lane >> 5);
+  floatx4 av[BM][4], bv[BN][4];
 #pragma unroll
-  for (int st = 0; st < Cfg<1>::TK / 2; ++st) {
-    if (2 * st >= kv) break;
-    const int k = 2 * st + (lane >> 5);
-    float av[BM], bv[BN];
+  for (int a = 0; a < BM; ++a)
 #pragma unroll
-    for (int a = 0; a < BM; ++a) av[a] = s.a[buf][wm + 32 * a + (lane & 31)][k];
+    for (int c = 0; c < 4; ++c)
+      av[a][c] = *reinterpret_cast<const floatx4*>(&s.a[buf][wm + 32 * a + (lane & 31)][h + 4 * c]);
 #pragma unroll
-    for (int b = 0; b < BN; ++b) bv[b] = s.b[buf][wn + 32 * b + (lane & 31)][k];
+  for (int b = 0; b < BN; ++b)
 #pragma unroll
-    for (int a = 0; a < BM; ++a)
+    for (int c = 0; c < 4; ++c)
+      bv[b][c] = *reinterpret_cast<const floatx4*>(&s.b[buf][wn + 32 * b + (lane & 31)][h + 4 * c]);
+  // groups of four steps (8 k); k beyond the chunk's length is zero in LDS
 #pragma unroll
-      for (int b = 0; b < BN; ++b)
-        acc.c[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a], bv[b], acc.c[a][b], 0, 0, 0);
+  for (int c = 0; c < 4; ++c) {
+    if (8 * c < kv) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int a = 0; a < BM; ++a)
+#pragma unroll
+          for (int b = 0; b < BN; ++b)
+            acc.c[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[a][c][e], bv[b][c][e], acc.c[a][b], 0, 0, 0);
+    }
   }
 }
 
