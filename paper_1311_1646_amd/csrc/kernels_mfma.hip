@@ -427,6 +427,55 @@ __device__ __forceinline__ void write(const Acc<MODE, BM, BN>& acc, const Bases&
       }
 }
 
+// FP32 accumulators: the finished tile is transposed through LDS (the
+// staging buffers, free once every wave has multiplied its last chunk) so
+// that each thread writes runs of four consecutive columns of one output
+// row with one address; runs that leave the block or cross a batch entry
+// fall back to single elements.
+template <class TOut, int MODE, int TM, int TN, int BM, int BN>
+__device__ __forceinline__ void write_rows(const Acc<MODE, BM, BN>& acc, float* O, const Bases& bo, const GJob& J,
+                                          const TileMap<TM, TN>& m, int fold, int wm, int wn, int lane, int tid) {
+  typedef Acc<MODE, BM, BN> A;
+  constexpr int MB = Cfg<MODE>::MB, LDO = TN + 8;
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < BM; ++a)
+#pragma unroll
+    for (int b = 0; b < BN; ++b)
+#pragma unroll
+      for (int r = 0; r < A::R; ++r)
+        O[(wm + MB * a + A::row(lane, r)) * LDO + wn + MB * b + A::col(lane, r)] = acc.c[a][b][r];
+  __syncthreads();
+  typedef float floatx4 __attribute__((ext_vector_type(4)));
+  const int c4 = 4 * (tid % (TN / 4));
+  const int j0 = m.cj[c4], v0 = m.cv[c4];
+  const bool run = j0 >= 0 && m.cj[c4 + 3] == j0 + 3 && m.cv[c4 + 3] == v0;
+  const long sc = bo.stride[J.baseC];
+  TOut* const C = reinterpret_cast<TOut*>(bo.p[J.baseC]) + J.offC;
+  const bool accumulate = J.flags & GJ_ACCUMULATE;
+#pragma unroll
+  for (int p = 0; p < TM * TN / 4 / NTH; ++p) {
+    const int row = tid / (TN / 4) + p * (NTH / (TN / 4));
+    const int ii = m.ri[row];
+    if (ii < 0) continue;
+    const floatx4 v = *reinterpret_cast<const floatx4*>(&O[row * LDO + c4]);
+    if (run) {
+      const int vb = fold == 2 ? m.rv[row] : v0;
+      TOut* q = C + long(vb) * sc + long(ii) * J.ldc + j0;
+      if (accumulate) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) q[e] = TOut(q[e] + TOut(v[e]));
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) q[e] = TOut(v[e]);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) put_out<TOut, TM, TN>(bo, J, m, fold, row, c4 + e, v[e]);
+    }
+  }
+}
+
 template <int MODE, int TN, int BM, int BN, class PT>
 __device__ __forceinline__ void write_partial(const Acc<MODE, BM, BN>& acc, PT* P, int wm, int wn, int lane) {
   typedef Acc<MODE, BM, BN> A;
@@ -519,8 +568,13 @@ __device__ __forceinline__ void do_tile(int ti, const GTile* __restrict__ tiles,
   if (slot >= 0) {
     const long entry = fold == 0 ? long(blockIdx.y) : 0;
     write_partial<MODE, TN>(acc, partial + (entry * nslots + slot) * long(TM * TN), wm, wn, lane);
+  } else if constexpr (MODE == 0) {
+    write<MODE, TM, TN>(acc, bout, J, m, fold, wm, wn, lane, true);
   } else {
-    write<MODE, TM, TN>(acc, bout, J, m, fold, wm, wn, lane, out_f64 != 0);
+    static_assert(sizeof(Lds<MODE, TM, TN>) >= sizeof(float) * TM * (TN + 8), "output tile does not fit");
+    float* O = reinterpret_cast<float*>(&s);
+    if (out_f64) write_rows<double, MODE, TM, TN>(acc, O, bout, J, m, fold, wm, wn, lane, tid);
+    else write_rows<float, MODE, TM, TN>(acc, O, bout, J, m, fold, wm, wn, lane, tid);
   }
 }
 
