@@ -513,7 +513,11 @@ void finish_two_stage(Ctx& x, TwoStageBuilder& B, TwoStagePlan& P, bool overwrit
       const int ck = s.t1 >= 0 ? chunk_of[s.t1] : 0;
       if (ck != c) continue;
       GContrib g = s.con;
-      if (s.t1 >= 0) {
+      if (s.t1 >= 0 && s.t_is_a) {
+        g.offA += toff[s.t1];
+        g.baseA = B_T;
+        if (ldt[s.t1]) g.lda = int(ldt[s.t1]);
+      } else if (s.t1 >= 0) {
         g.offB += toff[s.t1];
         g.baseB = B_T;
         if (ldt[s.t1]) g.ldb = int(ldt[s.t1]);
@@ -888,11 +892,16 @@ struct RJob {
 // before the one-site transform (one dressed operator per target) or after it
 // (one transformed building block per shared source, then a linear
 // combination), whichever needs fewer transforms.
-ContractionPlan& Ctx::renorm_plan(int dir, int i, const OpSet& src, const OpSet& dst) {
-  auto key = std::make_tuple(dir, i, src.first_order ? 1 : 0, 0);
+// bra_first: the kets are batched and the sources and the bra are shared, so
+// stage 1 forms U = A_bra^T X (left) or R_bra Z (right) once for all kets and
+// stage 2 multiplies U by each ket; otherwise stage 1 forms T = X A_ket
+// (left) or Z R_ket^T (right) per ket and stage 2 applies the bra.
+ContractionPlan& Ctx::renorm_plan(int dir, int i, const OpSet& src, const OpSet& dst, bool bra_first) {
+  auto key = std::make_tuple(dir, i, src.first_order ? 1 : 0, bra_first ? 1 : 0);
   auto it = renorm_plans_.find(key);
   if (it != renorm_plans_.end()) return *it->second;
   auto P = std::make_unique<ContractionPlan>();
+  P->bra_first = bra_first;
   const bool leftdir = dir == DMRG_DIR_LEFT;
   const SiteOp& W = leftdir ? H->site_op(i, 1, H->mode_left(i), H->mode_left(i + 1))
                             : H->site_op(i, 1, H->mode_right(i), H->mode_right(i + 1));
@@ -991,6 +1000,26 @@ ContractionPlan& Ctx::renorm_plan(int dir, int i, const OpSet& src, const OpSet&
           if (j.X.kind == REF_IDENTITY) {
             s2.t1 = -1;
             s2.con.offB = long(S.blk[b].off);
+          } else if (bra_first) {
+            // U = A_bra(a',n',c')^T X(a'<-a) (m_c' x m_a);  tgt(c'<-c) += al U A_ket(a,n,c)
+            auto tk = std::make_tuple(j.X.base, j.X.off, bp);
+            auto f = TB.t1_of.find(tk);
+            if (f == TB.t1_of.end()) {
+              TwoStageBuilder::T1 t{};
+              t.merge = 0;
+              t.elems = long(S.blk[bp].cols) * bl.dim[a];
+              t.job.ldc = bl.dim[a];
+              t.job.m = S.blk[bp].cols;
+              t.job.n = bl.dim[a];
+              t.con = {long(S.blk[bp].off), opoff(j.X, a), S.blk[bp].cols, bl.dim[a], bl.dim[ap], GC_TRANS_A, B_ABRA,
+                       j.X.base, 1.0};
+              TB.t1.push_back(t);
+              f = TB.t1_of.emplace(tk, int(TB.t1.size()) - 1).first;
+            }
+            s2.t1 = f->second;
+            s2.t_is_a = true;
+            s2.con = {0, long(S.blk[b].off), bl.dim[a], S.blk[b].cols, bl.dim[a], 0, B_T, B_AKET,
+                      j.alpha * ds.val[e] * sign};
           } else {
             auto tk = std::make_tuple(j.X.base, j.X.off, b);
             auto f = TB.t1_of.find(tk);
@@ -1032,6 +1061,26 @@ ContractionPlan& Ctx::renorm_plan(int dir, int i, const OpSet& src, const OpSet&
             s2.t1 = -1;
             s2.con = {long(S.blk[bp].off), long(S.blk[b].off), S.blk[bp].cols, S.blk[b].cols, S.blk[b].cols,
                       GC_TRANS_B, B_ABRA, B_AKET, j.alpha * ds.val[e] * sign};
+          } else if (bra_first) {
+            // U = R_bra(a',n',c') Z(c'<-c) (m_a' x m_c);  tgt(a'<-a) += al U R_ket(a,n,c)^T
+            auto tk = std::make_tuple(j.X.base, j.X.off, bp);
+            auto f = TB.t1_of.find(tk);
+            if (f == TB.t1_of.end()) {
+              TwoStageBuilder::T1 t{};
+              t.merge = 1;  // bra blocks share Z: stack their rows
+              t.elems = long(S.blk[bp].rows) * S.blk[b].cols;
+              t.job.ldc = S.blk[b].cols;
+              t.job.m = S.blk[bp].rows;
+              t.job.n = S.blk[b].cols;
+              t.con = {long(S.blk[bp].off), opoff(j.X, c), S.blk[bp].cols, S.blk[b].cols, br.dim[cp], 0, B_ABRA,
+                       j.X.base, 1.0};
+              TB.t1.push_back(t);
+              f = TB.t1_of.emplace(tk, int(TB.t1.size()) - 1).first;
+            }
+            s2.t1 = f->second;
+            s2.t_is_a = true;
+            s2.con = {0, long(S.blk[b].off), S.blk[b].cols, S.blk[b].cols, S.blk[b].cols, GC_TRANS_B, B_T, B_AKET,
+                      j.alpha * ds.val[e] * sign};
           } else {
             auto tk = std::make_tuple(j.X.base, j.X.off, b);
             auto f = TB.t1_of.find(tk);
@@ -1073,9 +1122,13 @@ ContractionPlan& Ctx::renorm_plan(int dir, int i, const OpSet& src, const OpSet&
 
 void Ctx::renorm(int dir, int i, const double* Abra, const double* Aket, long aket_stride, const OpSet& src,
                  OpSet& dst, bool accumulate, int batch, int prec) {
-  ContractionPlan& P = renorm_plan(dir, i, src, dst);
   const bool src_b = src.nvec > 1, ket_b = aket_stride != 0;
-  const bool t_b = src_b || ket_b;
+  ContractionPlan& P = renorm_plan(dir, i, src, dst, ket_b && !src_b && batch > 1);
+  // stage-1 products: per ket unless formed from the bra (shared); the
+  // results (and the building blocks) are per entry whenever a source or
+  // the ket is
+  const bool t_b = P.bra_first ? src_b : (src_b || ket_b);
+  const bool o_b = src_b || ket_b;
   const size_t esz = prec == DMRG_FP64 ? 8 : 4;
   Bases b{};
   b.p[B_ABRA] = const_cast<double*>(Abra);
@@ -1086,12 +1139,12 @@ void Ctx::renorm(int dir, int i, const double* Abra, const double* Aket, long ak
   b.p[B_DST] = dst.ptr();
   b.stride[B_DST] = dst.nvec > 1 ? dst.per_vec : 0;
   ws_dress.ensure(this, std::max<size_t>(size_t(P.dressed_per_vec) * (src_b ? batch : 1), 1) * esz);
-  ws_blk.ensure(this, std::max<size_t>(size_t(P.blocks_per_vec) * (t_b ? batch : 1), 1) * 8);
+  ws_blk.ensure(this, std::max<size_t>(size_t(P.blocks_per_vec) * (o_b ? batch : 1), 1) * 8);
   ws_T.ensure(this, std::max<size_t>(size_t(P.main.t_per_vec) * (t_b ? batch : 1), 1) * esz);
   b.p[B_DRESS] = ws_dress.as<double>();
   b.stride[B_DRESS] = src_b ? P.dressed_per_vec : 0;
   b.p[B_BLK] = ws_blk.as<double>();
-  b.stride[B_BLK] = t_b ? P.blocks_per_vec : 0;
+  b.stride[B_BLK] = o_b ? P.blocks_per_vec : 0;
   b.p[B_T] = ws_T.as<double>();
   b.stride[B_T] = t_b ? P.main.t_per_vec : 0;
   if (prec != DMRG_FP64) {
@@ -1111,7 +1164,7 @@ void Ctx::renorm(int dir, int i, const double* Abra, const double* Aket, long ak
   }
   dst.f32_valid = false;
   if (!accumulate) launch_fill_f64(dst.ptr(), long(dst.per_vec) * dst.nvec, 0.0, stream);
-  if (P.blocks_per_vec) launch_fill_f64(ws_blk.as<double>(), P.blocks_per_vec * (t_b ? batch : 1), 0.0, stream);
+  if (P.blocks_per_vec) launch_fill_f64(ws_blk.as<double>(), P.blocks_per_vec * (o_b ? batch : 1), 0.0, stream);
   P.form.launch(*this, b, src_b ? batch : 1, prec);
   for (auto& ch : P.main.chunks) {
     ch.first.launch(*this, b, t_b ? batch : 1, prec, prec == DMRG_FP64);
@@ -1253,11 +1306,15 @@ inline int term_sign(const DotString& ds, const STerm& t, int nleft, int ndot) {
 }
 }  // namespace
 
-ContractionPlan& Ctx::sigma_plan(int i, int width, const OpSet& X, const OpSet& Z) {
-  auto key = std::make_tuple(i, width, X.first_order ? 1 : 0, Z.first_order ? 1 : 0);
+// left_first: only Z is batched (C and X shared), so stage 1 forms
+// U = X C once and stage 2 multiplies U by each Z^T; otherwise stage 1 forms
+// T = C Z^T and stage 2 applies X.
+ContractionPlan& Ctx::sigma_plan(int i, int width, const OpSet& X, const OpSet& Z, bool left_first) {
+  auto key = std::make_tuple(i, width, (X.first_order ? 1 : 0) + (left_first ? 2 : 0), Z.first_order ? 1 : 0);
   auto it = sigma_plans_.find(key);
   if (it != sigma_plans_.end()) return *it->second;
   auto P = std::make_unique<ContractionPlan>();
+  P->left_first = left_first;
   const SiteLayout& S = layout(i, width);
   const Bond& bl = bonds[i];
   const Bond& br = bonds[i + width];
@@ -1306,6 +1363,40 @@ ContractionPlan& Ctx::sigma_plan(int i, int width, const OpSet& X, const OpSet& 
           g.offB = long(S.blk[b].off);
           g.baseB = B_CIN;
           g.ldb = S.blk[b].cols;
+        } else if (left_first) {
+          // sigma(bp) += al U Z(c'<-c)^T with U = X(a'<-a) C(a,n,c) (m_a' x m_c)
+          // (or C itself when X is the identity)
+          g.k = S.blk[b].cols;
+          g.offB = opoff(t.Z, c);
+          g.baseB = t.Z.base;
+          g.ldb = S.blk[b].cols;
+          g.flags = GC_TRANS_B;
+          if (t.X.kind == REF_IDENTITY) {
+            s2.t1 = -1;
+            g.offA = long(S.blk[b].off);
+            g.baseA = B_CIN;
+            g.lda = S.blk[b].cols;
+          } else {
+            auto tk = std::make_tuple(t.X.base, t.X.off, int(b));
+            auto f = TB.t1_of.find(tk);
+            if (f == TB.t1_of.end()) {
+              TwoStageBuilder::T1 t1{};
+              t1.merge = 1;  // X blocks share C: stack their rows
+              t1.elems = long(bl.dim[ap]) * S.blk[b].cols;
+              t1.job.ldc = S.blk[b].cols;
+              t1.job.m = bl.dim[ap];
+              t1.job.n = S.blk[b].cols;
+              t1.con = {opoff(t.X, a), long(S.blk[b].off), S.blk[b].rows, S.blk[b].cols, S.blk[b].rows, 0, t.X.base,
+                        B_CIN, 1.0};
+              TB.t1.push_back(t1);
+              f = TB.t1_of.emplace(tk, int(TB.t1.size()) - 1).first;
+            }
+            s2.t1 = f->second;
+            s2.t_is_a = true;
+            g.offA = 0;
+            g.baseA = B_T;
+            g.lda = S.blk[b].cols;
+          }
         } else {
           auto tk = std::make_tuple(t.Z.base, t.Z.off, int(b));
           auto f = TB.t1_of.find(tk);
@@ -1349,10 +1440,11 @@ void Ctx::ensure_f32(const OpSet& S) {
 
 void Ctx::sigma_general(int i, int width, const OpSet& X, const OpSet& Z, const double* C, long cstride, double* Sv,
                         long sstride, int batch, int prec) {
-  ContractionPlan& P = sigma_plan(i, width, X, Z);
   const bool xb = X.nvec > 1, zb = Z.nvec > 1, cb = cstride != 0;
+  ContractionPlan& P = sigma_plan(i, width, X, Z, zb && !xb && !cb && batch > 1);
   const bool dress_b = P.dress_left ? xb : zb;
-  const bool t_b = cb || zb;
+  // stage-1 products: C Z^T depend on C and Z, X C (left first) on X and C
+  const bool t_b = P.left_first ? (cb || xb) : (cb || zb);
   const size_t esz = prec == DMRG_FP64 ? 8 : 4;
   Bases b{};
   b.stride[B_CIN] = cstride;

@@ -124,7 +124,9 @@ struct TwoStageBuilder {
   // (gathered A rows); 2 columns may be placed side by side with other
   // items sharing op(A) (gathered B columns)
   struct T1 { long elems; GJob job; GContrib con; int merge; };
-  struct S2 { int t1; long offC; int baseC, ldc, m, n; GContrib con; };
+  // t_is_a: the stage-1 product is operand A of the stage-2 contribution
+  // (else operand B)
+  struct S2 { int t1; long offC; int baseC, ldc, m, n; GContrib con; bool t_is_a; };
   std::vector<T1> t1;
   std::map<std::tuple<int, long, int>, int> t1_of;  // (base, offset, block) -> item
   std::vector<S2> s2;
@@ -144,6 +146,8 @@ struct ContractionPlan {
   LinCombPlan post;   // building blocks -> targets
   long dressed_per_vec = 0, blocks_per_vec = 0;
   bool dress_left = true;
+  bool bra_first = false;  // renormalization: stage 1 forms A_bra^T X (shared by all kets)
+  bool left_first = false;  // sigma: stage 1 forms X C (shared when only Z is batched)
 };
 
 struct DiagPlan {
@@ -240,8 +244,8 @@ class Ctx {
   std::map<std::tuple<int, int, int, int>, std::unique_ptr<ContractionPlan>> renorm_plans_;
   std::map<std::tuple<int, int, int, int>, std::unique_ptr<ContractionPlan>> sigma_plans_;
   std::map<std::pair<int, int>, std::unique_ptr<DiagPlan>> diag_plans_;
-  ContractionPlan& renorm_plan(int dir, int i, const OpSet& src, const OpSet& dst);
-  ContractionPlan& sigma_plan(int i, int width, const OpSet& X, const OpSet& Z);
+  ContractionPlan& renorm_plan(int dir, int i, const OpSet& src, const OpSet& dst, bool bra_first);
+  ContractionPlan& sigma_plan(int i, int width, const OpSet& X, const OpSet& Z, bool left_first = false);
   void clear_plans();
 };
 
