@@ -775,7 +775,16 @@ void Ctx::export_mps(int* nsec_out, int* sectors_out, double* Ld, double* Rd, do
 
 // ---------------------------------------------------------------- operator sets
 
-void Ctx::alloc_opset(OpSet& S, int bond, int side, int nvec, bool first_order) {
+long Ctx::opset_size(int bond, int side) {
+  const BondChannels& B = side == 0 ? H->left_channels(bond) : H->right_channels(bond);
+  const uint64_t ident = side == 0 ? chan_key(CH_ID_H, -1, -1) : chan_key(CH_H_ID, -1, -1);
+  long n = 0;
+  for (size_t w = 0; w < B.ch.size(); ++w)
+    if (B.ch[w].key != ident) n += long(op_layout(bond, B.ch[w].dna, B.ch[w].dnb)->size);
+  return n;
+}
+
+void Ctx::alloc_opset(OpSet& S, int bond, int side, int nvec, bool first_order, bool reuse) {
   const BondChannels& B = side == 0 ? H->left_channels(bond) : H->right_channels(bond);
   S.bond = bond;
   S.side = side;
@@ -804,7 +813,8 @@ void Ctx::alloc_opset(OpSet& S, int bond, int side, int nvec, bool first_order) 
     }
   }
   S.per_vec = off;
-  S.data.alloc(this, std::max<size_t>(size_t(off) * nvec, 1) * 8);
+  const size_t bytes = std::max<size_t>(size_t(off) * nvec, 1) * 8;
+  if (!reuse || S.data.bytes < bytes) S.data.alloc(this, bytes);
 }
 
 // ---------------------------------------------------------------- planning helpers

@@ -206,7 +206,9 @@ class Ctx {
                   size_t* sizes);
   void upload_lambda();
   void build_ops(int prec);
-  void alloc_opset(OpSet& S, int bond, int side, int nvec, bool first_order);
+  // reuse: keep the set's buffer when it is large enough (no reallocation)
+  void alloc_opset(OpSet& S, int bond, int side, int nvec, bool first_order, bool reuse = false);
+  long opset_size(int bond, int side);  // elements per vector of the set at (bond, side)
 
   // Renormalization across site i into dst (left: bond i -> i+1; right:
   // bond i+1 -> i).  bra tensor Abra (unbatched), ket tensor Aket with batch

@@ -158,6 +158,15 @@ class TdaRunner {
   void q_c_project(int i, double* z, int nv);  // z -= C0 (C0 . z)
   void q_l_project(int i, const double* C, double* out, int nv);  // out = C - L (L^T C)
   void forward(int m, int lprev, bool init, uint64_t seed, std::vector<double>& r2);
+  // size both buffers of a ping-pong pair of first-order sets (side 0 left,
+  // 1 right) for the largest bond, so that a sweep allocates once
+  void reserve(OpSet* sets, int side, int nvec) {
+    long mx = 1;
+    for (int b = 0; b <= L_; ++b) mx = std::max(mx, x_.opset_size(b, side));
+    const size_t bytes = size_t(mx) * size_t(nvec) * 8;
+    for (int k = 0; k < 2; ++k)
+      if (sets[k].data.bytes < bytes) sets[k].data.alloc(&x_, bytes);
+  }
   void backward(int l);
 };
 
@@ -345,7 +354,8 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
   launch_fill_f64(HR_.as<double>(), long(l) * l, 0.0, x_.stream);
   launch_fill_f64(SR_.as<double>(), long(l) * l, 0.0, x_.stream);
   int cur = 0;
-  x_.alloc_opset(FL_[cur], 0, 0, l, true);
+  reserve(FL_, 0, l);
+  x_.alloc_opset(FL_[cur], 0, 0, l, true, true);
   HostRng rng(seed);
   std::vector<double> tmp;
   for (int i = 0; i < L_; ++i) {
@@ -414,13 +424,12 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
     copy(Wk, Ct, long(l) * S);
     scale(i, false, true, Wk, l);
     const int nxt = 1 - cur;
-    x_.alloc_opset(FL_[nxt], i + 1, 0, l, true);
+    x_.alloc_opset(FL_[nxt], i + 1, 0, l, true, true);
     const double* Li = x_.site[i].L.as<double>();
     x_.renorm(DMRG_DIR_LEFT, i, Li, Li, 0, FL_[cur], FL_[nxt], false, l, prec_);
     x_.renorm(DMRG_DIR_LEFT, i, Li, Wk, S, x_.left[i], FL_[nxt], true, l, prec_);
     if (m > 0) copy(Cprev_.as<double>(), Cm, long(m) * S);
     x_.sync();
-    FL_[cur].data.release();
     cur = nxt;
   }
   x_.sync();
@@ -430,7 +439,8 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
 
 void TdaRunner::backward(int l) {
   int cur = 0;
-  x_.alloc_opset(FR_[cur], L_, 1, l, true);
+  reserve(FR_, 1, l);
+  x_.alloc_opset(FR_[cur], L_, 1, l, true, true);
   double* Cb = Cb_.as<double>();
   copy(Cb, Ct_[L_ - 1].as<double>(), long(l) * size_[L_ - 1]);
   for (int i = L_ - 1; i >= 0; --i) {
@@ -448,7 +458,7 @@ void TdaRunner::backward(int l) {
     if (i == 0) break;
     // first-order right operators (eq. ropr1st)
     const int nxt = 1 - cur;
-    x_.alloc_opset(FR_[nxt], i, 1, l, true);
+    x_.alloc_opset(FR_[nxt], i, 1, l, true, true);
     x_.renorm(DMRG_DIR_RIGHT, i, Ri, Ri, 0, FR_[cur], FR_[nxt], false, l, prec_);
     x_.renorm(DMRG_DIR_RIGHT, i, Ri, R1, S, x_.right[i + 1], FR_[nxt], true, l, prec_);
     // gauge shift to site i-1 (eq. gauge_bwd): C_{i-1} = C~_{i-1} + L_{i-1} (C_i R_i^T)
@@ -457,7 +467,6 @@ void TdaRunner::backward(int l) {
     rmul(i - 1, true, x_.site[i - 1].L.as<double>(), 0, bm_.as<double>(), bm_size_[i], Wk, l);
     copy(Cb, Wk, long(l) * size_[i - 1]);
     x_.sync();
-    FR_[cur].data.release();
     cur = nxt;
   }
   x_.sync();
