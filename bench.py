@@ -211,6 +211,12 @@ def main():
         out["tda_sweep_s"] = round(s["tda_iter_ms"] / 1e3, 3)
         out["tda"] = {"iterations": its, "trial_vectors": 2 * a.nroots, "last_iteration_s": round(s["tda_iter_ms"] / 1e3, 3),
                       "total_s_incl_setup": round(wall, 2), "prec": a.prec}
+        if s["tda_sigma_ms"] > 0:
+            # TDA sigma of the middle site inside that iteration: first-order
+            # left part for all trial vectors + zeroth-order part for the roots
+            out["tda"]["middle_site_tda_sigma"] = {
+                "GFLOP/s": round(s["tda_sigma_flops"] / (s["tda_sigma_ms"] * 1e-3) / 1e9, 2),
+                "device_ms": round(s["tda_sigma_ms"], 3), "flops": s["tda_sigma_flops"]}
         log(f"[bench] TDA: {out['tda']}")
     if not a.no_cpu_baseline:
         try:

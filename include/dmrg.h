@@ -198,9 +198,13 @@ typedef struct {
   double renorm_flops, renorm_ms;
   double op_bytes;         /* device bytes held by zeroth-order operator pools     */
   double tda_iter_ms;      /* wall time of the last TDA Davidson iteration         */
-  double tda_sigma_flops;  /* algorithmic flops of that iteration                   */
+  double tda_sigma_flops;  /* algorithmic flops of the TDA sigma (eq. sigv1) at the
+                              middle site in that iteration: the first-order left
+                              part (eq. sigv2) for all trial vectors plus the
+                              zeroth-order part for the roots                      */
   int tda_iters;
   int sigma_main_launches; /* launches of the dominant kernel in the last sigma    */
+  double tda_sigma_ms;     /* device time of that TDA sigma                         */
 } dmrg_stats;
 
 int dmrg_get_stats(dmrg_ctx* ctx, dmrg_stats* out);

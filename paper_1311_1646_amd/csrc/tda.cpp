@@ -379,12 +379,34 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
     }
     // first-order left part of the sigma for all l vectors (eq. sigv2, first line)
     double* Dl = Dl_.as<double>();
+    // the TDA sigma of the middle site (first-order left part for the l
+    // trial vectors and zeroth-order part for the n roots) is timed
+    const bool timed = !init && i == L_ / 2;
+    hipEvent_t te[2] = {nullptr, nullptr};
+    double tfl = 0;
+    if (timed) {
+      DMRG_HIP(hipEventCreate(&te[0]));
+      DMRG_HIP(hipEventCreate(&te[1]));
+      DMRG_HIP(hipEventRecord(te[0], x_.stream));
+    }
     x_.sigma_general(i, 1, FL_[cur], x_.right[i + 1], C0, 0, Dl, S, l, prec_);
+    tfl += x_.stats.sigma_flops;
     double* Wk = Wk_.as<double>();
     if (!init) {
       // sigma (eq. sigv1), residual (eq. rnorm), correction (eqs. error, param)
       double* Sg = Sg_.as<double>();
       x_.sigma_general(i, 1, x_.left[i], x_.right[i + 1], Cm, S, Sg, S, n_, prec_);
+      if (timed) {
+        tfl += x_.stats.sigma_flops;
+        DMRG_HIP(hipEventRecord(te[1], x_.stream));
+        DMRG_HIP(hipEventSynchronize(te[1]));
+        float ms = 0;
+        DMRG_HIP(hipEventElapsedTime(&ms, te[0], te[1]));
+        x_.stats.tda_sigma_ms = ms;
+        x_.stats.tda_sigma_flops = tfl;
+        (void)hipEventDestroy(te[0]);
+        (void)hipEventDestroy(te[1]);
+      }
       launch_axpby_f64(ones_.as<double>(), Dl, S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
       launch_axpby_f64(ones_.as<double>(), Gr_.as<double>(), S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
       launch_axpby_f64(negw_.as<double>(), Cm, S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
