@@ -129,6 +129,7 @@ def main():
     ap.add_argument("--tda-iters", type=int, default=1, help="TDA Davidson iterations to time (0: none)")
     ap.add_argument("--copy-calib", action="store_true", help="run one 256 MiB device copy first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the planner's tile shapes")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -164,9 +165,16 @@ def main():
     C = torch.randn(a.nroots, size, dtype=torch.float64, device="cuda")
     S = torch.empty_like(C)
     ladder = {}
+    tuned = {}
     for name in PRECS:
         if name != a.prec and not a.ladder:
             continue
+        if not a.no_autotune:
+            pr = {"fp64": lib.FP64, "fp32": lib.FP32, "bf16x3": lib.BF16X3}[name]
+            s1, s2, ms = ctx.autotune(site, a.nroots, pr)
+            names = {-1: "planner", 0: "64x64", 1: "128x64", 2: "64x128"}
+            tuned[name] = {"stage1": names[s1], "stage2": names[s2]}
+            log(f"[bench] autotune {name}: {tuned[name]} ({ms:.1f} ms)")
         ladder[name] = time_sigma(ctx, lib, site, C, S, name, a.steps, a.warmup)
         log(f"[bench] {name}: {ladder[name]}")
     head = ladder[a.prec]
@@ -189,7 +197,8 @@ def main():
                    "sigma_size": size, "sigma_device_ms": head["device_ms"],
                    "op_GiB": round(st["op_bytes"] / 2**30, 2),
                    "precision_ladder": {k: {"GFLOP/s": v["gflops"], "device_ms": v["device_ms"]}
-                                        for k, v in ladder.items()}},
+                                        for k, v in ladder.items()},
+                   "tile_shapes": tuned or "planner"},
     }
     # dominant kernel: the accumulation stage (grouped GEMM, role 1) of the
     # sigma; per launch = per sigma / launches, so the ratio is the same

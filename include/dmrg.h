@@ -132,6 +132,18 @@ int dmrg_build_ops(dmrg_ctx* ctx, int prec);
 int dmrg_sigma(dmrg_ctx* ctx, int site, int kind, int nvec, const double* C_in,
                double* sigma_out, int prec);
 
+/* Tile-shape autotuner of the grouped block GEMM (the contractions of Sec.
+ * III B-D): times the one-site sigma at `site` for nvec vectors in precision
+ * prec under every pair of stage-1 / stage-2 tile shapes (the planner's
+ * choice, 64x64, 128x64, 64x128; a shape a launch cannot use falls back to
+ * the planner's choice) and keeps the fastest pair for all later
+ * contractions of that precision in this context.  shapes_out[0..1]
+ * receives the chosen stage-1 and stage-2 shapes (-1 = planner's choice,
+ * 0 = 64x64, 1 = 128x64, 2 = 64x128) and best_ms_out the device time of that
+ * sigma.  Allocates two nvec x size FP64 device buffers for the duration of
+ * the call.  Errors: STATE before build_ops, INVALID_ARG. */
+int dmrg_autotune(dmrg_ctx* ctx, int site, int nvec, int prec, int* shapes_out, double* best_ms_out);
+
 /* Diagonal of the one-site effective Hamiltonian at `site` (the Davidson
  * preconditioner of eq. error), written to a device FP64 array of `size`. */
 int dmrg_diag(dmrg_ctx* ctx, int site, int width, double* diag_out, int prec);

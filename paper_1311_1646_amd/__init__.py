@@ -84,6 +84,7 @@ _layout = _sig("dmrg_get_layout", _P, _I, _I, _IP, _IP, _SP)
 _build_ops = _sig("dmrg_build_ops", _P, _I)
 _sigma = _sig("dmrg_sigma", _P, _I, _I, _I, _P, _P, _I)
 _diag = _sig("dmrg_diag", _P, _I, _I, _P, _I)
+_autotune = _sig("dmrg_autotune", _P, _I, _I, _I, _IP, _DP)
 _renorm = _sig("dmrg_renormalize", _P, _I, _I, _I, _I)
 _sweep = _sig("dmrg_sweep_ground", _P, ctypes.POINTER(SweepParams), _DP, _DP)
 _tda = _sig("dmrg_tda_roots", _P, _I, ctypes.POINTER(DavidsonParams), _DP, _DP, _DP, _IP)
@@ -181,6 +182,14 @@ class Context:
         self._check(_sigma(self._h, site, kind, nvec, ctypes.c_void_p(C.data_ptr()),
                            ctypes.c_void_p(out.data_ptr()), prec))
         return out
+
+    def autotune(self, site, nvec, prec=FP32):
+        """Pick the stage-1 / stage-2 tile shapes by timing the sigma at `site`
+        (see dmrg_autotune); returns (stage1_shape, stage2_shape, best_ms)."""
+        shapes = (ctypes.c_int * 2)()
+        ms = ctypes.c_double()
+        self._check(_autotune(self._h, site, nvec, prec, shapes, ctypes.byref(ms)))
+        return shapes[0], shapes[1], ms.value
 
     def diag(self, site, width=1, prec=FP64):
         import torch

@@ -131,6 +131,14 @@ int dmrg_sigma(dmrg_ctx* ctx, int site, int kind, int nvec, const double* C_in, 
   });
 }
 
+int dmrg_autotune(dmrg_ctx* ctx, int site, int nvec, int prec, int* shapes_out, double* best_ms_out) {
+  return guard(ctx, [&](dmrg::Ctx& x) {
+    DMRG_REQUIRE(valid_prec(prec), DMRG_ERR_INVALID_ARG, "unsupported precision");
+    DMRG_REQUIRE(shapes_out && best_ms_out, DMRG_ERR_INVALID_ARG, "null outputs");
+    x.autotune(site, nvec, prec, shapes_out, best_ms_out);
+  });
+}
+
 int dmrg_diag(dmrg_ctx* ctx, int site, int width, double* diag_out, int prec) {
   return guard(ctx, [&](dmrg::Ctx& x) {
     DMRG_REQUIRE(prec == DMRG_FP64, DMRG_ERR_INVALID_ARG, "unsupported precision");

@@ -85,7 +85,7 @@ void GemmPlan::launch(Ctx& x, const Bases& b, int batch, int prec, bool out_f64,
     if (!batched(b, mask_a, false) && batched(b, mask_b, true)) fold = FOLD_N;
     else if (!batched(b, mask_b, false) && (mask_a == 0 || batched(b, mask_a, true))) fold = FOLD_M;
   }
-  const FoldTiles& F = fold_lists(x, fold, batch);
+  const FoldTiles& F = fold_lists(x, fold, batch, x.tile_policy[prec][role == 1 ? 1 : 0][fold]);
   void* part = nullptr;
   if (F.nslots > 0) {
     const size_t esz = prec == DMRG_FP64 ? 8 : 4;
@@ -106,8 +106,11 @@ void GemmPlan::launch(Ctx& x, const Bases& b, int batch, int prec, bool out_f64,
 // job whose work is far above the average share of a workgroup is split into
 // segments (one tile per segment, partial sums reduced afterwards), so that
 // a few long jobs do not leave the rest of the chip idle.
-const GemmPlan::FoldTiles& GemmPlan::fold_lists(Ctx& x, int fold, int batch) const {
-  const auto key = std::make_pair(fold, batch);
+const GemmPlan::FoldTiles& GemmPlan::fold_lists(Ctx& x, int fold, int batch, int want) const {
+  // a shape the fold cannot use (128 along the folded dimension) falls back
+  // to the planner's choice
+  if ((fold == FOLD_N && want == TILE_64x128) || (fold == FOLD_M && want == TILE_128x64)) want = -1;
+  const auto key = std::make_tuple(fold, batch, want);
   FoldTiles& F = fold_tiles[key];
   if (F.ntiles > 0) return F;
   const long entries = fold == FOLD_NONE ? batch : 1;
@@ -132,20 +135,24 @@ const GemmPlan::FoldTiles& GemmPlan::fold_lists(Ctx& x, int fold, int batch) con
     return sh == TILE_64x64 ? w : 1.5 * w;  // the wider tiles run at lower occupancy
   };
   int shape = TILE_64x64;
-  double best = padded(TILE_64x64);
-  for (int sh : {TILE_128x64, TILE_64x128}) {
-    if ((fold == FOLD_N && sh == TILE_64x128) || (fold == FOLD_M && sh == TILE_128x64)) continue;
-    const double c = padded(sh);
-    if (c < best) {
-      best = c;
-      shape = sh;
+  if (want >= 0) {
+    shape = want;  // set by the autotuner (Ctx::autotune)
+  } else {
+    double best = padded(TILE_64x64);
+    for (int sh : {TILE_128x64, TILE_64x128}) {
+      if ((fold == FOLD_N && sh == TILE_64x128) || (fold == FOLD_M && sh == TILE_128x64)) continue;
+      const double c = padded(sh);
+      if (c < best) {
+        best = c;
+        shape = sh;
+      }
     }
-  }
-  // DMRG_TILE_SHAPE=64x64|128x64|64x128 fixes the shape where the fold allows it
-  if (const char* e = std::getenv("DMRG_TILE_SHAPE")) {
-    const std::string v(e);
-    const int want = v == "128x64" ? TILE_128x64 : v == "64x128" ? TILE_64x128 : TILE_64x64;
-    if (!((fold == FOLD_N && want == TILE_64x128) || (fold == FOLD_M && want == TILE_128x64))) shape = want;
+    // DMRG_TILE_SHAPE=64x64|128x64|64x128 fixes the shape where the fold allows it
+    if (const char* e = std::getenv("DMRG_TILE_SHAPE")) {
+      const std::string v(e);
+      const int w = v == "128x64" ? TILE_128x64 : v == "64x128" ? TILE_64x128 : TILE_64x64;
+      if (!((fold == FOLD_N && w == TILE_64x128) || (fold == FOLD_M && w == TILE_128x64))) shape = w;
+    }
   }
   F.shape = shape;
   const long TR = tile_rows(shape), TC = tile_cols(shape);
@@ -571,6 +578,9 @@ Ctx::Ctx(int L_, int na, int nb, const double* h, const double* eri, double ecor
   // FP64 contractions: matrix cores (default) or the plain FMA kernel
   const char* g = std::getenv("DMRG_FP64_GEMM");
   fp64_mfma = !(g && std::string(g) == "fma");
+  for (auto& a : tile_policy)
+    for (auto& b : a)
+      for (int& c : b) c = -1;
   if (device >= 0) DMRG_HIP(hipSetDevice(device));
   H.reset(new QCHamiltonian(L, h, eri, ecore));
 }
@@ -1539,6 +1549,58 @@ void Ctx::sigma(int i, int width, int nvec, const double* Cin, double* Sout, int
   }
   stats.sigma_main_ms = main_ms;
   stats.sigma_main_launches = main_events_used_ / 2;
+}
+
+void Ctx::autotune(int i, int nvec, int prec, int* shapes, double* best_ms) {
+  require_gpu();
+  DMRG_REQUIRE(ops_prec >= 0, DMRG_ERR_STATE, "call dmrg_build_ops first");
+  DMRG_REQUIRE(i >= 0 && i < L && nvec >= 1, DMRG_ERR_INVALID_ARG, "bad autotune arguments");
+  DMRG_REQUIRE(prec >= 0 && prec <= 2, DMRG_ERR_INVALID_ARG, "unsupported precision");
+  const long n = long(layout(i, 1).size);
+  DBuf cin, sout;
+  cin.alloc(this, size_t(n) * nvec * 8);
+  sout.alloc(this, size_t(n) * nvec * 8);
+  // inputs: copies of the site's coefficient tensor (timing only)
+  for (int v = 0; v < nvec; ++v)
+    DMRG_HIP(hipMemcpyAsync(cin.as<double>() + long(v) * n, site[i].C.as<double>(), size_t(n) * 8,
+                            hipMemcpyDeviceToDevice, stream));
+  const int cand[4] = {-1, TILE_64x64, TILE_128x64, TILE_64x128};
+  int keep[2][3];
+  for (int r = 0; r < 2; ++r)
+    for (int f = 0; f < 3; ++f) keep[r][f] = tile_policy[prec][r][f];
+  double best = 1e300;
+  int b1 = -1, b2 = -1;
+  for (int s1 : cand)
+    for (int s2 : cand) {
+      for (int f = 0; f < 3; ++f) {
+        tile_policy[prec][0][f] = s1;
+        tile_policy[prec][1][f] = s2;
+      }
+      sigma(i, 1, nvec, cin.as<double>(), sout.as<double>(), prec);  // warm-up (lists, FP32 copies)
+      double t = 1e300;
+      for (int rep = 0; rep < 3; ++rep) {
+        sigma(i, 1, nvec, cin.as<double>(), sout.as<double>(), prec);
+        t = std::min(t, double(stats.sigma_ms));
+      }
+      // the planner's choice (first candidate) is replaced only by a pair
+      // at least 2% faster, so that timing noise does not flip near ties
+      if (s1 == -1 && s2 == -1) best = t;
+      else if (t < 0.98 * best) {
+        best = t;
+        b1 = s1;
+        b2 = s2;
+      }
+    }
+  for (int r = 0; r < 2; ++r)
+    for (int f = 0; f < 3; ++f) tile_policy[prec][r][f] = keep[r][f];
+  for (int f = 0; f < 3; ++f) {
+    tile_policy[prec][0][f] = b1;
+    tile_policy[prec][1][f] = b2;
+  }
+  sync();
+  shapes[0] = b1;
+  shapes[1] = b2;
+  *best_ms = best;
 }
 
 void Ctx::mark_main(bool begin) {

@@ -96,8 +96,9 @@ struct GemmPlan {
     DBuf tiles, segs, red;
     int ntiles = 0, nred = 0, nslots = 0, shape = 0;
   };
-  mutable std::map<std::pair<int, int>, FoldTiles> fold_tiles;
-  const FoldTiles& fold_lists(Ctx& x, int fold, int batch) const;
+  mutable std::map<std::tuple<int, int, int>, FoldTiles> fold_tiles;  // (fold, batch, shape or -1)
+  // want: a tile shape, or -1 for the planner's choice
+  const FoldTiles& fold_lists(Ctx& x, int fold, int batch, int want = -1) const;
   // prec: DMRG_FP64 (FP64 MFMA), DMRG_FP32 or DMRG_BF16X3 (FP32 operands);
   // outputs go through bout when given (FP64 outputs of a lower-precision run)
   // role 1 marks the accumulation stage (the dominant kernel of a sigma):
@@ -175,6 +176,11 @@ class Ctx {
   std::unique_ptr<QCHamiltonian> H;
   long t_budget_per_vec;  // workspace elements per batch entry
   bool fp64_mfma = true;   // FP64 grouped GEMM on matrix cores (else FMA kernel)
+  // tile shape per (precision, stage, fold); -1 = the planner's choice
+  int tile_policy[3][2][3];
+  // time the sigma at `site` for nvec vectors under each pair of stage-1 /
+  // stage-2 tile shapes and keep the fastest for precision prec
+  void autotune(int site, int nvec, int prec, int* shapes, double* best_ms);
 
   // MPS
   bool have_mps = false;

@@ -113,3 +113,24 @@ def test_every_tile_shape(ppp12, prec, shape, monkeypatch):
         err = _rel(out, ref)
         assert err < TOL[prec], (shape, w, i, err)
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_autotuned_shapes_keep_parity(ppp12, prec):
+    # the autotuner's choice (any pair of stage shapes) leaves the sigma at
+    # the precision's tolerance, at the tuned site and at others
+    import paper_1311_1646_amd as lib
+    L, Na, Nb, h, eri, mps, dets, H = ppp12
+    ctx = _ctx(lib, L, Na, Nb, h, eri, mps)
+    s1, s2, ms = ctx.autotune(5, 3, _prec(lib, prec))
+    assert s1 in (-1, 0, 1, 2) and s2 in (-1, 0, 1, 2) and ms > 0
+    rng = np.random.default_rng(31)
+    for w, i in ((1, 5), (1, 3), (2, 6)):
+        kind = lib.SIGMA_ZEROTH_1SITE if w == 1 else lib.SIGMA_ZEROTH_2SITE
+        _, n = ctx.layout(i, w)
+        C = rng.normal(size=(3, n))
+        ref = mpsvec.heff_apply(H, mps, dets, i, C, width=w)
+        out = ctx.sigma(i, torch.tensor(C, device="cuda"), kind=kind, prec=_prec(lib, prec)).cpu().numpy()
+        err = _rel(out, ref)
+        assert err < TOL[prec], (s1, s2, w, i, err)
+    ctx.close()
