@@ -135,8 +135,7 @@ int dmrg_sigma(dmrg_ctx* ctx, int site, int kind, int nvec, const double* C_in,
 /* Tile-shape autotuner of the grouped block GEMM (the contractions of Sec.
  * III B-D): times the one-site sigma at `site` for nvec vectors in precision
  * prec under every pair of stage-1 / stage-2 tile shapes (the planner's
- * choice, 64x64, 128x64, 64x128; a shape a launch cannot use falls back to
- * the planner's choice) and keeps the fastest pair for all later
+ * choice, 64x64, 128x64, 64x128) and keeps the fastest pair for all later
  * contractions of that precision in this context.  shapes_out[0..1]
  * receives the chosen stage-1 and stage-2 shapes (-1 = planner's choice,
  * 0 = 64x64, 1 = 128x64, 2 = 64x128) and best_ms_out the device time of that

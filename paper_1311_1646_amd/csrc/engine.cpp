@@ -107,9 +107,8 @@ void GemmPlan::launch(Ctx& x, const Bases& b, int batch, int prec, bool out_f64,
 // segments (one tile per segment, partial sums reduced afterwards), so that
 // a few long jobs do not leave the rest of the chip idle.
 const GemmPlan::FoldTiles& GemmPlan::fold_lists(Ctx& x, int fold, int batch, int want) const {
-  // a shape the fold cannot use (128 along the folded dimension) falls back
-  // to the planner's choice
-  if ((fold == FOLD_N && want == TILE_64x128) || (fold == FOLD_M && want == TILE_128x64)) want = -1;
+  // an explicit shape (autotuner) may put 128 along either dimension; the
+  // planner's own choice below puts it only along the unfolded one
   const auto key = std::make_tuple(fold, batch, want);
   FoldTiles& F = fold_tiles[key];
   if (F.ntiles > 0) return F;
@@ -147,11 +146,10 @@ const GemmPlan::FoldTiles& GemmPlan::fold_lists(Ctx& x, int fold, int batch, int
         shape = sh;
       }
     }
-    // DMRG_TILE_SHAPE=64x64|128x64|64x128 fixes the shape where the fold allows it
+    // DMRG_TILE_SHAPE=64x64|128x64|64x128 fixes the shape of every launch
     if (const char* e = std::getenv("DMRG_TILE_SHAPE")) {
       const std::string v(e);
-      const int w = v == "128x64" ? TILE_128x64 : v == "64x128" ? TILE_64x128 : TILE_64x64;
-      if (!((fold == FOLD_N && w == TILE_64x128) || (fold == FOLD_M && w == TILE_128x64))) shape = w;
+      shape = v == "128x64" ? TILE_128x64 : v == "64x128" ? TILE_64x128 : TILE_64x64;
     }
   }
   F.shape = shape;

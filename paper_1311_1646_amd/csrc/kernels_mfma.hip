@@ -520,7 +520,7 @@ __device__ __forceinline__ void do_tile(int ti, const GTile* __restrict__ tiles,
                                         const GSeg* __restrict__ segs, int nslots,
                                         typename Cfg<MODE>::T* __restrict__ partial, const Bases& bout, int fold,
                                         int batch, int out_f64, Lds<MODE, TM, TN>& s, TileMap<TM, TN>& m,
-                                        const Bases& sb) {
+                                        Bases& sb, const Bases* bs_copy) {
   constexpr int TK = Cfg<MODE>::TK, MB = Cfg<MODE>::MB;
   constexpr int BM = TM / 2 / MB, BN = TN / 2 / MB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -534,6 +534,16 @@ __device__ __forceinline__ void do_tile(int ti, const GTile* __restrict__ tiles,
     c1 = g.c1;
     slot = g.slot;
   }
+  // the first contribution's record is requested before the maps are
+  // built, so that its latency overlaps theirs and the barrier
+  GContrib cfirst{};
+  if (c0 < c1) cfirst = con[c0];
+  // the base table (kernel argument) is copied to LDS once per workgroup,
+  // after the descriptor loads above are under way
+  if (bs_copy && tid < kMaxBases) {
+    sb.p[tid] = bs_copy->p[tid];
+    sb.stride[tid] = bs_copy->stride[tid];
+  }
   tile_maps<TM, TN>(m, J, t.tm, t.tn, fold, batch, tid, gather);
   __syncthreads();
   Acc<MODE, BM, BN> acc;
@@ -541,7 +551,7 @@ __device__ __forceinline__ void do_tile(int ti, const GTile* __restrict__ tiles,
   if (c0 < c1) {
     Stage<MODE, TM, TN> st;
     int ci = c0, k0 = 0, buf = 0;
-    st.begin(con[ci], sb, m, tid, J.flags);
+    st.begin(cfirst, sb, m, tid, J.flags);
     st.load(0, tid);
     for (;;) {
       const int ck = st.ck, fl = st.flags;
@@ -596,20 +606,30 @@ __global__ __launch_bounds__(NTH, Persist<MODE>::waves) void ggemm_mfma_kernel(
   __shared__ Lds<MODE, TM, TN> s;
   __shared__ TileMap<TM, TN> m;
   __shared__ Bases sb;  // base table indexed per contribution (LDS, not a private copy)
-  const int tid = threadIdx.x;
-  if (tid < kMaxBases) {
-    sb.p[tid] = bs.p[tid];
-    sb.stride[tid] = bs.stride[tid];
+  // block-cyclic XCD remap: workgroup b runs on XCD b % 8; each XCD takes
+  // chunks of C consecutive tiles in turn, so neighbouring tiles (sharing
+  // operand tiles) run on one L2 while the chunks stay balanced
+  constexpr int C = 32;
+  const int G = int(gridDim.x), bb = int(blockIdx.x), full = (G / (8 * C)) * (8 * C);
+  int bx = bb;
+  if (bb < full) {
+    const int x = bb & 7, q = bb >> 3;
+    bx = ((q / C) * 8 + x) * C + (q % C);
   }
   if constexpr (Persist<MODE>::on) {
-    for (int ti = blockIdx.x; ti < ntiles; ti += gridDim.x) {
+    const int tid = threadIdx.x;
+    if (tid < kMaxBases) {
+      sb.p[tid] = bs.p[tid];
+      sb.stride[tid] = bs.stride[tid];
+    }
+    for (int ti = bx; ti < ntiles; ti += gridDim.x) {
       __syncthreads();  // the previous tile is done with the maps
       do_tile<MODE, TM, TN>(ti, tiles, jobs, con, gather, segs, nslots, partial, bout, fold, batch, out_f64, s, m,
-                            sb);
+                            sb, nullptr);
     }
   } else {
-    do_tile<MODE, TM, TN>(blockIdx.x, tiles, jobs, con, gather, segs, nslots, partial, bout, fold, batch, out_f64, s,
-                          m, sb);
+    do_tile<MODE, TM, TN>(bx, tiles, jobs, con, gather, segs, nslots, partial, bout, fold, batch, out_f64, s,
+                          m, sb, &bs);
   }
 }
 
