@@ -606,13 +606,14 @@ __global__ __launch_bounds__(NTH, Persist<MODE>::waves) void ggemm_mfma_kernel(
   __shared__ Lds<MODE, TM, TN> s;
   __shared__ TileMap<TM, TN> m;
   __shared__ Bases sb;  // base table indexed per contribution (LDS, not a private copy)
-  // block-cyclic XCD remap: workgroup b runs on XCD b % 8; each XCD takes
-  // chunks of C consecutive tiles in turn, so neighbouring tiles (sharing
-  // operand tiles) run on one L2 while the chunks stay balanced
+  // block-cyclic XCD remap of the products stage: workgroup b runs on XCD
+  // b % 8; each XCD takes chunks of C consecutive tiles in turn, so
+  // neighbouring tiles (sharing an operand tile) run on one L2 while the
+  // chunks stay balanced.  (The accumulation stage measured faster without.)
   constexpr int C = 32;
   const int G = int(gridDim.x), bb = int(blockIdx.x), full = (G / (8 * C)) * (8 * C);
   int bx = bb;
-  if (bb < full) {
+  if (ROLE == 0 && bb < full) {
     const int x = bb & 7, q = bb >> 3;
     bx = ((q / C) * 8 + x) * C + (q % C);
   }
