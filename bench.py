@@ -2,7 +2,8 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4] [--M 1000]
                     [--nroots 16] [--prec fp32] [--ladder] [--tda-iters 1]
-                    [--copy-calib] [--no-cpu-baseline]
+                    [--copy-calib] [--no-cpu-baseline] [--no-autotune]
+                    [--no-sweep-avg]
 
 Workload (synthetic, seeded): the [2Fe-2S]-shaped problem L=36 orbitals,
 N=30 electrons, Sz=0, a 10-orbital near-degenerate block with strong
@@ -11,7 +12,11 @@ A step is one sigma of the one-site effective Hamiltonian at the middle site
 for all TDA roots at once (nroots vectors resident in HBM); `value` is its
 rate.  After the timed steps, one DMRG-TDA Davidson iteration (a forward and
 a backward sweep over all sites with l = 2 nroots trial vectors) is timed
-and reported as `tda_sweep_s`.  --copy-calib first runs one 256 MiB device
+and reported as `tda_sweep_s`, with the TDA sigma of the middle site measured
+inside that iteration; then the zeroth-order sigma at every site once gives
+the sweep-averaged rate.  Before timing a precision, the tile-shape
+autotuner picks the stage shapes (--no-autotune keeps the planner's).
+--copy-calib first runs one 256 MiB device
 copy, so that a hardware-counter run of this command also measures a
 transfer of known size.  One JSON line is printed.
 """
@@ -101,6 +106,27 @@ def time_sigma(ctx, lib, site, C, S, name, steps, warmup):
             "main_bytes": s["sigma_main_bytes"], "main_launches": s["sigma_main_launches"]}
 
 
+def sweep_averaged_sigma(ctx, lib, L, nvec, name):
+    """Zeroth-order sigma for nvec vectors at every site once (plans built
+    first, outside the timing): total flops / total device time."""
+    import torch
+    prec = {"fp64": lib.FP64, "fp32": lib.FP32, "bf16x3": lib.BF16X3}[name]
+    bufs = []
+    for i in range(L):
+        _, n = ctx.layout(i)
+        C = torch.randn(nvec, n, dtype=torch.float64, device="cuda")
+        bufs.append((C, torch.empty_like(C)))
+        ctx.sigma(i, C, out=bufs[-1][1], prec=prec)  # plan + lists
+    torch.cuda.synchronize()
+    fl = ms = 0.0
+    for i in range(L):
+        ctx.sigma(i, bufs[i][0], out=bufs[i][1], prec=prec)
+        s = ctx.stats()
+        fl += s["sigma_flops"]
+        ms += s["sigma_ms"]
+    return {"GFLOP/s": round(fl / (ms * 1e-3) / 1e9, 2), "device_ms_all_sites": round(ms, 2), "sites": L}
+
+
 def measured_traffic(prec, M):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary, or None when there is none for this precision and workload or
@@ -130,6 +156,7 @@ def main():
     ap.add_argument("--copy-calib", action="store_true", help="run one 256 MiB device copy first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the planner's tile shapes")
+    ap.add_argument("--no-sweep-avg", action="store_true", help="skip the sigma at every site")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -227,6 +254,9 @@ def main():
                 "GFLOP/s": round(s["tda_sigma_flops"] / (s["tda_sigma_ms"] * 1e-3) / 1e9, 2),
                 "device_ms": round(s["tda_sigma_ms"], 3), "flops": s["tda_sigma_flops"]}
         log(f"[bench] TDA: {out['tda']}")
+    if not a.no_sweep_avg:
+        out["config"]["sweep_averaged_sigma"] = sweep_averaged_sigma(ctx, lib, p.L, a.nroots, a.prec)
+        log(f"[bench] sweep-averaged sigma: {out['config']['sweep_averaged_sigma']}")
     if not a.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(a.nroots)
