@@ -223,6 +223,8 @@ def main():
                    "L": p.L, "N": p.Na + p.Nb, "M": p.M, "nroots": a.nroots, "site": site,
                    "sigma_size": size, "sigma_device_ms": head["device_ms"],
                    "op_GiB": round(st["op_bytes"] / 2**30, 2),
+                   "build_ops": {"prec": "fp64", "device_ms": round(st["renorm_ms"], 1),
+                                 "GFLOP/s": round(st["renorm_flops"] / max(st["renorm_ms"], 1e-9) / 1e6, 1)},
                    "precision_ladder": {k: {"GFLOP/s": v["gflops"], "device_ms": v["device_ms"]}
                                         for k, v in ladder.items()},
                    "tile_shapes": tuned or "planner"},
