@@ -224,7 +224,8 @@ def main():
                    "sigma_size": size, "sigma_device_ms": head["device_ms"],
                    "op_GiB": round(st["op_bytes"] / 2**30, 2),
                    "build_ops": {"prec": "fp64", "device_ms": round(st["renorm_ms"], 1),
-                                 "GFLOP/s": round(st["renorm_flops"] / max(st["renorm_ms"], 1e-9) / 1e6, 1)},
+                                 "GFLOP/s": round(st["renorm_flops"] / max(st["renorm_ms"], 1e-9) / 1e6, 1),
+                                 "host_planning_ms": round(st["plan_ms"], 1)},
                    "precision_ladder": {k: {"GFLOP/s": v["gflops"], "device_ms": v["device_ms"]}
                                         for k, v in ladder.items()},
                    "tile_shapes": tuned or "planner"},

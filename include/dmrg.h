@@ -216,6 +216,9 @@ typedef struct {
   int tda_iters;
   int sigma_main_launches; /* launches of the dominant kernel in the last sigma    */
   double tda_sigma_ms;     /* device time of that TDA sigma                         */
+  double plan_ms;          /* host time of planning the contractions of the last
+                              dmrg_build_ops (renorm_ms is then the device time of
+                              its renormalizations alone)                           */
 } dmrg_stats;
 
 int dmrg_get_stats(dmrg_ctx* ctx, dmrg_stats* out);

@@ -53,7 +53,8 @@ class Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_double) for n in (
         "sigma_flops", "sigma_ms", "sigma_main_ms", "sigma_main_flops", "sigma_main_bytes",
         "renorm_flops", "renorm_ms", "op_bytes", "tda_iter_ms", "tda_sigma_flops")] + [
-        ("tda_iters", ctypes.c_int), ("sigma_main_launches", ctypes.c_int), ("tda_sigma_ms", ctypes.c_double)]
+        ("tda_iters", ctypes.c_int), ("sigma_main_launches", ctypes.c_int), ("tda_sigma_ms", ctypes.c_double),
+        ("plan_ms", ctypes.c_double)]
 
 
 class SweepParams(ctypes.Structure):

@@ -8,6 +8,7 @@
 #include "kernels_mfma.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -1206,22 +1207,26 @@ void Ctx::build_ops(int prec) {
   left.resize(L + 1);
   right.resize(L + 1);
   stats.renorm_flops = 0;
+  // all sets and plans first (host planning, timed apart), then the
+  // renormalizations back to back on the stream
+  const auto h0 = std::chrono::steady_clock::now();
+  for (int b = 0; b <= L; ++b) {
+    alloc_opset(left[b], b, 0, 1, false);
+    alloc_opset(right[b], b, 1, 1, false);
+  }
+  for (int i = 0; i < L; ++i) renorm_plan(DMRG_DIR_LEFT, i, left[i], left[i + 1], false);
+  for (int i = L - 1; i >= 0; --i) renorm_plan(DMRG_DIR_RIGHT, i, right[i + 1], right[i], false);
+  stats.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
   hipEvent_t e0, e1;
   DMRG_HIP(hipEventCreate(&e0));
   DMRG_HIP(hipEventCreate(&e1));
   DMRG_HIP(hipEventRecord(e0, stream));
-  alloc_opset(left[0], 0, 0, 1, false);
-  for (int i = 0; i < L; ++i) {
-    alloc_opset(left[i + 1], i + 1, 0, 1, false);
+  for (int i = 0; i < L; ++i)
     renorm(DMRG_DIR_LEFT, i, site[i].L.as<double>(), site[i].L.as<double>(), 0, left[i], left[i + 1], false, 1,
            rprec);
-  }
-  alloc_opset(right[L], L, 1, 1, false);
-  for (int i = L - 1; i >= 0; --i) {
-    alloc_opset(right[i], i, 1, 1, false);
+  for (int i = L - 1; i >= 0; --i)
     renorm(DMRG_DIR_RIGHT, i, site[i].R.as<double>(), site[i].R.as<double>(), 0, right[i + 1], right[i], false, 1,
            rprec);
-  }
   DMRG_HIP(hipEventRecord(e1, stream));
   DMRG_HIP(hipEventSynchronize(e1));
   float ms = 0;
