@@ -50,7 +50,7 @@ template <> struct Cfg<0> {  // FP64
 };
 template <> struct Cfg<1> {  // FP32
   typedef float T;
-  static constexpr int TK = 32, MB = 32;
+  static constexpr int TK = 16, MB = 32;
 };
 template <> struct Cfg<2> {  // BF16x3
   typedef float T;
@@ -60,10 +60,11 @@ template <> struct Cfg<2> {  // BF16x3
 // LDS images of one chunk, one row per output index (tile row of op(A),
 // tile column of op(B)), written four consecutive k at a time.
 //   FP64  : a[i][k], rows padded by one element.
-//   FP32  : a[i][p(k)] with p(k) = 16 (k & 1) + (k >> 1): the 32x32x2 product
-//           at step s takes k = 2s + h in lane half h, so the sixteen values
-//           a lane needs over a chunk are contiguous (four 128-bit reads);
-//           rows padded to 36 elements (16-byte aligned).
+//   FP32  : a[i][p(k)] with p(k) = 8 (k & 1) + (k >> 1) (K-chunks of 16):
+//           the 32x32x2 product at step s takes k = 2s + h in lane half h,
+//           so the eight values a lane needs over a chunk are contiguous
+//           (two 128-bit reads); rows padded to 20 elements (16-byte
+//           aligned).
 //   BF16x3: hi and lo parts, k contiguous, rows padded to a multiple of 16
 //           bytes so that eight consecutive k load as one 128-bit read.
 template <int MODE, int TM, int TN> struct Lds {
@@ -73,9 +74,11 @@ template <int MODE, int TM, int TN> struct Lds {
   T b[2][TN][TK + 1];
 };
 template <int TM, int TN> struct Lds<1, TM, TN> {
-  static constexpr int TK = 32, LD = TK + 4;
+  static constexpr int TK = 16, LD = TK + 4;
   alignas(16) float a[2][TM][LD];
   alignas(16) float b[2][TN][LD];
+  // the finished tile is transposed through this storage (TM x (TN + 8))
+  float spare[TM * (TN + 8) > 2 * (TM + TN) * LD ? TM * (TN + 8) - 2 * (TM + TN) * LD : 1];
 };
 template <int TM, int TN> struct Lds<2, TM, TN> {
   static constexpr int TK = 32, LD = TK + 8;
@@ -98,9 +101,9 @@ template <class T> using gptr = const __attribute__((address_space(1))) T*;
 
 // Four consecutive k (k0 a multiple of 4) of one LDS row.
 __device__ __forceinline__ void put4_f32(float* rowp, int k0, const float* v) {
-  // p(k0) = k0/2 (even k), p(k0 + 1) = 16 + k0/2 (odd k)
+  // p(k0) = k0/2 (even k), p(k0 + 1) = 8 + k0/2 (odd k)
   *reinterpret_cast<float2*>(rowp + (k0 >> 1)) = float2{v[0], v[2]};
-  *reinterpret_cast<float2*>(rowp + 16 + (k0 >> 1)) = float2{v[1], v[3]};
+  *reinterpret_cast<float2*>(rowp + 8 + (k0 >> 1)) = float2{v[1], v[3]};
 }
 __device__ __forceinline__ void put4_bf16(__bf16* hip, __bf16* lop, int k0, const float* v) {
   typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -342,23 +345,23 @@ template <int TM, int TN, int BM, int BN>
 __device__ __forceinline__ void mma(Acc<1, BM, BN>& acc, const Lds<1, TM, TN>& s, int buf, int kv, int wm, int wn,
                                     int lane) {
   typedef float floatx4 __attribute__((ext_vector_type(4)));
-  // all sixteen steps of the chunk are read first (lane half h holds
-  // k = 2s + h at position 16h + s), then the products run back to back
-  const int h = 16 * (lane >> 5);
-  floatx4 av[BM][4], bv[BN][4];
+  // all eight steps of the chunk are read first (lane half h holds
+  // k = 2s + h at position 8h + s), then the products run back to back
+  const int h = 8 * (lane >> 5);
+  floatx4 av[BM][2], bv[BN][2];
 #pragma unroll
   for (int a = 0; a < BM; ++a)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < 2; ++c)
       av[a][c] = *reinterpret_cast<const floatx4*>(&s.a[buf][wm + 32 * a + (lane & 31)][h + 4 * c]);
 #pragma unroll
   for (int b = 0; b < BN; ++b)
 #pragma unroll
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < 2; ++c)
       bv[b][c] = *reinterpret_cast<const floatx4*>(&s.b[buf][wn + 32 * b + (lane & 31)][h + 4 * c]);
   // groups of four steps (8 k); k beyond the chunk's length is zero in LDS
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < 2; ++c) {
     if (8 * c < kv) {
 #pragma unroll
       for (int e = 0; e < 4; ++e)
