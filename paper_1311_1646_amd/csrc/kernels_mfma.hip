@@ -54,7 +54,7 @@ template <> struct Cfg<1> {  // FP32
 };
 template <> struct Cfg<2> {  // BF16x3
   typedef float T;
-  static constexpr int TK = 32, MB = 32;
+  static constexpr int TK = 16, MB = 32;
 };
 
 // LDS images of one chunk, one row per output index (tile row of op(A),
@@ -65,8 +65,9 @@ template <> struct Cfg<2> {  // BF16x3
 //           so the eight values a lane needs over a chunk are contiguous
 //           (two 128-bit reads); rows padded to 20 elements (16-byte
 //           aligned).
-//   BF16x3: hi and lo parts, k contiguous, rows padded to a multiple of 16
-//           bytes so that eight consecutive k load as one 128-bit read.
+//   BF16x3: hi and lo parts, k contiguous (K-chunks of 16, one 32x32x16
+//           product per part pair), rows padded to a multiple of 16 bytes so
+//           that eight consecutive k load as one 128-bit read.
 template <int MODE, int TM, int TN> struct Lds {
   typedef typename Cfg<MODE>::T T;
   static constexpr int TK = Cfg<MODE>::TK;
@@ -81,7 +82,7 @@ template <int TM, int TN> struct Lds<1, TM, TN> {
   float spare[TM * (TN + 8) > 2 * (TM + TN) * LD ? TM * (TN + 8) - 2 * (TM + TN) * LD : 1];
 };
 template <int TM, int TN> struct Lds<2, TM, TN> {
-  static constexpr int TK = 32, LD = TK + 8;
+  static constexpr int TK = 16, LD = TK + 8;
   alignas(16) __bf16 ah[2][TM][LD];
   alignas(16) __bf16 al[2][TM][LD];
   alignas(16) __bf16 bh[2][TN][LD];
