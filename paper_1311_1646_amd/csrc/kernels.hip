@@ -382,29 +382,76 @@ void launch_grouped_gemm_f64(const GTile* tiles, int ntiles, const GJob* jobs, c
   hipLaunchKernelGGL(grouped_gemm_f64_kernel, dim3(ntiles, batch), dim3(NT), 0, s, tiles, jobs, con, gather, b);
 }
 
+// Each thread owns lc_elems<T>() elements a block width apart and reads
+// kLCAhead sources for all of them before applying the coefficients, so a
+// wave keeps several loads in flight instead of one.  Every element still
+// sums its sources in list order.
+template <class T>
+__host__ __device__ constexpr int lc_elems() { return sizeof(T) == 8 ? 2 : 4; }
+constexpr int kLCAhead = 4;
+
 template <class T>
 __global__ __launch_bounds__(256) void lincomb_grouped_kernel(const LCGroup* __restrict__ groups,
                                                               const LCTarget* __restrict__ tg,
                                                               const LCSource* __restrict__ us,
                                                               const double* __restrict__ coef, Bases bs) {
+  constexpr int kElems = lc_elems<T>();
   const LCGroup G = groups[blockIdx.y];
   const long bz = blockIdx.z;
-  for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < G.size; e += long(gridDim.x) * blockDim.x) {
-    T acc[kLCGroup];
+  const long span = long(blockDim.x) * kElems;
+  for (long e0 = long(blockIdx.x) * span + threadIdx.x; e0 < G.size; e0 += long(gridDim.x) * span) {
+    bool in[kElems];
 #pragma unroll
-    for (int k = 0; k < kLCGroup; ++k) acc[k] = T(0);
-    for (int u = G.u0; u < G.u1; ++u) {
+    for (int j = 0; j < kElems; ++j) in[j] = e0 + long(j) * blockDim.x < G.size;
+    T acc[kElems][kLCGroup];
+#pragma unroll
+    for (int j = 0; j < kElems; ++j)
+#pragma unroll
+      for (int k = 0; k < kLCGroup; ++k) acc[j][k] = T(0);
+    int u = G.u0;
+    for (; u + kLCAhead <= G.u1; u += kLCAhead) {
+      T x[kLCAhead][kElems];
+#pragma unroll
+      for (int v = 0; v < kLCAhead; ++v) {
+        const LCSource q = us[u + v];
+        const T* p = reinterpret_cast<const T*>(bs.p[q.base]) + q.off + bz * bs.stride[q.base] + e0;
+#pragma unroll
+        for (int j = 0; j < kElems; ++j) x[v][j] = in[j] ? p[long(j) * blockDim.x] : T(0);
+      }
+#pragma unroll
+      for (int v = 0; v < kLCAhead; ++v)
+#pragma unroll
+        for (int k = 0; k < kLCGroup; ++k) {
+          const T c = T(coef[long(u + v) * kLCGroup + k]);
+#pragma unroll
+          for (int j = 0; j < kElems; ++j) acc[j][k] += c * x[v][j];
+        }
+    }
+    for (; u < G.u1; ++u) {
       const LCSource q = us[u];
-      const T x = reinterpret_cast<const T*>(bs.p[q.base])[q.off + bz * bs.stride[q.base] + e];
+      const T* p = reinterpret_cast<const T*>(bs.p[q.base]) + q.off + bz * bs.stride[q.base] + e0;
+      T x[kElems];
 #pragma unroll
-      for (int k = 0; k < kLCGroup; ++k) acc[k] += T(coef[long(u) * kLCGroup + k]) * x;
+      for (int j = 0; j < kElems; ++j) x[j] = in[j] ? p[long(j) * blockDim.x] : T(0);
+#pragma unroll
+      for (int k = 0; k < kLCGroup; ++k) {
+        const T c = T(coef[long(u) * kLCGroup + k]);
+#pragma unroll
+        for (int j = 0; j < kElems; ++j) acc[j][k] += c * x[j];
+      }
     }
 #pragma unroll
     for (int k = 0; k < kLCGroup; ++k) {
-      if (k >= G.nt) break;
-      const LCTarget t = tg[G.t0 + k];
-      T* o = reinterpret_cast<T*>(bs.p[t.base]) + t.off + bz * bs.stride[t.base] + e;
-      *o = t.accumulate ? *o + acc[k] : acc[k];
+      if (k < G.nt) {
+        const LCTarget t = tg[G.t0 + k];
+        T* o = reinterpret_cast<T*>(bs.p[t.base]) + t.off + bz * bs.stride[t.base] + e0;
+#pragma unroll
+        for (int j = 0; j < kElems; ++j) {
+          if (!in[j]) continue;
+          T* oj = o + long(j) * blockDim.x;
+          *oj = t.accumulate ? *oj + acc[j][k] : acc[j][k];
+        }
+      }
     }
   }
 }
@@ -412,7 +459,8 @@ __global__ __launch_bounds__(256) void lincomb_grouped_kernel(const LCGroup* __r
 void launch_lincomb_grouped(int prec, const LCGroup* g, int ngroups, const LCTarget* t, const LCSource* u,
                             const double* coef, long max_size, const Bases& b, int batch, hipStream_t s) {
   if (ngroups <= 0 || max_size <= 0 || batch <= 0) return;
-  long blocks = (max_size + 255) / 256;
+  const long span = 256L * (prec == 0 ? lc_elems<double>() : lc_elems<float>());
+  long blocks = (max_size + span - 1) / span;
   if (blocks > 1024) blocks = 1024;
   for (int g0 = 0; g0 < ngroups; g0 += 65535) {
     const int ng = ngroups - g0 < 65535 ? ngroups - g0 : 65535;

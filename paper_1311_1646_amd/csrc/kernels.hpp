@@ -73,7 +73,7 @@ void launch_lincomb_f64(const LCTarget* t, int ntargets, const LCSource* src, lo
 // merged, sorted list of sources; each source element is loaded once per
 // group and applied to every target of the group with its coefficient
 // (coef[u * kLCGroup + k], zero where target k does not use source u).
-constexpr int kLCGroup = 8;
+constexpr int kLCGroup = 16;
 struct LCGroup {
   long size;
   int t0, nt, u0, u1;
