@@ -1563,10 +1563,15 @@ void Ctx::autotune(int i, int nvec, int prec, int* shapes, double* best_ms) {
   DBuf cin, sout;
   cin.alloc(this, size_t(n) * nvec * 8);
   sout.alloc(this, size_t(n) * nvec * 8);
-  // inputs: copies of the site's coefficient tensor (timing only)
-  for (int v = 0; v < nvec; ++v)
-    DMRG_HIP(hipMemcpyAsync(cin.as<double>() + long(v) * n, site[i].C.as<double>(), size_t(n) * 8,
-                            hipMemcpyDeviceToDevice, stream));
+  // inputs: copies of the site's coefficient tensor when it has the current
+  // layout's size, else a constant vector (timing only)
+  if (site[i].C.p && site[i].C.bytes >= size_t(n) * 8) {
+    for (int v = 0; v < nvec; ++v)
+      DMRG_HIP(hipMemcpyAsync(cin.as<double>() + long(v) * n, site[i].C.as<double>(), size_t(n) * 8,
+                              hipMemcpyDeviceToDevice, stream));
+  } else {
+    launch_fill_f64(cin.as<double>(), n * nvec, 1.0 / std::sqrt(double(std::max(n, 1L))), stream);
+  }
   const int cand[4] = {-1, TILE_64x64, TILE_128x64, TILE_64x128};
   int keep[2][3];
   for (int r = 0; r < 2; ++r)
