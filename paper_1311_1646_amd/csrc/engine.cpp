@@ -793,12 +793,13 @@ long Ctx::opset_size(int bond, int side) {
   return n;
 }
 
-void Ctx::alloc_opset(OpSet& S, int bond, int side, int nvec, bool first_order, bool reuse) {
+void Ctx::alloc_opset(OpSet& S, int bond, int side, int nvec, bool first_order, bool reuse, bool f32) {
   const BondChannels& B = side == 0 ? H->left_channels(bond) : H->right_channels(bond);
   S.bond = bond;
   S.side = side;
   S.nvec = nvec;
   S.f32_valid = false;
+  S.f32 = f32;
   S.first_order = first_order;
   const uint64_t ident = side == 0 ? chan_key(CH_ID_H, -1, -1) : chan_key(CH_H_ID, -1, -1);
   S.kind.assign(B.ch.size(), REF_OP);
@@ -822,7 +823,7 @@ void Ctx::alloc_opset(OpSet& S, int bond, int side, int nvec, bool first_order, 
     }
   }
   S.per_vec = off;
-  const size_t bytes = std::max<size_t>(size_t(off) * nvec, 1) * 8;
+  const size_t bytes = std::max<size_t>(size_t(off) * nvec, 1) * (f32 ? 4 : 8);
   if (!reuse || S.data.bytes < bytes) S.data.alloc(this, bytes);
 }
 
@@ -1158,7 +1159,10 @@ void Ctx::renorm(int dir, int i, const double* Abra, const double* Aket, long ak
   b.p[B_DST] = dst.ptr();
   b.stride[B_DST] = dst.nvec > 1 ? dst.per_vec : 0;
   ws_dress.ensure(this, std::max<size_t>(size_t(P.dressed_per_vec) * (src_b ? batch : 1), 1) * esz);
-  ws_blk.ensure(this, std::max<size_t>(size_t(P.blocks_per_vec) * (o_b ? batch : 1), 1) * 8);
+  // an FP32 destination takes FP32 building blocks and an FP32 combination
+  const bool dst32 = dst.f32;
+  DMRG_REQUIRE(prec != DMRG_FP64 || (!src.f32 && !dst32), DMRG_ERR_INTERNAL, "FP32 operator set in an FP64 renormalization");
+  ws_blk.ensure(this, std::max<size_t>(size_t(P.blocks_per_vec) * (o_b ? batch : 1), 1) * (dst32 ? 4 : 8));
   ws_T.ensure(this, std::max<size_t>(size_t(P.main.t_per_vec) * (t_b ? batch : 1), 1) * esz);
   b.p[B_DRESS] = ws_dress.as<double>();
   b.stride[B_DRESS] = src_b ? P.dressed_per_vec : 0;
@@ -1168,8 +1172,7 @@ void Ctx::renorm(int dir, int i, const double* Abra, const double* Aket, long ak
   b.stride[B_T] = t_b ? P.main.t_per_vec : 0;
   if (prec != DMRG_FP64) {
     // FP32 operands: operator shadow, site tensors converted per call
-    ensure_f32(src);
-    b.p[B_SRC] = reinterpret_cast<double*>(src.data32.as<float>());
+    b.p[B_SRC] = reinterpret_cast<double*>(f32_data(src));
     const long S = long(layout(i, 1).size);
     const long nket = ket_b ? S * batch : S;
     ws_a32.ensure(this, size_t(S + nket) * 4);
@@ -1182,14 +1185,20 @@ void Ctx::renorm(int dir, int i, const double* Abra, const double* Aket, long ak
     b.stride[B_AKET] = ket_b ? S : 0;
   }
   dst.f32_valid = false;
-  if (!accumulate) launch_fill_f64(dst.ptr(), long(dst.per_vec) * dst.nvec, 0.0, stream);
-  if (P.blocks_per_vec) launch_fill_f64(ws_blk.as<double>(), P.blocks_per_vec * (o_b ? batch : 1), 0.0, stream);
+  const long nblk = P.blocks_per_vec * (o_b ? batch : 1);
+  if (dst32) {
+    if (!accumulate) launch_fill_f32(dst.data.as<float>(), long(dst.per_vec) * dst.nvec, stream);
+    if (nblk) launch_fill_f32(ws_blk.as<float>(), nblk, stream);
+  } else {
+    if (!accumulate) launch_fill_f64(dst.ptr(), long(dst.per_vec) * dst.nvec, 0.0, stream);
+    if (nblk) launch_fill_f64(ws_blk.as<double>(), nblk, 0.0, stream);
+  }
   P.form.launch(*this, b, src_b ? batch : 1, prec);
   for (auto& ch : P.main.chunks) {
     ch.first.launch(*this, b, t_b ? batch : 1, prec, prec == DMRG_FP64);
-    ch.second.launch(*this, b, batch, prec, true);
+    ch.second.launch(*this, b, batch, prec, !dst32);
   }
-  P.post.launch(*this, b, batch);
+  P.post.launch(*this, b, batch, dst32 ? DMRG_FP32 : DMRG_FP64);
   stats.renorm_flops += P.main.flops1 * (t_b ? batch : 1) + P.main.flops2 * batch;
 }
 
@@ -1451,8 +1460,15 @@ ContractionPlan& Ctx::sigma_plan(int i, int width, const OpSet& X, const OpSet& 
   return *(sigma_plans_[key] = std::move(P));
 }
 
+float* Ctx::f32_data(const OpSet& S) {
+  if (S.f32) return S.data.as<float>();
+  ensure_f32(S);
+  return S.data32.as<float>();
+}
+
 void Ctx::ensure_f32(const OpSet& S) {
   OpSet& M = const_cast<OpSet&>(S);
+  DMRG_REQUIRE(!M.f32, DMRG_ERR_INTERNAL, "operator set already held in FP32");
   if (M.f32_valid) return;
   const long n = long(M.per_vec) * M.nvec;
   M.data32.ensure(this, std::max<size_t>(size_t(n), 1) * 4);
@@ -1482,6 +1498,7 @@ void Ctx::sigma_general(int i, int width, const OpSet& X, const OpSet& Z, const 
   b.p[B_T] = ws_T.as<double>();
   b.stride[B_T] = t_b ? P.main.t_per_vec : 0;
   if (prec == DMRG_FP64) {
+    DMRG_REQUIRE(!X.f32 && !Z.f32, DMRG_ERR_INTERNAL, "FP32 operator set in an FP64 sigma");
     b.p[B_CIN] = const_cast<double*>(C);
     b.p[B_LOPS] = X.ptr();
     b.p[B_ROPS] = Z.ptr();
@@ -1491,16 +1508,16 @@ void Ctx::sigma_general(int i, int width, const OpSet& X, const OpSet& Z, const 
       ch.second.launch(*this, b, batch, 0, true, nullptr, 1);
     }
   } else {
-    ensure_f32(X);
-    ensure_f32(Z);
+    float* x32 = f32_data(X);
+    float* z32 = f32_data(Z);
     const long cs = layout(i, width).size;
     const long nc = cb ? cs * batch : cs;
     ws_c32.ensure(this, std::max<size_t>(size_t(nc), 1) * 4);
     launch_convert_f64_f32(C, ws_c32.as<float>(), nc, stream);
     b.p[B_CIN] = reinterpret_cast<double*>(ws_c32.as<float>());
     b.stride[B_CIN] = cb ? cs : 0;
-    b.p[B_LOPS] = reinterpret_cast<double*>(X.data32.as<float>());
-    b.p[B_ROPS] = reinterpret_cast<double*>(Z.data32.as<float>());
+    b.p[B_LOPS] = reinterpret_cast<double*>(x32);
+    b.p[B_ROPS] = reinterpret_cast<double*>(z32);
     P.form.launch(*this, b, dress_b ? batch : 1, prec);
     for (auto& ch : P.main.chunks) {
       ch.first.launch(*this, b, t_b ? batch : 1, prec, false, nullptr);

@@ -59,8 +59,9 @@ struct OpSet {
   std::vector<long> off;
   std::vector<const OpLayout*> lay;
   long per_vec = 0;
+  bool f32 = false;        // data held in FP32 (first-order sets of an FP32 / BF16x3 run)
   DBuf data;
-  DBuf data32;             // FP32 copy for the lower-precision sigma
+  DBuf data32;             // FP32 copy of FP64 data for the lower-precision contractions
   bool f32_valid = false;
   bool valid() const { return bond >= 0; }
   ORef ref(int w, int base) const {
@@ -213,7 +214,7 @@ class Ctx {
   void upload_lambda();
   void build_ops(int prec);
   // reuse: keep the set's buffer when it is large enough (no reallocation)
-  void alloc_opset(OpSet& S, int bond, int side, int nvec, bool first_order, bool reuse = false);
+  void alloc_opset(OpSet& S, int bond, int side, int nvec, bool first_order, bool reuse = false, bool f32 = false);
   long opset_size(int bond, int side);  // elements per vector of the set at (bond, side)
 
   // Renormalization across site i into dst (left: bond i -> i+1; right:
@@ -230,6 +231,9 @@ class Ctx {
                      long sstride, int batch, int prec = 0);
   void sigma(int i, int width, int nvec, const double* Cin, double* Sout, int prec = 0);
   void ensure_f32(const OpSet& S);
+  // FP32 operands of a set: its own data when held in FP32, else the
+  // converted copy
+  float* f32_data(const OpSet& S);
   // events bracketing the dominant (stage-2) launches of a timed sigma
   void mark_main(bool begin);
   bool timing_main_ = false;

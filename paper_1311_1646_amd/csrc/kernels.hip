@@ -115,6 +115,10 @@ __global__ void fill_f64_kernel(double* p, long n, double v) {
   for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += long(gridDim.x) * blockDim.x) p[e] = v;
 }
 
+__global__ void zero_f32_kernel(float* p, long n) {
+  for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += long(gridDim.x) * blockDim.x) p[e] = 0.0f;
+}
+
 __global__ void diag_jobs_f64_kernel(const DiagJob* __restrict__ jobs, const DiagTerm* __restrict__ t, Bases bs) {
   const DiagJob J = jobs[blockIdx.x];
   const int n = J.rows * J.cols;
@@ -512,6 +516,13 @@ void launch_fill_f64(double* p, long n, double v, hipStream_t s) {
   long blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(fill_f64_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, p, n, v);
+}
+
+void launch_fill_f32(float* p, long n, hipStream_t s) {
+  if (n <= 0) return;
+  long blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(zero_f32_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, p, n);
 }
 
 void launch_diag_jobs_f64(const DiagJob* j, int n, const DiagTerm* t, const Bases& b, hipStream_t s) {

@@ -163,7 +163,7 @@ class TdaRunner {
   void reserve(OpSet* sets, int side, int nvec) {
     long mx = 1;
     for (int b = 0; b <= L_; ++b) mx = std::max(mx, x_.opset_size(b, side));
-    const size_t bytes = size_t(mx) * size_t(nvec) * 8;
+    const size_t bytes = size_t(mx) * size_t(nvec) * (prec_ != DMRG_FP64 ? 4 : 8);
     for (int k = 0; k < 2; ++k)
       if (sets[k].data.bytes < bytes) sets[k].data.alloc(&x_, bytes);
   }
@@ -355,7 +355,7 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
   launch_fill_f64(SR_.as<double>(), long(l) * l, 0.0, x_.stream);
   int cur = 0;
   reserve(FL_, 0, l);
-  x_.alloc_opset(FL_[cur], 0, 0, l, true, true);
+  x_.alloc_opset(FL_[cur], 0, 0, l, true, true, prec_ != DMRG_FP64);
   HostRng rng(seed);
   std::vector<double> tmp;
   for (int i = 0; i < L_; ++i) {
@@ -446,7 +446,7 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
     copy(Wk, Ct, long(l) * S);
     scale(i, false, true, Wk, l);
     const int nxt = 1 - cur;
-    x_.alloc_opset(FL_[nxt], i + 1, 0, l, true, true);
+    x_.alloc_opset(FL_[nxt], i + 1, 0, l, true, true, prec_ != DMRG_FP64);
     const double* Li = x_.site[i].L.as<double>();
     x_.renorm(DMRG_DIR_LEFT, i, Li, Li, 0, FL_[cur], FL_[nxt], false, l, prec_);
     x_.renorm(DMRG_DIR_LEFT, i, Li, Wk, S, x_.left[i], FL_[nxt], true, l, prec_);
@@ -462,7 +462,7 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
 void TdaRunner::backward(int l) {
   int cur = 0;
   reserve(FR_, 1, l);
-  x_.alloc_opset(FR_[cur], L_, 1, l, true, true);
+  x_.alloc_opset(FR_[cur], L_, 1, l, true, true, prec_ != DMRG_FP64);
   double* Cb = Cb_.as<double>();
   copy(Cb, Ct_[L_ - 1].as<double>(), long(l) * size_[L_ - 1]);
   for (int i = L_ - 1; i >= 0; --i) {
@@ -480,7 +480,7 @@ void TdaRunner::backward(int l) {
     if (i == 0) break;
     // first-order right operators (eq. ropr1st)
     const int nxt = 1 - cur;
-    x_.alloc_opset(FR_[nxt], i, 1, l, true, true);
+    x_.alloc_opset(FR_[nxt], i, 1, l, true, true, prec_ != DMRG_FP64);
     x_.renorm(DMRG_DIR_RIGHT, i, Ri, Ri, 0, FR_[cur], FR_[nxt], false, l, prec_);
     x_.renorm(DMRG_DIR_RIGHT, i, Ri, R1, S, x_.right[i + 1], FR_[nxt], true, l, prec_);
     // gauge shift to site i-1 (eq. gauge_bwd): C_{i-1} = C~_{i-1} + L_{i-1} (C_i R_i^T)
