@@ -1194,6 +1194,8 @@ void Ctx::renorm(int dir, int i, const double* Abra, const double* Aket, long ak
     if (nblk) launch_fill_f64(ws_blk.as<double>(), nblk, 0.0, stream);
   }
   P.form.launch(*this, b, src_b ? batch : 1, prec);
+  // both stages run with the products tag: the block-cyclic XCD order of
+  // that instantiation is faster for the renormalization's accumulation
   for (auto& ch : P.main.chunks) {
     ch.first.launch(*this, b, t_b ? batch : 1, prec, prec == DMRG_FP64);
     ch.second.launch(*this, b, batch, prec, !dst32);
