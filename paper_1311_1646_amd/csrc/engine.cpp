@@ -216,8 +216,8 @@ const GemmPlan::FoldTiles& GemmPlan::fold_lists(Ctx& x, int fold, int batch, int
 
 void LinCombPlan::launch(Ctx& x, const Bases& b, int batch, int prec) const {
   if (ng)
-    launch_lincomb_grouped(prec, g.as<LCGroup>(), ng, t.as<LCTarget>(), u.as<LCSource>(), coef.as<double>(), max_size,
-                           b, batch, x.stream);
+    launch_lincomb_grouped(prec, g.as<LCGroup>(), ng, t.as<LCTarget>(), u.as<LCSource>(), coef.as<double>(),
+                           coef32.as<float>(), max_size, b, batch, x.stream);
   if (nd) {
     if (prec == 0) launch_diag_add_f64(d.as<DiagAdd>(), nd, b, batch, x.stream);
     else launch_diag_add_f32(d.as<DiagAdd>(), nd, b, batch, x.stream);
@@ -283,6 +283,7 @@ struct LinCombBuilder {
     upload(x, P.t, tg);
     upload(x, P.u, us);
     upload(x, P.coef, cf);
+    upload(x, P.coef32, std::vector<float>(cf.begin(), cf.end()));
     upload(x, P.g, gr);
     upload(x, P.d, d);
     P.nt = int(tg.size());

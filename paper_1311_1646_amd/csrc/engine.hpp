@@ -112,7 +112,7 @@ void build_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<s
                      const std::vector<int>& gather = {});
 
 struct LinCombPlan {
-  DBuf t, s, d, g, u, coef;
+  DBuf t, s, d, g, u, coef, coef32;  // coef32: the coefficients rounded to FP32
   int nt = 0, nd = 0, ng = 0;
   long max_size = 0;
   double elems = 0, reads = 0;  // plan statistics: target elements, source element reads

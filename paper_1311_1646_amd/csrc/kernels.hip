@@ -398,7 +398,7 @@ template <class T>
 __global__ __launch_bounds__(256) void lincomb_grouped_kernel(const LCGroup* __restrict__ groups,
                                                               const LCTarget* __restrict__ tg,
                                                               const LCSource* __restrict__ us,
-                                                              const double* __restrict__ coef, Bases bs) {
+                                                              const T* __restrict__ coef, Bases bs) {
   constexpr int kElems = lc_elems<T>();
   const LCGroup G = groups[blockIdx.y];
   const long bz = blockIdx.z;
@@ -426,7 +426,7 @@ __global__ __launch_bounds__(256) void lincomb_grouped_kernel(const LCGroup* __r
       for (int v = 0; v < kLCAhead; ++v)
 #pragma unroll
         for (int k = 0; k < kLCGroup; ++k) {
-          const T c = T(coef[long(u + v) * kLCGroup + k]);
+          const T c = coef[long(u + v) * kLCGroup + k];
 #pragma unroll
           for (int j = 0; j < kElems; ++j) acc[j][k] += c * x[v][j];
         }
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(256) void lincomb_grouped_kernel(const LCGroup* __r
       for (int j = 0; j < kElems; ++j) x[j] = in[j] ? p[long(j) * blockDim.x] : T(0);
 #pragma unroll
       for (int k = 0; k < kLCGroup; ++k) {
-        const T c = T(coef[long(u) * kLCGroup + k]);
+        const T c = coef[long(u) * kLCGroup + k];
 #pragma unroll
         for (int j = 0; j < kElems; ++j) acc[j][k] += c * x[j];
       }
@@ -461,7 +461,8 @@ __global__ __launch_bounds__(256) void lincomb_grouped_kernel(const LCGroup* __r
 }
 
 void launch_lincomb_grouped(int prec, const LCGroup* g, int ngroups, const LCTarget* t, const LCSource* u,
-                            const double* coef, long max_size, const Bases& b, int batch, hipStream_t s) {
+                            const double* coef, const float* coef32, long max_size, const Bases& b, int batch,
+                            hipStream_t s) {
   if (ngroups <= 0 || max_size <= 0 || batch <= 0) return;
   const long span = 256L * (prec == 0 ? lc_elems<double>() : lc_elems<float>());
   long blocks = (max_size + span - 1) / span;
@@ -472,7 +473,7 @@ void launch_lincomb_grouped(int prec, const LCGroup* g, int ngroups, const LCTar
     if (prec == 0)
       hipLaunchKernelGGL(lincomb_grouped_kernel<double>, grid, dim3(256), 0, s, g + g0, t, u, coef, b);
     else
-      hipLaunchKernelGGL(lincomb_grouped_kernel<float>, grid, dim3(256), 0, s, g + g0, t, u, coef, b);
+      hipLaunchKernelGGL(lincomb_grouped_kernel<float>, grid, dim3(256), 0, s, g + g0, t, u, coef32, b);
   }
 }
 

@@ -78,9 +78,11 @@ struct LCGroup {
   long size;
   int t0, nt, u0, u1;
 };
-// prec 0: FP64 data; otherwise FP32 data (coefficients applied in FP32)
+// prec 0: FP64 data and coefficients coef; otherwise FP32 data and the
+// same coefficients rounded to FP32 (coef32)
 void launch_lincomb_grouped(int prec, const LCGroup* g, int ngroups, const LCTarget* t, const LCSource* u,
-                            const double* coef, long max_size, const Bases& b, int batch, hipStream_t s);
+                            const double* coef, const float* coef32, long max_size, const Bases& b, int batch,
+                            hipStream_t s);
 
 // Strided 2-D copies dst(r, c) = src(r, c) * scale, element (r, c) at
 // r*ss_r + c*ss_c in the source and r*ds_r + c*ds_c in the destination;
