@@ -54,8 +54,7 @@ def cpu_baseline(nvec):
     import paper_1311_1646_amd as lib
     import synth
     from oracle import fci, mpsvec
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from helpers import mps_arrays
+    from synth import mps_arrays
 
     p = synth.config(0)
     mps = synth.random_mps(p.L, p.Na, p.Nb, p.M, seed=17)
@@ -167,8 +166,7 @@ def main():
 
     import paper_1311_1646_amd as lib
     import synth
-    sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from helpers import mps_arrays
+    from synth import mps_arrays
 
     if a.copy_calib:
         src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")

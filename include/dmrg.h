@@ -53,41 +53,75 @@ enum {
  * matrices are FP64 in every mode. */
 enum { DMRG_FP64 = 0, DMRG_FP32 = 1, DMRG_BF16X3 = 2 };
 
-/* Kinds of sigma (Sec. III B-D):
+/* Kinds of sigma (Sec. II A eq. dmrg; Sec. III B-D):
  *  ZEROTH_1SITE : sigma = H_0^[i] C, the one-site effective Hamiltonian
- *                 L_{i-1} x h_i x R_i (eq. hzero_sb) applied to nvec vectors.
- *  ZEROTH_2SITE : the two-site effective Hamiltonian on sites (i, i+1).
- *  TDA_FULL     : sigma_i^mu of eq. sigv1 for the TDA trial vectors held by the
- *                 library (internal use by dmrg_tda_roots; not callable).
- *  TDA_DH_LEFT  : the first-order left part of eq. sigv2 (internal). */
+ *                 L_{i-1} x h_i x R_i (Sec. III B, eq. hzero_sb) applied to
+ *                 nvec vectors.
+ *  ZEROTH_2SITE : the two-site effective Hamiltonian on sites (i, i+1)
+ *                 (Sec. II A, the site problem on two sites).
+ *  TDA_FULL     : the TDA sigma of Sec. III D, eq. sigv1 with Delta-sigma of
+ *                 eq. sigv2, for nvec first-order wavefunctions:
+ *                   sigma^mu = H_0^[i] C^mu(1)
+ *                            + [H_mu^{L} x h_i x H_0^{R}] C_i^(0)
+ *                            + [H_0^{L} x h_i x H_mu^{R}] C_i^(0),
+ *                 where C_in holds C_i^{mu(1)}, C_i^(0) is the imported centre
+ *                 tensor at site i, and H_mu^{L} / H_mu^{R} are the
+ *                 first-order block operators (Sec. III B eq. lopr1st, Sec.
+ *                 III D eq. ropr1st) built beforehand by dmrg_renormalize
+ *                 with order DMRG_FIRST: the left chain must end at bond i
+ *                 and the right chain at bond i+1 (the left part is zero at
+ *                 site 0 and the right part at site L-1, where no chain is
+ *                 needed).  Width 1 only.
+ *  TDA_DH_LEFT  : the first line of eq. sigv2 alone, applied to the given
+ *                 vectors: sigma^mu = [H_mu^{L} x h_i x H_0^{R}] C_in^mu
+ *                 (the left chain must end at bond i; zero at site 0). */
 enum { DMRG_SIGMA_ZEROTH_1SITE = 0, DMRG_SIGMA_ZEROTH_2SITE = 1,
        DMRG_SIGMA_TDA_FULL = 2, DMRG_SIGMA_TDA_DH_LEFT = 3 };
+
+/* Order of a renormalization (dmrg_renormalize). */
+enum { DMRG_ZEROTH = 0, DMRG_FIRST = 1 };
 
 enum { DMRG_DIR_LEFT = 0, DMRG_DIR_RIGHT = 1 };
 
 typedef struct dmrg_ctx dmrg_ctx;
 
+/* Device allocator of a context.  The library owns its operator pools, MPS
+ * tensors, plans and workspaces; with this callback their device memory comes
+ * from the caller's memory manager (e.g. a framework's caching allocator).
+ * alloc returns memory usable in stream order on the context's stream, or
+ * NULL (the call then fails with DMRG_ERR_OOM); free receives exactly the
+ * pointers alloc returned, after the work that used them was enqueued on the
+ * context's stream.  NULL members mean hipMalloc / hipFree. */
 typedef struct {
-  /* optional device allocator; NULL members mean hipMalloc/hipFree */
   void* (*alloc)(size_t bytes, void* stream, void* user);
   void (*free)(void* ptr, void* user);
   void* user;
 } dmrg_allocator;
 
-/* Create a context for L orbitals and (n_alpha, n_beta) electrons.
+/* Create a context for L orbitals and (n_alpha, n_beta) electrons: the
+ * quantum-chemical Hamiltonian of real orbitals in second quantization
+ * (the H of Sec. II A, eq. dmrg) with one-electron integrals h, two-electron
+ * integrals eri and the constant ecore.
  * The integrals are copied; the caller keeps ownership of h and eri.
  * device < 0 creates a host-only context on which only the host/test-support
  * calls (dmrg_debug_*, layout queries) are valid.  stream: a hipStream_t or
- * NULL for the null stream.  alloc may be NULL.
- * Errors: INVALID_ARG (sizes, electron counts), HIP_ERROR, OOM. */
+ * NULL for the null stream.  alloc may be NULL (hipMalloc / hipFree); the
+ * struct is copied.
+ * Errors: INVALID_ARG (L outside [2, 128], electron counts, null integrals),
+ * HIP_ERROR, OOM. */
 int dmrg_create(int L, int n_alpha, int n_beta, const double* h, const double* eri,
                 double ecore, int device, void* stream, const dmrg_allocator* alloc,
                 dmrg_ctx** out);
+/* Release the context and everything it owns (waits for nothing: the caller
+ * synchronizes its stream first if work is still queued).  INVALID_ARG on NULL. */
 int dmrg_destroy(dmrg_ctx* ctx);
+/* Message of the last failed call on ctx (of the last failed dmrg_create when
+ * ctx is NULL); owned by the library, valid until the next call on ctx. */
 const char* dmrg_last_error(const dmrg_ctx* ctx);
 
 /* Number of channels (normal + complementary operators) of the block
- * operator sets at bond b: the "x" summation of eq. hzero_sb made explicit. */
+ * operator sets at bond b: the "x" summation over complementary operators
+ * of Sec. III B (eq. hzero_sb) made explicit.  INVALID_ARG on a bad bond. */
 int dmrg_num_channels(dmrg_ctx* ctx, int bond, int* out);
 
 /* Import a mixed-canonical MPS (host FP64; copied to the device).
@@ -102,16 +136,18 @@ int dmrg_num_channels(dmrg_ctx* ctx, int bond, int* out);
 int dmrg_import_mps(dmrg_ctx* ctx, const int* nsec, const int* sectors, const double* Ldata,
                     const double* Rdata, const double* Cdata, const double* lam);
 
-/* Export the current MPS in the same format.  Call with NULL data pointers
- * to get the sizes: nsec_out must hold L+1 ints; sizes_out[0..3] receives the
- * number of sector triples and the lengths of L/R/C data and of lam. */
+/* Export the current MPS in the same format (Sec. II A, eq. gauge-shift).
+ * Call with NULL data pointers to get the sizes: nsec_out must hold L+1
+ * ints; sizes_out[0..3] receives the number of sector triples and the
+ * lengths of L/R/C data and of lam.  Errors: STATE without an MPS. */
 int dmrg_export_mps(dmrg_ctx* ctx, int* nsec_out, int* sectors_out, double* Ldata,
                     double* Rdata, double* Cdata, double* lam, size_t* sizes_out);
 
 /* Layout of the one-site (width 1) or two-site (width 2) coefficient tensor
- * at `site`: nblocks_out receives the block count; if blocks_out is non-NULL
- * it receives 6 ints per block (a, n, c, rows, cols, offset); size_out
- * receives the element count. */
+ * at `site` (the C_i of Sec. II A, eq. mps_wave, blocked by the symmetry
+ * sectors of its bonds): nblocks_out receives the block count; if blocks_out
+ * is non-NULL it receives 6 ints per block (a, n, c, rows, cols, offset);
+ * size_out receives the element count.  STATE without an MPS. */
 int dmrg_get_layout(dmrg_ctx* ctx, int site, int width, int* nblocks_out, int* blocks_out,
                     size_t* size_out);
 
@@ -124,13 +160,19 @@ int dmrg_get_layout(dmrg_ctx* ctx, int site, int width, int* nblocks_out, int* b
  * lower-precision sigma.  Errors: STATE without an MPS, INVALID_ARG. */
 int dmrg_build_ops(dmrg_ctx* ctx, int prec);
 
-/* Sigma vectors: sigma = H_eff C for nvec vectors (Sec. II A eq. dmrg and
- * Sec. III B eq. hzero_sb).  C_in and sigma_out are device FP64 arrays of
- * nvec * size elements (vector-major, each vector in the flat layout of the
- * one-site tensor at `site` or of the two-site tensor at (site, site+1)).
- * Requires dmrg_build_ops.  Errors: STATE before build_ops, INVALID_ARG. */
+/* Sigma vectors (Sec. II A eq. dmrg; Sec. III B eq. hzero_sb; Sec. III D
+ * eqs. sigv1, sigv2 for the TDA kinds, see above).  C_in and sigma_out are
+ * device FP64 arrays of len = nvec * size elements each (vector-major, each
+ * vector in the flat layout of the one-site tensor at `site` or of the
+ * two-site tensor at (site, site+1); size from dmrg_get_layout).  Both are
+ * borrowed for the (stream-ordered) call and must not overlap.  prec is the
+ * arithmetic of the contractions.  Requires dmrg_build_ops.
+ * Errors: STATE before build_ops or when a TDA kind finds the first-order
+ * chains at other bonds; INVALID_ARG on a bad site / kind / nvec, a len that
+ * is not nvec * size, null pointers, or a TDA kind whose chains hold another
+ * nvec (or FP32 sets for an FP64 sigma). */
 int dmrg_sigma(dmrg_ctx* ctx, int site, int kind, int nvec, const double* C_in,
-               double* sigma_out, int prec);
+               double* sigma_out, size_t len, int prec);
 
 /* Tile-shape autotuner of the grouped block GEMM (the contractions of Sec.
  * III B-D): times the one-site sigma at `site` for nvec vectors in precision
@@ -143,15 +185,38 @@ int dmrg_sigma(dmrg_ctx* ctx, int site, int kind, int nvec, const double* C_in,
  * the call.  Errors: STATE before build_ops, INVALID_ARG. */
 int dmrg_autotune(dmrg_ctx* ctx, int site, int nvec, int prec, int* shapes_out, double* best_ms_out);
 
-/* Diagonal of the one-site effective Hamiltonian at `site` (the Davidson
- * preconditioner of eq. error), written to a device FP64 array of `size`. */
-int dmrg_diag(dmrg_ctx* ctx, int site, int width, double* diag_out, int prec);
+/* Diagonal of the one-site (width 1) or two-site (width 2) effective
+ * Hamiltonian at `site`, the Davidson preconditioner of Sec. III D eq. error,
+ * written to a device FP64 array of len = size elements.  prec must be FP64.
+ * Errors: STATE before build_ops, INVALID_ARG (len, precision). */
+int dmrg_diag(dmrg_ctx* ctx, int site, int width, double* diag_out, size_t len, int prec);
 
-/* Recompute the zeroth-order block operators of one bond from the current
- * MPS: dir LEFT builds H_0^{L_{site+1}} from H_0^{L_site} and L_site; RIGHT
- * builds H_0^{R_site} from H_0^{R_{site+1}} and R_site.  order must be 0
- * (first-order sets are internal to dmrg_tda_roots). */
-int dmrg_renormalize(dmrg_ctx* ctx, int site, int dir, int order, int prec);
+/* Renormalization of block operators across one site.
+ * order DMRG_ZEROTH: recompute the zeroth-order operators of one bond from
+ *   the current MPS (the operators "known from the ground-state DMRG" of
+ *   Sec. III B): dir LEFT builds H_0^{L_{site+1}} from H_0^{L_site} and L_site;
+ *   RIGHT builds H_0^{R_site} from H_0^{R_{site+1}} and R_site.  nvec must be
+ *   0 and A1 NULL.
+ * order DMRG_FIRST: grow a chain of first-order operators (bra zeroth order,
+ *   ket first order) by one site, for nvec first-order tensors at once:
+ *   LEFT (Sec. III B, eq. lopr1st):
+ *     H_mu^{L_{site+1}} = L^T [H_mu^{L_site} x h] L + L^T [H_0^{L_site} x h] L^{mu(1)}
+ *   with A1 = L_site^{mu(1)}; the chain starts at site 0 (from the empty
+ *   block) and every later call must be at the site where the chain ends.
+ *   RIGHT (Sec. III D, eq. ropr1st): the mirror image with A1 = R_site^{mu(1)},
+ *   starting at site L-1 and moving left.
+ *   A1 is a device FP64 array of len = nvec * size(site) elements in the flat
+ *   one-site layout, borrowed for the call.  The library applies the gauge
+ *   condition of the first-order tensors (Sec. II B, eqs. left-orthoSeb,
+ *   right-orthoSeb) itself: it uses Q^L A1 = A1 - L (L^T A1) (left) or
+ *   A1 Q^R = A1 - (A1 R^T) R (right), per symmetry block.  The chain's sets
+ *   are held in FP64 for prec FP64 and in FP32 otherwise; they are used by
+ *   the TDA sigma kinds of dmrg_sigma and dropped by dmrg_import_mps,
+ *   dmrg_build_ops and dmrg_sweep_ground.
+ * Errors: STATE (before build_ops, chain at another bond), INVALID_ARG (site,
+ * dir, order, nvec or precision class differing from the chain's, len). */
+int dmrg_renormalize(dmrg_ctx* ctx, int site, int dir, int order, int nvec, const double* A1,
+                     size_t len, int prec);
 
 typedef struct {
   int nsweeps;            /* two-site sweeps (left->right->left counts 1)  */

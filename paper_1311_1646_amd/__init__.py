@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdmrg.so")
 
 FP64, FP32, BF16X3 = 0, 1, 2
-SIGMA_ZEROTH_1SITE, SIGMA_ZEROTH_2SITE = 0, 1
+SIGMA_ZEROTH_1SITE, SIGMA_ZEROTH_2SITE, SIGMA_TDA_FULL, SIGMA_TDA_DH_LEFT = 0, 1, 2, 3
+ZEROTH, FIRST = 0, 1
 DIR_LEFT, DIR_RIGHT = 0, 1
 
 _ERRORS = {
@@ -83,14 +84,45 @@ _import = _sig("dmrg_import_mps", _P, _IP, _IP, _DP, _DP, _DP, _DP)
 _export = _sig("dmrg_export_mps", _P, _IP, _IP, _DP, _DP, _DP, _DP, _SP)
 _layout = _sig("dmrg_get_layout", _P, _I, _I, _IP, _IP, _SP)
 _build_ops = _sig("dmrg_build_ops", _P, _I)
-_sigma = _sig("dmrg_sigma", _P, _I, _I, _I, _P, _P, _I)
-_diag = _sig("dmrg_diag", _P, _I, _I, _P, _I)
+_Z = ctypes.c_size_t
+_sigma = _sig("dmrg_sigma", _P, _I, _I, _I, _P, _P, _Z, _I)
+_diag = _sig("dmrg_diag", _P, _I, _I, _P, _Z, _I)
 _autotune = _sig("dmrg_autotune", _P, _I, _I, _I, _IP, _DP)
-_renorm = _sig("dmrg_renormalize", _P, _I, _I, _I, _I)
+_renorm = _sig("dmrg_renormalize", _P, _I, _I, _I, _I, _P, _Z, _I)
 _sweep = _sig("dmrg_sweep_ground", _P, ctypes.POINTER(SweepParams), _DP, _DP)
 _tda = _sig("dmrg_tda_roots", _P, _I, ctypes.POINTER(DavidsonParams), _DP, _DP, _DP, _IP)
 _stats = _sig("dmrg_get_stats", _P, ctypes.POINTER(Stats))
 _debug_dense = _sig("dmrg_debug_mpo_dense", _P, _I, _I, _DP)
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", ctypes.c_void_p)]
+
+
+def _torch_allocator(device):
+    """dmrg_allocator backed by torch's caching allocator: the library's
+    device memory (operator pools, MPS tensors, plans, workspaces) is then
+    owned and recycled by torch, in stream order on the context's stream."""
+    import torch
+
+    def alloc(nbytes, stream, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream or 0)
+        except Exception:  # out of memory: the library reports DMRG_ERR_OOM
+            return None
+
+    def free(ptr, user):
+        if ptr:
+            try:
+                torch.cuda.caching_allocator_delete(ptr)
+            except Exception:  # interpreter shutdown: torch's pool is already gone
+                pass
+
+    return Allocator(_ALLOC_FN(alloc), _FREE_FN(free), None)
 
 
 def _dp(a):
@@ -105,18 +137,28 @@ class Context:
     """One problem (integrals, electron numbers) on one GPU (device >= 0) or
     host-only (device < 0: layout and test-support calls only)."""
 
-    def __init__(self, L, n_alpha, n_beta, h, eri, ecore=0.0, device=0, stream=None):
+    def __init__(self, L, n_alpha, n_beta, h, eri, ecore=0.0, device=0, stream=None, allocator="torch"):
+        """allocator: "torch" (device memory from torch's caching allocator)
+        or "hip" (the library's own hipMalloc / hipFree)."""
         self.L, self.na, self.nb = L, n_alpha, n_beta
         h = np.ascontiguousarray(h, dtype=np.float64)
         eri = np.ascontiguousarray(eri, dtype=np.float64)
+        if h.shape != (L, L) or eri.shape != (L, L, L, L):
+            raise ValueError(f"integrals must have shapes ({L}, {L}) and ({L},) * 4")
+        if allocator not in ("torch", "hip"):
+            raise ValueError("allocator must be 'torch' or 'hip'")
         if stream is None and device >= 0:
             import torch
             torch.cuda.set_device(device)
             stream = torch.cuda.current_stream(device).cuda_stream
         self.device = device
+        self._sizes = {}
+        self._alloc = _torch_allocator(device) if (allocator == "torch" and device >= 0) else None
         self._h = ctypes.c_void_p()
         rc = _create(L, n_alpha, n_beta, _dp(h), _dp(eri), float(ecore), device,
-                     ctypes.c_void_p(stream or 0), None, ctypes.byref(self._h))
+                     ctypes.c_void_p(stream or 0),
+                     ctypes.cast(ctypes.pointer(self._alloc), _P) if self._alloc is not None else None,
+                     ctypes.byref(self._h))
         if rc != 0:
             raise DMRGError(rc, _lib.dmrg_last_error(None).decode())
 
@@ -126,6 +168,9 @@ class Context:
 
     def close(self):
         if self._h:
+            if self._alloc is not None:
+                import torch
+                torch.cuda.synchronize(self.device)  # freed blocks go back to torch's pool
             _destroy(self._h)
             self._h = ctypes.c_void_p()
 
@@ -146,6 +191,7 @@ class Context:
         sectors = np.ascontiguousarray(sectors, np.int32)
         arrs = [np.ascontiguousarray(a, np.float64) for a in (Ldata, Rdata, Cdata, lam)]
         self._check(_import(self._h, _ip(nsec), _ip(sectors), *[_dp(a) for a in arrs]))
+        self._sizes = {}
 
     def export_mps(self):
         nsec = np.zeros(self.L + 1, np.int32)
@@ -169,19 +215,53 @@ class Context:
         self._check(_layout(self._h, site, width, ctypes.byref(nb), _ip(blocks), ctypes.byref(size)))
         return blocks.reshape(-1, 6), size.value
 
+    def size(self, site, width=1):
+        """Element count of the coefficient tensor at `site` (cached)."""
+        key = (site, width)
+        if key not in self._sizes:
+            size = ctypes.c_size_t()
+            self._check(_layout(self._h, site, width, None, None, ctypes.byref(size)))
+            self._sizes[key] = size.value
+        return self._sizes[key]
+
+    def _vectors(self, name, t, size, nvec=None):
+        """Check a device vector argument (float64, this context's GPU,
+        contiguous, shape (size,) or (nvec, size)) and return its nvec."""
+        import torch
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.dtype != torch.float64:
+            raise ValueError(f"{name} must be float64, got {t.dtype}")
+        if t.device != torch.device("cuda", self.device):
+            raise ValueError(f"{name} must be on cuda:{self.device}, got {t.device}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        if t.dim() not in (1, 2) or t.shape[-1] != size or t.numel() == 0:
+            raise ValueError(f"{name} must have shape ({size},) or (nvec, {size}), got {tuple(t.shape)}")
+        n = 1 if t.dim() == 1 else t.shape[0]
+        if nvec is not None and n != nvec:
+            raise ValueError(f"{name} holds {n} vectors, expected {nvec}")
+        return n
+
     # ---- compute
     def build_ops(self, prec=FP64):
         self._check(_build_ops(self._h, prec))
 
     def sigma(self, site, C, kind=SIGMA_ZEROTH_1SITE, prec=FP64, out=None):
-        """C: torch float64 CUDA tensor (nvec, size) or (size,)."""
+        """sigma = H_eff C (see dmrg_sigma).  C: float64 tensor on the
+        context's GPU, (nvec, size) or (size,); out, when given, the same."""
         import torch
-        assert C.dtype == torch.float64 and C.is_cuda and C.is_contiguous()
-        nvec = 1 if C.dim() == 1 else C.shape[0]
+        width = 2 if kind == SIGMA_ZEROTH_2SITE else 1
+        size = self.size(site, width)
+        nvec = self._vectors("C", C, size)
         if out is None:
             out = torch.empty_like(C)
+        else:
+            self._vectors("out", out, size, nvec)
+            if out.data_ptr() == C.data_ptr():
+                raise ValueError("out must not alias C")
         self._check(_sigma(self._h, site, kind, nvec, ctypes.c_void_p(C.data_ptr()),
-                           ctypes.c_void_p(out.data_ptr()), prec))
+                           ctypes.c_void_p(out.data_ptr()), C.numel(), prec))
         return out
 
     def autotune(self, site, nvec, prec=FP32):
@@ -194,13 +274,23 @@ class Context:
 
     def diag(self, site, width=1, prec=FP64):
         import torch
-        _, size = self.layout(site, width)
+        size = self.size(site, width)
         out = torch.empty(size, dtype=torch.float64, device=f"cuda:{self.device}")
-        self._check(_diag(self._h, site, width, ctypes.c_void_p(out.data_ptr()), prec))
+        self._check(_diag(self._h, site, width, ctypes.c_void_p(out.data_ptr()), size, prec))
         return out
 
-    def renormalize(self, site, direction, order=0, prec=FP64):
-        self._check(_renorm(self._h, site, direction, order, prec))
+    def renormalize(self, site, direction, order=ZEROTH, prec=FP64, A1=None):
+        """order ZEROTH: recompute the zeroth-order operators across `site`.
+        order FIRST: grow the first-order chain of `direction` by `site` with
+        the first-order tensors A1 ((nvec, size) float64 on the GPU)."""
+        if order == ZEROTH:
+            if A1 is not None:
+                raise ValueError("zeroth-order renormalization takes no tensors")
+            self._check(_renorm(self._h, site, direction, order, 0, None, 0, prec))
+            return
+        nvec = self._vectors("A1", A1, self.size(site, 1))
+        self._check(_renorm(self._h, site, direction, order, nvec, ctypes.c_void_p(A1.data_ptr()),
+                            A1.numel(), prec))
 
     def sweep_ground(self, M_schedule, noise=None, davidson_tol=1e-12, davidson_max_iter=40,
                      seed=1, prec=FP64, verbose=0):
@@ -211,6 +301,7 @@ class Context:
         e = ctypes.c_double()
         dw = ctypes.c_double()
         rc = _sweep(self._h, ctypes.byref(p), ctypes.byref(e), ctypes.byref(dw))
+        self._sizes = {}
         if rc not in (0, -3):
             self._check(rc)
         return e.value, dw.value, rc == 0

@@ -1,6 +1,7 @@
 // extern "C" entry points (see include/dmrg.h).
 #include <cstring>
 #include <new>
+#include <string>
 
 #include "engine.hpp"
 
@@ -122,12 +123,23 @@ int dmrg_build_ops(dmrg_ctx* ctx, int prec) {
   });
 }
 
-int dmrg_sigma(dmrg_ctx* ctx, int site, int kind, int nvec, const double* C_in, double* sigma_out, int prec) {
+int dmrg_sigma(dmrg_ctx* ctx, int site, int kind, int nvec, const double* C_in, double* sigma_out, size_t len,
+               int prec) {
   return guard(ctx, [&](dmrg::Ctx& x) {
+    x.require_gpu();
     DMRG_REQUIRE(valid_prec(prec), DMRG_ERR_INVALID_ARG, "unsupported precision");
-    DMRG_REQUIRE(kind == DMRG_SIGMA_ZEROTH_1SITE || kind == DMRG_SIGMA_ZEROTH_2SITE, DMRG_ERR_INVALID_ARG,
-                 "TDA sigma kinds are internal to dmrg_tda_roots");
-    x.sigma(site, kind == DMRG_SIGMA_ZEROTH_1SITE ? 1 : 2, nvec, C_in, sigma_out, prec);
+    DMRG_REQUIRE(kind >= DMRG_SIGMA_ZEROTH_1SITE && kind <= DMRG_SIGMA_TDA_DH_LEFT, DMRG_ERR_INVALID_ARG,
+                 "unknown sigma kind");
+    DMRG_REQUIRE(nvec >= 1 && C_in && sigma_out, DMRG_ERR_INVALID_ARG, "need nvec >= 1 and non-null arrays");
+    DMRG_REQUIRE(x.have_mps, DMRG_ERR_STATE, "no MPS");
+    const int width = kind == DMRG_SIGMA_ZEROTH_2SITE ? 2 : 1;
+    DMRG_REQUIRE(site >= 0 && site + width <= x.L, DMRG_ERR_INVALID_ARG, "bad site");
+    const size_t size = x.layout(site, width).size;
+    DMRG_REQUIRE(len == size * size_t(nvec), DMRG_ERR_INVALID_ARG,
+                 "len " + std::to_string(len) + " is not nvec * size = " + std::to_string(nvec) + " * " +
+                     std::to_string(size));
+    if (kind <= DMRG_SIGMA_ZEROTH_2SITE) x.sigma(site, width, nvec, C_in, sigma_out, prec);
+    else x.sigma_tda(site, kind, nvec, C_in, sigma_out, prec);
   });
 }
 
@@ -139,21 +151,37 @@ int dmrg_autotune(dmrg_ctx* ctx, int site, int nvec, int prec, int* shapes_out, 
   });
 }
 
-int dmrg_diag(dmrg_ctx* ctx, int site, int width, double* diag_out, int prec) {
+int dmrg_diag(dmrg_ctx* ctx, int site, int width, double* diag_out, size_t len, int prec) {
   return guard(ctx, [&](dmrg::Ctx& x) {
+    x.require_gpu();
     DMRG_REQUIRE(prec == DMRG_FP64, DMRG_ERR_INVALID_ARG, "unsupported precision");
+    DMRG_REQUIRE(diag_out, DMRG_ERR_INVALID_ARG, "null output");
+    DMRG_REQUIRE(x.have_mps, DMRG_ERR_STATE, "no MPS");
+    DMRG_REQUIRE(width >= 1 && width <= 2 && site >= 0 && site + width <= x.L, DMRG_ERR_INVALID_ARG,
+                 "bad site/width");
+    DMRG_REQUIRE(len == x.layout(site, width).size, DMRG_ERR_INVALID_ARG, "len is not the tensor size");
     x.diag(site, width, diag_out);
     x.sync();
   });
 }
 
-int dmrg_renormalize(dmrg_ctx* ctx, int site, int dir, int order, int prec) {
+int dmrg_renormalize(dmrg_ctx* ctx, int site, int dir, int order, int nvec, const double* A1, size_t len,
+                     int prec) {
   return guard(ctx, [&](dmrg::Ctx& x) {
     x.require_gpu();
-    DMRG_REQUIRE(order == 0, DMRG_ERR_INVALID_ARG, "first-order sets are internal to dmrg_tda_roots");
+    DMRG_REQUIRE(order == DMRG_ZEROTH || order == DMRG_FIRST, DMRG_ERR_INVALID_ARG, "order must be 0 or 1");
+    DMRG_REQUIRE(dir == DMRG_DIR_LEFT || dir == DMRG_DIR_RIGHT, DMRG_ERR_INVALID_ARG, "bad direction");
     DMRG_REQUIRE(valid_prec(prec), DMRG_ERR_INVALID_ARG, "unsupported precision");
     DMRG_REQUIRE(x.ops_prec >= 0, DMRG_ERR_STATE, "call dmrg_build_ops first");
     DMRG_REQUIRE(site >= 0 && site < x.L, DMRG_ERR_INVALID_ARG, "bad site");
+    if (order == DMRG_FIRST) {
+      DMRG_REQUIRE(nvec >= 1 && A1, DMRG_ERR_INVALID_ARG, "first order needs nvec >= 1 tensors");
+      DMRG_REQUIRE(len == x.layout(site, 1).size * size_t(nvec), DMRG_ERR_INVALID_ARG,
+                   "len is not nvec * size of the site tensor");
+      x.renorm_first(site, dir, nvec, A1, prec);
+      return;
+    }
+    DMRG_REQUIRE(nvec == 0 && !A1, DMRG_ERR_INVALID_ARG, "zeroth order takes no tensors (nvec 0, A1 NULL)");
     if (dir == DMRG_DIR_LEFT) {
       x.renorm(DMRG_DIR_LEFT, site, x.site[site].L.as<double>(), x.site[site].L.as<double>(), 0, x.left[site],
                x.left[site + 1], false, 1, prec);

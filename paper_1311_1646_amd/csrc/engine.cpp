@@ -587,6 +587,8 @@ Ctx::Ctx(int L_, int na, int nb, const double* h, const double* eri, double ecor
 
 Ctx::~Ctx() {
   for (hipEvent_t e : main_events_) (void)hipEventDestroy(e);
+  for (auto& f : fo_chain) f.reset();
+  drop_gauge_kit();
   clear_plans();
   left.clear();
   right.clear();
@@ -678,6 +680,8 @@ void Ctx::import_mps(const int* nsec, const int* sectors, const double* Ld, cons
   DMRG_REQUIRE(B[L].q.size() == 1 && B[L].q[0] == (QN{Na, Nb}) && B[L].dim[0] == 1, DMRG_ERR_INVALID_ARG,
                "bond L must hold the target (n_alpha, n_beta)");
   clear_plans();
+  drop_gauge_kit();
+  for (auto& f : fo_chain) f.reset();
   bonds = std::move(B);
   layouts_.clear();
   op_layouts_.clear();
@@ -746,6 +750,8 @@ void Ctx::invalidate_bond(int b) {
 
 void Ctx::set_bond(int b, Bond nb, std::vector<std::vector<double>> lam_b) {
   invalidate_bond(b);
+  drop_gauge_kit();
+  for (auto& f : fo_chain) f.reset();
   bonds[b] = std::move(nb);
   lam[b] = std::move(lam_b);
   if (int(lam_dev.size()) == L + 1) upload_lambda_bond(b);
@@ -1218,6 +1224,7 @@ void Ctx::build_ops(int prec) {
   right.clear();
   left.resize(L + 1);
   right.resize(L + 1);
+  for (auto& f : fo_chain) f.reset();
   stats.renorm_flops = 0;
   // all sets and plans first (host planning, timed apart), then the
   // renormalizations back to back on the stream
@@ -1544,34 +1551,9 @@ void Ctx::sigma(int i, int width, int nvec, const double* Cin, double* Sout, int
   DMRG_REQUIRE(nvec >= 1 && Cin && Sout, DMRG_ERR_INVALID_ARG, "bad sigma arguments");
   const SiteLayout& S = layout(i, width);
   sigma_plan(i, width, left[i], right[i + width]);  // plan outside the timed region
-  hipEvent_t e0, e1;
-  DMRG_HIP(hipEventCreate(&e0));
-  DMRG_HIP(hipEventCreate(&e1));
-  main_events_used_ = 0;
-  timing_main_ = true;
-  DMRG_HIP(hipEventRecord(e0, stream));
-  try {
+  timed_sigma([&] {
     sigma_general(i, width, left[i], right[i + width], Cin, long(S.size), Sout, long(S.size), nvec, prec);
-  } catch (...) {
-    timing_main_ = false;
-    throw;
-  }
-  timing_main_ = false;
-  DMRG_HIP(hipEventRecord(e1, stream));
-  DMRG_HIP(hipEventSynchronize(e1));
-  float ms = 0;
-  DMRG_HIP(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  stats.sigma_ms = ms;
-  double main_ms = 0;
-  for (int k = 0; k + 1 < main_events_used_; k += 2) {
-    float d = 0;
-    DMRG_HIP(hipEventElapsedTime(&d, main_events_[k], main_events_[k + 1]));
-    main_ms += d;
-  }
-  stats.sigma_main_ms = main_ms;
-  stats.sigma_main_launches = main_events_used_ / 2;
+  });
 }
 
 void Ctx::autotune(int i, int nvec, int prec, int* shapes, double* best_ms) {

@@ -163,6 +163,63 @@ struct SiteTensors {
   DBuf L, R, C;  // device FP64, flat one-site layout
 };
 
+// Per-site GEMM plans of the gauge transforms and projections of first-order
+// tensors (Sec. II B, eqs. gauge_fwd, gauge_bwd, left1st, right1st; Sec. III
+// B, eq. cwfn1st): bond matrices A^T B contracted over (l, n) or over (n, r),
+// left / right multiplication of a site tensor by a bond matrix, and scaling
+// by Lambda or its inverse.  Bond matrices are block diagonal over the bond's
+// sectors (dense m_q x m_q blocks, consecutive).  Built once per MPS; every
+// call is batched over `batch` tensors with the given strides.
+class GaugeKit {
+ public:
+  explicit GaugeKit(Ctx& x);
+  std::vector<long> size;                 // elements of the one-site tensor per site
+  std::vector<std::vector<long>> bm_off;  // per bond: offset of each sector block
+  std::vector<long> bm_size;              // per bond: elements of one bond matrix
+  long max_size = 1, max_bm = 1;
+  // out[bond i+1] = sum over (a, n) of A(a,n,c)^T B(a,n,c)
+  void lt(int i, const double* A, long sa, const double* B, long sb, double* out, int batch);
+  // out[bond i] = sum over (n, c) of A(a,n,c) B(a,n,c)^T
+  void rt(int i, const double* A, long sa, const double* B, long sb, double* out, int batch);
+  // Out(a,n,c) (+|-)= M[a] A(a,n,c)
+  void lmul(int i, bool add, const double* M, long sm, const double* A, long sa, double* out, int batch);
+  // Out(a,n,c) (+|-)= A(a,n,c) M[c]
+  void rmul(int i, bool add, const double* A, long sa, const double* M, long sm, double* out, int batch);
+  // rows (by Lambda of bond i) or columns (Lambda of bond i+1), or their inverses
+  void scale(int i, bool rows, bool inverse, double* data, int batch);
+  // Q^L projection out = A - L_i (L_i^T A) and Q^R projection
+  // out = A - (A R_i^T) R_i; bm must hold batch bond matrices of bond i+1
+  // (left) or bond i (right); out may equal A
+  void q_left(int i, const double* A, double* out, double* bm, int batch);
+  void q_right(int i, const double* A, double* out, double* bm, int batch);
+
+ private:
+  Ctx& x_;
+  struct SiteOps {
+    GemmPlan lt, rt, lmul_add, lmul_sub, rmul_sub, rmul_add;
+    DBuf scale_rows, scale_cols;  // BlockScale lists
+    int nrows = 0, ncols = 0;
+  };
+  std::vector<SiteOps> sp_;
+};
+
+// First-order block operators built by dmrg_renormalize with order 1
+// (Sec. III B eq. lopr1st, Sec. III D eq. ropr1st), one chain per side: the
+// set at `bond` for nvec first-order tensors, ping-ponged between two
+// buffers as the chain grows by one site per call.
+struct FirstOrderChain {
+  OpSet set[2];
+  int cur = 0, bond = -1, nvec = 0, prec = -1;
+  const OpSet& at() const { return set[cur]; }
+  void reset() {
+    bond = -1;
+    nvec = 0;
+    prec = -1;
+    cur = 0;
+    for (auto& s : set) s = OpSet();
+  }
+};
+
 class Ctx {
  public:
   Ctx(int L, int na, int nb, const double* h, const double* eri, double ecore, int device, void* stream,
@@ -199,6 +256,7 @@ class Ctx {
 
   // workspaces
   DBuf ws_T, ws_dress, ws_blk, ws_aux, ws_c32, ws_part, ws_a32;
+  DBuf ws_fo, ws_tda;  // projected first-order tensors; partial TDA sigmas
 
   dmrg_stats stats{};
 
@@ -230,6 +288,17 @@ class Ctx {
   void sigma_general(int i, int width, const OpSet& X, const OpSet& Z, const double* C, long cstride, double* S,
                      long sstride, int batch, int prec = 0);
   void sigma(int i, int width, int nvec, const double* Cin, double* Sout, int prec = 0);
+  // dmrg_renormalize with order 1: grow the first-order chain of side dir by
+  // site i with the nvec first-order tensors A1 (device FP64, flat layout)
+  void renorm_first(int i, int dir, int nvec, const double* A1, int prec);
+  // dmrg_sigma with a TDA kind (DMRG_SIGMA_TDA_FULL / TDA_DH_LEFT) at site i
+  void sigma_tda(int i, int kind, int nvec, const double* Cin, double* Sout, int prec);
+  FirstOrderChain fo_chain[2];  // [0]: left sets, [1]: right sets
+  GaugeKit& gauge_kit();
+  void drop_gauge_kit();
+  // record device time of f() (and of the dominant launches inside it) into
+  // stats.sigma_ms / sigma_main_ms / sigma_main_launches
+  template <class F> void timed_sigma(F&& f);
   void ensure_f32(const OpSet& S);
   // FP32 operands of a set: its own data when held in FP32, else the
   // converted copy
@@ -251,6 +320,7 @@ class Ctx {
   void upload_lambda_bond(int b);
 
  private:
+  std::unique_ptr<GaugeKit> kit_;
   std::map<std::pair<int, int>, std::unique_ptr<SiteLayout>> layouts_;
   std::map<std::tuple<int, int, int>, std::unique_ptr<OpLayout>> op_layouts_;
   std::map<std::tuple<int, int, int, int>, std::unique_ptr<ContractionPlan>> renorm_plans_;
@@ -260,5 +330,43 @@ class Ctx {
   ContractionPlan& sigma_plan(int i, int width, const OpSet& X, const OpSet& Z, bool left_first = false);
   void clear_plans();
 };
+
+}  // namespace dmrg
+
+namespace dmrg {
+
+template <class F>
+void Ctx::timed_sigma(F&& f) {
+  hipEvent_t e0, e1;
+  DMRG_HIP(hipEventCreate(&e0));
+  DMRG_HIP(hipEventCreate(&e1));
+  main_events_used_ = 0;
+  timing_main_ = true;
+  DMRG_HIP(hipEventRecord(e0, stream));
+  try {
+    f();
+  } catch (...) {
+    timing_main_ = false;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    throw;
+  }
+  timing_main_ = false;
+  DMRG_HIP(hipEventRecord(e1, stream));
+  DMRG_HIP(hipEventSynchronize(e1));
+  float ms = 0;
+  DMRG_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  stats.sigma_ms = ms;
+  double main_ms = 0;
+  for (int k = 0; k + 1 < main_events_used_; k += 2) {
+    float d = 0;
+    DMRG_HIP(hipEventElapsedTime(&d, main_events_[k], main_events_[k + 1]));
+    main_ms += d;
+  }
+  stats.sigma_main_ms = main_ms;
+  stats.sigma_main_launches = main_events_used_ / 2;
+}
 
 }  // namespace dmrg

@@ -115,6 +115,10 @@ __global__ void fill_f64_kernel(double* p, long n, double v) {
   for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += long(gridDim.x) * blockDim.x) p[e] = v;
 }
 
+__global__ void add_f64_kernel(const double* __restrict__ x, double* __restrict__ y, long n) {
+  for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += long(gridDim.x) * blockDim.x) y[e] += x[e];
+}
+
 __global__ void zero_f32_kernel(float* p, long n) {
   for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += long(gridDim.x) * blockDim.x) p[e] = 0.0f;
 }
@@ -517,6 +521,13 @@ void launch_fill_f64(double* p, long n, double v, hipStream_t s) {
   long blocks = (n + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(fill_f64_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, p, n, v);
+}
+
+void launch_add_f64(const double* x, double* y, long n, hipStream_t s) {
+  if (n <= 0) return;
+  long blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(add_f64_kernel, dim3(unsigned(blocks)), dim3(256), 0, s, x, y, n);
 }
 
 void launch_fill_f32(float* p, long n, hipStream_t s) {

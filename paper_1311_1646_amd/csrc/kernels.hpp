@@ -106,6 +106,7 @@ void launch_diag_add_f64(const DiagAdd* d, int n, const Bases& b, int batch, hip
 
 void launch_fill_f64(double* p, long n, double v, hipStream_t s);
 void launch_fill_f32(float* p, long n, hipStream_t s);  // p[0..n) = 0
+void launch_add_f64(const double* x, double* y, long n, hipStream_t s);  // y[0..n) += x[0..n)
 
 // Diagonal of sum_t alpha_t X_t (x) |n><n| (x) Z_t on one output block:
 // out[l, r] = sum_t alpha_t X_t[l, l] Z_t[r, r]; one workgroup per job.

@@ -52,128 +52,28 @@ struct HostRng {
 
 }  // namespace
 
-class TdaRunner {
- public:
-  TdaRunner(Ctx& x, int nroots, const dmrg_davidson_params& p) : x_(x), n_(nroots), p_(p), prec_(p.prec) {
-    L_ = x.L;
-    Nmax_ = p.max_space > 0 ? p.max_space : std::min(64, std::max(3 * n_, n_ + 16));
-    DMRG_REQUIRE(Nmax_ <= 64, DMRG_ERR_INVALID_ARG, "max_space must be <= 64");
-    DMRG_REQUIRE(n_ >= 1 && 2 * n_ <= Nmax_, DMRG_ERR_INVALID_ARG, "need 1 <= nroots and 2*nroots <= max_space");
-    size_.resize(L_);
-    maxsize_ = 1;
-    for (int i = 0; i < L_; ++i) {
-      size_[i] = long(x.layout(i, 1).size);
-      maxsize_ = std::max(maxsize_, size_[i]);
-    }
-    bm_off_.resize(L_ + 1);
-    bm_size_.assign(L_ + 1, 0);
-    long maxbm = 1;
-    for (int b = 0; b <= L_; ++b) {
-      bm_off_[b].resize(x.bonds[b].q.size());
-      long o = 0;
-      for (size_t s = 0; s < x.bonds[b].q.size(); ++s) {
-        bm_off_[b][s] = o;
-        o += long(x.bonds[b].dim[s]) * x.bonds[b].dim[s];
-      }
-      bm_size_[b] = o;
-      maxbm = std::max(maxbm, o);
-    }
-    // per-site storage
-    R1_.resize(L_);
-    G_.resize(L_);
-    Ct_.resize(L_);
-    diag_.resize(L_);
-    for (int i = 0; i < L_; ++i) {
-      R1_[i].alloc(&x, size_t(Nmax_) * size_[i] * 8);
-      G_[i].alloc(&x, size_t(Nmax_) * size_[i] * 8);
-      Ct_[i].alloc(&x, size_t(Nmax_) * size_[i] * 8);
-      diag_[i].alloc(&x, size_t(size_[i]) * 8);
-    }
-    const size_t vs = size_t(Nmax_) * maxsize_ * 8;
-    for (DBuf* b : {&Cm_, &Cprev_, &Cb_, &Sg_, &S0_, &Dl_, &Wk_, &R1r_, &Gr_}) b->alloc(&x, vs);
-    bm_.alloc(&x, size_t(Nmax_) * maxbm * 8);
-    HR_.alloc(&x, 64 * 64 * 8);
-    SR_.alloc(&x, 64 * 64 * 8);
-    alpha_.alloc(&x, 64 * 64 * 8);
-    w_.alloc(&x, 64 * 8);
-    rank_.alloc(&x, 8);
-    negw_.alloc(&x, 64 * 8);
-    ones_.alloc(&x, 64 * 8);
-    zscale_.alloc(&x, 64 * 8);
-    tmpd_.alloc(&x, 64 * 64 * 8);
-    part_.alloc(&x, size_t(gram_parts(maxsize_) + 1) * 64 * 64 * 8);
-    std::vector<double> one(64, 1.0);
-    DMRG_HIP(hipMemcpy(ones_.p, one.data(), 64 * 8, hipMemcpyHostToDevice));
-    for (int k = 0; k < 2; ++k) {
-      FL_[k].bond = -1;
-      FR_[k].bond = -1;
-    }
-    build_site_plans();
+GaugeKit::GaugeKit(Ctx& x) : x_(x) {
+  const int L = x.L;
+  size.resize(L);
+  for (int i = 0; i < L; ++i) {
+    size[i] = long(x.layout(i, 1).size);
+    max_size = std::max(max_size, size[i]);
   }
-
-  void run(double* omega, double* etot, double* resid2, int* iters, bool* converged);
-
- private:
-  Ctx& x_;
-  int n_, L_, Nmax_;
-  dmrg_davidson_params p_;
-  int prec_;  // contraction precision of sigma and renormalization
-  std::vector<long> size_;
-  long maxsize_;
-  std::vector<std::vector<long>> bm_off_;
-  std::vector<long> bm_size_;
-  std::vector<DBuf> R1_, G_, Ct_, diag_;
-  DBuf Cm_, Cprev_, Cb_, Sg_, S0_, Dl_, Wk_, R1r_, Gr_, bm_;
-  DBuf HR_, SR_, alpha_, w_, rank_, negw_, ones_, tmpd_, part_, zscale_;
-  OpSet FL_[2], FR_[2];
-  double E0_ = 0;
-  std::vector<double> hw_;  // host copy of Ritz values
-
-  // site-level GEMM plans
-  struct SiteOps {
-    GemmPlan lt, rt, lmul_add, lmul_sub, rmul_sub, rmul_add;
-    DBuf scale_rows, scale_cols;  // BlockScale lists
-    int nrows = 0, ncols = 0;
-  };
-  std::vector<SiteOps> sp_;
-
-  void build_site_plans();
-  // bond matrices: out[bond] = A^T B contracted over (l, n) (lt) or over (n, r) (rt)
-  void lt(int i, const double* A, long sa, const double* B, long sb, double* out, int batch);
-  void rt(int i, const double* A, long sa, const double* B, long sb, double* out, int batch);
-  // Out(a,n,c) += M[a] A(a,n,c)  /  -= M[a] A(a,n,c)
-  void lmul_add(int i, const double* M, long sm, const double* A, long sa, double* out, int batch);
-  void lmul_sub(int i, const double* M, long sm, const double* A, long sa, double* out, int batch);
-  // Out(a,n,c) -= A(a,n,c) M[c]  /  += A(a,n,c) M[c]
-  void rmul(int i, bool add, const double* A, long sa, const double* M, long sm, double* out, int batch);
-  void scale(int i, bool rows, bool inverse, double* data, int batch);
-  void copy(double* dst, const double* src, long n) {
-    if (n > 0) DMRG_HIP(hipMemcpyAsync(dst, src, size_t(n) * 8, hipMemcpyDeviceToDevice, x_.stream));
+  bm_off.resize(L + 1);
+  bm_size.assign(L + 1, 0);
+  for (int b = 0; b <= L; ++b) {
+    bm_off[b].resize(x.bonds[b].q.size());
+    long o = 0;
+    for (size_t s = 0; s < x.bonds[b].q.size(); ++s) {
+      bm_off[b][s] = o;
+      o += long(x.bonds[b].dim[s]) * x.bonds[b].dim[s];
+    }
+    bm_size[b] = o;
+    max_bm = std::max(max_bm, o);
   }
-  void gram(const double* A, long lda, int na, const double* B, long ldb, int nb, long n, double* G, int ldg,
-            double alpha, bool acc) {
-    launch_gram_f64(A, lda, na, B, ldb, nb, n, G, ldg, part_.as<double>(), alpha, acc, x_.stream);
-    DMRG_HIP(hipGetLastError());
-  }
-  void q_c_project(int i, double* z, int nv);  // z -= C0 (C0 . z)
-  void q_l_project(int i, const double* C, double* out, int nv);  // out = C - L (L^T C)
-  void forward(int m, int lprev, bool init, uint64_t seed, std::vector<double>& r2);
-  // size both buffers of a ping-pong pair of first-order sets (side 0 left,
-  // 1 right) for the largest bond, so that a sweep allocates once
-  void reserve(OpSet* sets, int side, int nvec) {
-    long mx = 1;
-    for (int b = 0; b <= L_; ++b) mx = std::max(mx, x_.opset_size(b, side));
-    const size_t bytes = size_t(mx) * size_t(nvec) * (prec_ != DMRG_FP64 ? 4 : 8);
-    for (int k = 0; k < 2; ++k)
-      if (sets[k].data.bytes < bytes) sets[k].data.alloc(&x_, bytes);
-  }
-  void backward(int l);
-};
-
-void TdaRunner::build_site_plans() {
-  sp_.resize(L_);
-  for (int i = 0; i < L_; ++i) {
-    const SiteLayout& S = x_.layout(i, 1);
+  sp_.resize(L);
+  for (int i = 0; i < L; ++i) {
+    const SiteLayout& S = x.layout(i, 1);
     SiteOps& so = sp_[i];
     // lt: out[c] (bond i+1) = sum_{(a,n)->c} A(a,n,c)^T B(a,n,c)
     {
@@ -184,7 +84,7 @@ void TdaRunner::build_site_plans() {
         auto it = jo.find(b.c);
         if (it == jo.end()) {
           GJob j{};
-          j.offC = bm_off_[i + 1][b.c];
+          j.offC = bm_off[i + 1][b.c];
           j.baseC = B_SOUT;
           j.ldc = b.cols;
           j.m = b.cols;
@@ -195,7 +95,7 @@ void TdaRunner::build_site_plans() {
         }
         per[it->second].push_back({long(b.off), long(b.off), b.cols, b.cols, b.rows, GC_TRANS_A, B_ABRA, B_AKET, 1.0});
       }
-      build_gemm_plan(x_, so.lt, jobs, per);
+      build_gemm_plan(x, so.lt, jobs, per);
     }
     // rt: out[a] (bond i) = sum_{(n,c)} A(a,n,c) B(a,n,c)^T
     {
@@ -206,7 +106,7 @@ void TdaRunner::build_site_plans() {
         auto it = jo.find(b.a);
         if (it == jo.end()) {
           GJob j{};
-          j.offC = bm_off_[i][b.a];
+          j.offC = bm_off[i][b.a];
           j.baseC = B_SOUT;
           j.ldc = b.rows;
           j.m = b.rows;
@@ -217,7 +117,7 @@ void TdaRunner::build_site_plans() {
         }
         per[it->second].push_back({long(b.off), long(b.off), b.cols, b.cols, b.cols, GC_TRANS_B, B_ABRA, B_AKET, 1.0});
       }
-      build_gemm_plan(x_, so.rt, jobs, per);
+      build_gemm_plan(x, so.rt, jobs, per);
     }
     // lmul: Out(a,n,c) +-= M[a] A(a,n,c)
     for (int add = 0; add < 2; ++add) {
@@ -232,9 +132,9 @@ void TdaRunner::build_site_plans() {
         j.n = b.cols;
         j.flags = GJ_ACCUMULATE;
         jobs.push_back(j);
-        per.push_back({{bm_off_[i][b.a], long(b.off), b.rows, b.cols, b.rows, 0, B_AUX, B_AKET, add ? 1.0 : -1.0}});
+        per.push_back({{bm_off[i][b.a], long(b.off), b.rows, b.cols, b.rows, 0, B_AUX, B_AKET, add ? 1.0 : -1.0}});
       }
-      build_gemm_plan(x_, add ? so.lmul_add : so.lmul_sub, jobs, per);
+      build_gemm_plan(x, add ? so.lmul_add : so.lmul_sub, jobs, per);
     }
     // rmul: Out(a,n,c) +-= A(a,n,c) M[c]
     for (int add = 0; add < 2; ++add) {
@@ -249,103 +149,184 @@ void TdaRunner::build_site_plans() {
         j.n = b.cols;
         j.flags = GJ_ACCUMULATE;
         jobs.push_back(j);
-        per.push_back({{long(b.off), bm_off_[i + 1][b.c], b.cols, b.cols, b.cols, 0, B_AKET, B_AUX,
+        per.push_back({{long(b.off), bm_off[i + 1][b.c], b.cols, b.cols, b.cols, 0, B_AKET, B_AUX,
                         add ? 1.0 : -1.0}});
       }
-      build_gemm_plan(x_, add ? so.rmul_add : so.rmul_sub, jobs, per);
+      build_gemm_plan(x, add ? so.rmul_add : so.rmul_sub, jobs, per);
     }
     std::vector<BlockScale> rows, cols;
     for (auto& b : S.blk) {
-      rows.push_back({long(b.off), x_.bond_offset(i, b.a), b.rows, b.cols, 1, 0});
-      cols.push_back({long(b.off), x_.bond_offset(i + 1, b.c), b.rows, b.cols, 0, 0});
+      rows.push_back({long(b.off), x.bond_offset(i, b.a), b.rows, b.cols, 1, 0});
+      cols.push_back({long(b.off), x.bond_offset(i + 1, b.c), b.rows, b.cols, 0, 0});
     }
-    upload_vec(x_, so.scale_rows, rows);
-    upload_vec(x_, so.scale_cols, cols);
+    upload_vec(x, so.scale_rows, rows);
+    upload_vec(x, so.scale_cols, cols);
     so.nrows = int(rows.size());
     so.ncols = int(cols.size());
   }
 }
 
-}  // namespace dmrg
-
-namespace dmrg {
-
-void TdaRunner::lt(int i, const double* A, long sa, const double* B, long sb, double* out, int batch) {
+void GaugeKit::lt(int i, const double* A, long sa, const double* B, long sb, double* out, int batch) {
   Bases b{};
   b.p[B_ABRA] = const_cast<double*>(A);
   b.stride[B_ABRA] = sa;
   b.p[B_AKET] = const_cast<double*>(B);
   b.stride[B_AKET] = sb;
   b.p[B_SOUT] = out;
-  b.stride[B_SOUT] = bm_size_[i + 1];
+  b.stride[B_SOUT] = bm_size[i + 1];
   sp_[i].lt.launch(x_, b, batch);
 }
 
-void TdaRunner::rt(int i, const double* A, long sa, const double* B, long sb, double* out, int batch) {
+void GaugeKit::rt(int i, const double* A, long sa, const double* B, long sb, double* out, int batch) {
   Bases b{};
   b.p[B_ABRA] = const_cast<double*>(A);
   b.stride[B_ABRA] = sa;
   b.p[B_AKET] = const_cast<double*>(B);
   b.stride[B_AKET] = sb;
   b.p[B_SOUT] = out;
-  b.stride[B_SOUT] = bm_size_[i];
+  b.stride[B_SOUT] = bm_size[i];
   sp_[i].rt.launch(x_, b, batch);
 }
 
-void TdaRunner::lmul_add(int i, const double* M, long sm, const double* A, long sa, double* out, int batch) {
+void GaugeKit::lmul(int i, bool add, const double* M, long sm, const double* A, long sa, double* out, int batch) {
   Bases b{};
   b.p[B_AUX] = const_cast<double*>(M);
   b.stride[B_AUX] = sm;
   b.p[B_AKET] = const_cast<double*>(A);
   b.stride[B_AKET] = sa;
   b.p[B_SOUT] = out;
-  b.stride[B_SOUT] = size_[i];
-  sp_[i].lmul_add.launch(x_, b, batch);
+  b.stride[B_SOUT] = size[i];
+  (add ? sp_[i].lmul_add : sp_[i].lmul_sub).launch(x_, b, batch);
 }
 
-void TdaRunner::lmul_sub(int i, const double* M, long sm, const double* A, long sa, double* out, int batch) {
+void GaugeKit::rmul(int i, bool add, const double* A, long sa, const double* M, long sm, double* out, int batch) {
   Bases b{};
   b.p[B_AUX] = const_cast<double*>(M);
   b.stride[B_AUX] = sm;
   b.p[B_AKET] = const_cast<double*>(A);
   b.stride[B_AKET] = sa;
   b.p[B_SOUT] = out;
-  b.stride[B_SOUT] = size_[i];
-  sp_[i].lmul_sub.launch(x_, b, batch);
-}
-
-void TdaRunner::rmul(int i, bool add, const double* A, long sa, const double* M, long sm, double* out, int batch) {
-  Bases b{};
-  b.p[B_AUX] = const_cast<double*>(M);
-  b.stride[B_AUX] = sm;
-  b.p[B_AKET] = const_cast<double*>(A);
-  b.stride[B_AKET] = sa;
-  b.p[B_SOUT] = out;
-  b.stride[B_SOUT] = size_[i];
+  b.stride[B_SOUT] = size[i];
   (add ? sp_[i].rmul_add : sp_[i].rmul_sub).launch(x_, b, batch);
 }
 
-void TdaRunner::scale(int i, bool rows, bool inverse, double* data, int batch) {
+void GaugeKit::scale(int i, bool rows, bool inverse, double* data, int batch) {
   const int bond = rows ? i : i + 1;
   const DBuf& v = inverse ? x_.laminv_dev[bond] : x_.lam_dev[bond];
   const SiteOps& so = sp_[i];
   launch_block_scale_f64(rows ? so.scale_rows.as<BlockScale>() : so.scale_cols.as<BlockScale>(),
-                         rows ? so.nrows : so.ncols, v.as<double>(), data, size_[i], batch, x_.stream);
+                         rows ? so.nrows : so.ncols, v.as<double>(), data, size[i], batch, x_.stream);
   DMRG_HIP(hipGetLastError());
 }
+
+void GaugeKit::q_left(int i, const double* A, double* out, double* bm, int batch) {
+  const double* Li = x_.site[i].L.as<double>();
+  lt(i, Li, 0, A, size[i], bm, batch);
+  if (out != A && batch > 0)
+    DMRG_HIP(hipMemcpyAsync(out, A, size_t(batch) * size[i] * 8, hipMemcpyDeviceToDevice, x_.stream));
+  rmul(i, false, Li, 0, bm, bm_size[i + 1], out, batch);
+}
+
+void GaugeKit::q_right(int i, const double* A, double* out, double* bm, int batch) {
+  const double* Ri = x_.site[i].R.as<double>();
+  rt(i, A, size[i], Ri, 0, bm, batch);
+  if (out != A && batch > 0)
+    DMRG_HIP(hipMemcpyAsync(out, A, size_t(batch) * size[i] * 8, hipMemcpyDeviceToDevice, x_.stream));
+  lmul(i, false, bm, bm_size[i], Ri, 0, out, batch);
+}
+
+GaugeKit& Ctx::gauge_kit() {
+  require_gpu();
+  DMRG_REQUIRE(have_mps, DMRG_ERR_STATE, "no MPS");
+  if (!kit_) kit_.reset(new GaugeKit(*this));
+  return *kit_;
+}
+
+void Ctx::drop_gauge_kit() { kit_.reset(); }
+
+class TdaRunner {
+ public:
+  TdaRunner(Ctx& x, int nroots, const dmrg_davidson_params& p) : x_(x), k_(x.gauge_kit()), n_(nroots), p_(p), prec_(p.prec) {
+    L_ = x.L;
+    Nmax_ = p.max_space > 0 ? p.max_space : std::min(64, std::max(3 * n_, n_ + 16));
+    DMRG_REQUIRE(Nmax_ <= 64, DMRG_ERR_INVALID_ARG, "max_space must be <= 64");
+    DMRG_REQUIRE(n_ >= 1 && 2 * n_ <= Nmax_, DMRG_ERR_INVALID_ARG, "need 1 <= nroots and 2*nroots <= max_space");
+    const long maxsize = k_.max_size;
+    // per-site storage
+    R1_.resize(L_);
+    G_.resize(L_);
+    Ct_.resize(L_);
+    diag_.resize(L_);
+    for (int i = 0; i < L_; ++i) {
+      R1_[i].alloc(&x, size_t(Nmax_) * k_.size[i] * 8);
+      G_[i].alloc(&x, size_t(Nmax_) * k_.size[i] * 8);
+      Ct_[i].alloc(&x, size_t(Nmax_) * k_.size[i] * 8);
+      diag_[i].alloc(&x, size_t(k_.size[i]) * 8);
+    }
+    const size_t vs = size_t(Nmax_) * maxsize * 8;
+    for (DBuf* b : {&Cm_, &Cprev_, &Cb_, &Sg_, &S0_, &Dl_, &Wk_, &R1r_, &Gr_}) b->alloc(&x, vs);
+    bm_.alloc(&x, size_t(Nmax_) * k_.max_bm * 8);
+    HR_.alloc(&x, 64 * 64 * 8);
+    SR_.alloc(&x, 64 * 64 * 8);
+    alpha_.alloc(&x, 64 * 64 * 8);
+    w_.alloc(&x, 64 * 8);
+    rank_.alloc(&x, 8);
+    negw_.alloc(&x, 64 * 8);
+    ones_.alloc(&x, 64 * 8);
+    zscale_.alloc(&x, 64 * 8);
+    tmpd_.alloc(&x, 64 * 64 * 8);
+    part_.alloc(&x, size_t(gram_parts(maxsize) + 1) * 64 * 64 * 8);
+    std::vector<double> one(64, 1.0);
+    DMRG_HIP(hipMemcpy(ones_.p, one.data(), 64 * 8, hipMemcpyHostToDevice));
+    for (int k = 0; k < 2; ++k) {
+      FL_[k].bond = -1;
+      FR_[k].bond = -1;
+    }
+  }
+
+  void run(double* omega, double* etot, double* resid2, int* iters, bool* converged);
+
+ private:
+  Ctx& x_;
+  GaugeKit& k_;
+  int n_, L_, Nmax_;
+  dmrg_davidson_params p_;
+  int prec_;  // contraction precision of sigma and renormalization
+  std::vector<DBuf> R1_, G_, Ct_, diag_;
+  DBuf Cm_, Cprev_, Cb_, Sg_, S0_, Dl_, Wk_, R1r_, Gr_, bm_;
+  DBuf HR_, SR_, alpha_, w_, rank_, negw_, ones_, tmpd_, part_, zscale_;
+  OpSet FL_[2], FR_[2];
+  double E0_ = 0;
+  std::vector<double> hw_;  // host copy of Ritz values
+
+  long size(int i) const { return k_.size[i]; }
+  void copy(double* dst, const double* src, long n) {
+    if (n > 0) DMRG_HIP(hipMemcpyAsync(dst, src, size_t(n) * 8, hipMemcpyDeviceToDevice, x_.stream));
+  }
+  void gram(const double* A, long lda, int na, const double* B, long ldb, int nb, long n, double* G, int ldg,
+            double alpha, bool acc) {
+    launch_gram_f64(A, lda, na, B, ldb, nb, n, G, ldg, part_.as<double>(), alpha, acc, x_.stream);
+    DMRG_HIP(hipGetLastError());
+  }
+  void q_c_project(int i, double* z, int nv);  // z -= C0 (C0 . z)
+  void forward(int m, int lprev, bool init, uint64_t seed, std::vector<double>& r2);
+  // size both buffers of a ping-pong pair of first-order sets (side 0 left,
+  // 1 right) for the largest bond, so that a sweep allocates once
+  void reserve(OpSet* sets, int side, int nvec) {
+    long mx = 1;
+    for (int b = 0; b <= L_; ++b) mx = std::max(mx, x_.opset_size(b, side));
+    const size_t bytes = size_t(mx) * size_t(nvec) * (prec_ != DMRG_FP64 ? 4 : 8);
+    for (int k = 0; k < 2; ++k)
+      if (sets[k].data.bytes < bytes) sets[k].data.alloc(&x_, bytes);
+  }
+  void backward(int l);
+};
 
 void TdaRunner::q_c_project(int i, double* z, int nv) {
   const double* C0 = x_.site[i].C.as<double>();
-  gram(z, size_[i], nv, C0, size_[i], 1, size_[i], tmpd_.as<double>(), 1, -1.0, false);
-  launch_axpby_f64(tmpd_.as<double>(), C0, 0, ones_.as<double>(), z, size_[i], nv, size_[i], x_.stream);
+  gram(z, size(i), nv, C0, size(i), 1, size(i), tmpd_.as<double>(), 1, -1.0, false);
+  launch_axpby_f64(tmpd_.as<double>(), C0, 0, ones_.as<double>(), z, size(i), nv, size(i), x_.stream);
   DMRG_HIP(hipGetLastError());
-}
-
-void TdaRunner::q_l_project(int i, const double* C, double* out, int nv) {
-  const double* Li = x_.site[i].L.as<double>();
-  lt(i, Li, 0, C, size_[i], bm_.as<double>(), nv);
-  if (out != C) copy(out, C, long(nv) * size_[i]);
-  rmul(i, false, Li, 0, bm_.as<double>(), bm_size_[i + 1], out, nv);
 }
 
 void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<double>& r2) {
@@ -360,7 +341,7 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
   std::vector<double> tmp;
   for (int i = 0; i < L_; ++i) {
     if (p_.verbose >= 2) std::fprintf(stderr, "[tda] forward site %d (l=%d)\n", i, m + n_);
-    const long S = size_[i];
+    const long S = size(i);
     double* Cm = Cm_.as<double>();
     const double* C0 = x_.site[i].C.as<double>();
     // Ritz rotation of the right-gauge objects and gauge shift (eq. gauge_fwd)
@@ -371,10 +352,10 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
                         x_.stream);
       DMRG_HIP(hipGetLastError());
       copy(Cm, R1r_.as<double>(), long(m) * S);
-      scale(i, true, false, Cm, m);
+      k_.scale(i, true, false, Cm, m);
       if (i > 0) {
-        lt(i - 1, x_.site[i - 1].L.as<double>(), 0, Cprev_.as<double>(), size_[i - 1], bm_.as<double>(), m);
-        lmul_add(i, bm_.as<double>(), bm_size_[i], x_.site[i].R.as<double>(), 0, Cm, m);
+        k_.lt(i - 1, x_.site[i - 1].L.as<double>(), 0, Cprev_.as<double>(), size(i - 1), bm_.as<double>(), m);
+        k_.lmul(i, true, bm_.as<double>(), k_.bm_size[i], x_.site[i].R.as<double>(), 0, Cm, m);
       }
     }
     // first-order left part of the sigma for all l vectors (eq. sigv2, first line)
@@ -433,7 +414,7 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
     copy(Cm + long(m) * S, Wk, long(n_) * S);
     // projected coefficients (eq. cwfn1st)
     double* Ct = Ct_[i].as<double>();
-    q_l_project(i, Cm, Ct, l);
+    k_.q_left(i, Cm, Ct, bm_.as<double>(), l);
     // reduced matrices (eqs. hleft2, sleft2)
     double* S0 = S0_.as<double>();
     x_.sigma_general(i, 1, x_.left[i], x_.right[i + 1], Ct, S, S0, S, l, prec_);
@@ -444,7 +425,7 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
     if (i == L_ - 1) break;
     // L^(1) (eq. left1st) and the first-order left operators (eq. lopr1st)
     copy(Wk, Ct, long(l) * S);
-    scale(i, false, true, Wk, l);
+    k_.scale(i, false, true, Wk, l);
     const int nxt = 1 - cur;
     x_.alloc_opset(FL_[nxt], i + 1, 0, l, true, true, prec_ != DMRG_FP64);
     const double* Li = x_.site[i].L.as<double>();
@@ -464,17 +445,15 @@ void TdaRunner::backward(int l) {
   reserve(FR_, 1, l);
   x_.alloc_opset(FR_[cur], L_, 1, l, true, true, prec_ != DMRG_FP64);
   double* Cb = Cb_.as<double>();
-  copy(Cb, Ct_[L_ - 1].as<double>(), long(l) * size_[L_ - 1]);
+  copy(Cb, Ct_[L_ - 1].as<double>(), long(l) * size(L_ - 1));
   for (int i = L_ - 1; i >= 0; --i) {
     if (p_.verbose >= 2) std::fprintf(stderr, "[tda] backward site %d (l=%d)\n", i, l);
-    const long S = size_[i];
+    const long S = size(i);
     const double* Ri = x_.site[i].R.as<double>();
     // R^(1) (eq. right1st): Lambda^-1 C (1 - R^T R)
-    rt(i, Cb, S, Ri, 0, bm_.as<double>(), l);
     double* R1 = R1_[i].as<double>();
-    copy(R1, Cb, long(l) * S);
-    lmul_sub(i, bm_.as<double>(), bm_size_[i], Ri, 0, R1, l);
-    scale(i, true, true, R1, l);
+    k_.q_right(i, Cb, R1, bm_.as<double>(), l);
+    k_.scale(i, true, true, R1, l);
     // first-order right part of the sigma contracted with C^(0)
     x_.sigma_general(i, 1, x_.left[i], FR_[cur], x_.site[i].C.as<double>(), 0, G_[i].as<double>(), S, l, prec_);
     if (i == 0) break;
@@ -485,9 +464,9 @@ void TdaRunner::backward(int l) {
     x_.renorm(DMRG_DIR_RIGHT, i, Ri, R1, S, x_.right[i + 1], FR_[nxt], true, l, prec_);
     // gauge shift to site i-1 (eq. gauge_bwd): C_{i-1} = C~_{i-1} + L_{i-1} (C_i R_i^T)
     double* Wk = Wk_.as<double>();
-    copy(Wk, Ct_[i - 1].as<double>(), long(l) * size_[i - 1]);
-    rmul(i - 1, true, x_.site[i - 1].L.as<double>(), 0, bm_.as<double>(), bm_size_[i], Wk, l);
-    copy(Cb, Wk, long(l) * size_[i - 1]);
+    copy(Wk, Ct_[i - 1].as<double>(), long(l) * size(i - 1));
+    k_.rmul(i - 1, true, x_.site[i - 1].L.as<double>(), 0, bm_.as<double>(), k_.bm_size[i], Wk, l);
+    copy(Cb, Wk, long(l) * size(i - 1));
     x_.sync();
     cur = nxt;
   }
@@ -504,8 +483,8 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
   // reference energy E0 = <Psi0|H|Psi0> at site 0
   {
     const double* C0 = x_.site[0].C.as<double>();
-    x_.sigma_general(0, 1, x_.left[0], x_.right[1], C0, 0, Wk_.as<double>(), size_[0], 1, DMRG_FP64);
-    gram(C0, size_[0], 1, Wk_.as<double>(), size_[0], 1, size_[0], tmpd_.as<double>(), 1, 1.0, false);
+    x_.sigma_general(0, 1, x_.left[0], x_.right[1], C0, 0, Wk_.as<double>(), size(0), 1, DMRG_FP64);
+    gram(C0, size(0), 1, Wk_.as<double>(), size(0), 1, size(0), tmpd_.as<double>(), 1, 1.0, false);
     DMRG_HIP(hipMemcpy(&E0_, tmpd_.p, 8, hipMemcpyDeviceToHost));
   }
   for (int i = 0; i < L_; ++i) x_.diag(i, 1, diag_[i].as<double>());
@@ -568,6 +547,137 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
   }
   *iters = std::min(it, p_.max_iter);
   *converged = conv;
+}
+
+// First-order block operators through the C-ABI (Sec. III B eq. lopr1st,
+// Sec. III D eq. ropr1st).  The input tensors are first projected on the
+// complement of the zeroth-order tensor (Q^L for left, Q^R for right), which
+// is the gauge condition of the first-order tensors (Sec. II B); the
+// first-order sets have no identity channel because of it.
+void Ctx::renorm_first(int i, int dir, int nvec, const double* A1, int prec) {
+  require_gpu();
+  DMRG_REQUIRE(ops_prec >= 0, DMRG_ERR_STATE, "call dmrg_build_ops first");
+  DMRG_REQUIRE(i >= 0 && i < L, DMRG_ERR_INVALID_ARG, "bad site");
+  DMRG_REQUIRE(dir == DMRG_DIR_LEFT || dir == DMRG_DIR_RIGHT, DMRG_ERR_INVALID_ARG, "bad direction");
+  DMRG_REQUIRE(nvec >= 1 && A1, DMRG_ERR_INVALID_ARG, "first-order renormalization needs nvec >= 1 tensors");
+  const bool left_dir = dir == DMRG_DIR_LEFT;
+  FirstOrderChain& F = fo_chain[left_dir ? 0 : 1];
+  const int side = left_dir ? 0 : 1;
+  const bool f32 = prec != DMRG_FP64;
+  const bool start = left_dir ? i == 0 : i == L - 1;
+  if (start) {
+    // the chain starts at the empty block: bond 0 (left) or bond L (right)
+    F.cur = 0;
+    F.nvec = nvec;
+    F.prec = prec;
+    F.bond = left_dir ? 0 : L;
+    alloc_opset(F.set[0], F.bond, side, nvec, true, true, f32);
+    if (F.set[0].per_vec > 0) {
+      if (f32) launch_fill_f32(F.set[0].data.as<float>(), F.set[0].per_vec * nvec, stream);
+      else launch_fill_f64(F.set[0].ptr(), F.set[0].per_vec * nvec, 0.0, stream);
+    }
+  } else {
+    const int want = left_dir ? i : i + 1;
+    DMRG_REQUIRE(F.bond == want, DMRG_ERR_STATE,
+                 "the first-order " + std::string(left_dir ? "left" : "right") + " chain is at bond " +
+                     std::to_string(F.bond) + ", not at bond " + std::to_string(want) +
+                     " (grow it one site at a time from the chain's start site)");
+    DMRG_REQUIRE(F.nvec == nvec, DMRG_ERR_INVALID_ARG, "nvec differs from the chain's");
+    DMRG_REQUIRE((F.prec != DMRG_FP64) == f32, DMRG_ERR_INVALID_ARG,
+                 "precision class (FP64 or FP32 sets) differs from the chain's");
+  }
+  GaugeKit& K = gauge_kit();
+  const long S = K.size[i];
+  ws_fo.ensure(this, (size_t(nvec) * S + size_t(nvec) * K.max_bm) * 8);
+  double* X = ws_fo.as<double>();
+  double* bm = X + size_t(nvec) * S;
+  if (left_dir) K.q_left(i, A1, X, bm, nvec);
+  else K.q_right(i, A1, X, bm, nvec);
+  const int nxt = 1 - F.cur;
+  const int nb = left_dir ? i + 1 : i;
+  alloc_opset(F.set[nxt], nb, side, nvec, true, true, f32);
+  if (left_dir) {
+    const double* Li = site[i].L.as<double>();
+    renorm(DMRG_DIR_LEFT, i, Li, Li, 0, F.set[F.cur], F.set[nxt], false, nvec, prec);
+    renorm(DMRG_DIR_LEFT, i, Li, X, S, left[i], F.set[nxt], true, nvec, prec);
+  } else {
+    const double* Ri = site[i].R.as<double>();
+    renorm(DMRG_DIR_RIGHT, i, Ri, Ri, 0, F.set[F.cur], F.set[nxt], false, nvec, prec);
+    renorm(DMRG_DIR_RIGHT, i, Ri, X, S, right[i + 1], F.set[nxt], true, nvec, prec);
+  }
+  F.cur = nxt;
+  F.bond = nb;
+  sync();
+}
+
+// TDA sigma at site i (Sec. III D): TDA_FULL is eq. sigv1,
+//   sigma^mu = H_0^[i] C^mu(1) + [H_mu^L x h_i x H_0^R] C_i^(0)
+//                              + [H_0^L x h_i x H_mu^R] C_i^(0)   (eq. sigv2),
+// with the first-order sets of the two chains (a part is zero at the chain's
+// start: site 0 for the left part, site L-1 for the right part);
+// TDA_DH_LEFT is the first line of eq. sigv2 applied to the given vectors,
+//   sigma^mu = [H_mu^L x h_i x H_0^R] C^mu.
+void Ctx::sigma_tda(int i, int kind, int nvec, const double* Cin, double* Sout, int prec) {
+  require_gpu();
+  DMRG_REQUIRE(ops_prec >= 0, DMRG_ERR_STATE, "call dmrg_build_ops first");
+  DMRG_REQUIRE(i >= 0 && i < L, DMRG_ERR_INVALID_ARG, "bad site");
+  const FirstOrderChain& FL = fo_chain[0];
+  const FirstOrderChain& FR = fo_chain[1];
+  const bool use_left = i > 0;
+  const bool use_right = kind == DMRG_SIGMA_TDA_FULL && i < L - 1;
+  auto check = [&](const FirstOrderChain& F, int bond, const char* side) {
+    DMRG_REQUIRE(F.bond == bond, DMRG_ERR_STATE,
+                 std::string("the first-order ") + side + " chain must be at bond " + std::to_string(bond) +
+                     " (dmrg_renormalize with order 1 up to this site)");
+    DMRG_REQUIRE(F.nvec == nvec, DMRG_ERR_INVALID_ARG, std::string("nvec differs from the ") + side + " chain's");
+    DMRG_REQUIRE(prec != DMRG_FP64 || F.prec == DMRG_FP64, DMRG_ERR_INVALID_ARG,
+                 std::string("an FP64 sigma needs FP64 first-order sets (the ") + side + " chain holds FP32)");
+  };
+  if (use_left) check(FL, i, "left");
+  if (use_right) check(FR, i + 1, "right");
+  const long S = long(layout(i, 1).size);
+  const double* C0 = site[i].C.as<double>();
+  // plans outside the timed region
+  if (kind == DMRG_SIGMA_TDA_FULL) sigma_plan(i, 1, left[i], right[i + 1]);
+  if (use_left) sigma_plan(i, 1, FL.at(), right[i + 1]);
+  if (use_right) sigma_plan(i, 1, left[i], FR.at(), nvec > 1);
+  const int parts = (kind == DMRG_SIGMA_TDA_FULL) + use_left + use_right;
+  if (parts > 1) ws_tda.ensure(this, size_t(nvec) * S * 8);
+  double fl = 0, mfl = 0, mby = 0;
+  auto acc = [&]() {
+    fl += stats.sigma_flops;
+    mfl += stats.sigma_main_flops;
+    mby += stats.sigma_main_bytes;
+  };
+  timed_sigma([&] {
+    bool first = true;
+    auto target = [&]() { return first ? Sout : ws_tda.as<double>(); };
+    auto merge = [&]() {
+      if (!first) launch_add_f64(ws_tda.as<double>(), Sout, long(nvec) * S, stream);
+      first = false;
+    };
+    if (kind == DMRG_SIGMA_TDA_FULL) {
+      sigma_general(i, 1, left[i], right[i + 1], Cin, S, target(), S, nvec, prec);
+      acc();
+      merge();
+    }
+    if (use_left) {
+      const bool shared = kind == DMRG_SIGMA_TDA_FULL;  // C^(0) for every vector
+      sigma_general(i, 1, FL.at(), right[i + 1], shared ? C0 : Cin, shared ? 0 : S, target(), S, nvec, prec);
+      acc();
+      merge();
+    }
+    if (use_right) {
+      sigma_general(i, 1, left[i], FR.at(), C0, 0, target(), S, nvec, prec);
+      acc();
+      merge();
+    }
+    if (first) launch_fill_f64(Sout, long(nvec) * S, 0.0, stream);  // no part (left part at site 0)
+    DMRG_HIP(hipGetLastError());
+  });
+  stats.sigma_flops = fl;
+  stats.sigma_main_flops = mfl;
+  stats.sigma_main_bytes = mby;
 }
 
 void Ctx::tda_roots(int nroots, const dmrg_davidson_params& p, double* omega, double* etot, double* resid2,

@@ -15,7 +15,7 @@ import pytest
 
 import synth
 
-from helpers import mps_arrays
+from synth import mps_arrays
 
 pytestmark = pytest.mark.gpu
 

@@ -8,7 +8,7 @@ import pytest
 import synth
 from oracle import fci, mpsvec, tda
 
-from helpers import mps_from_arrays
+from synth import mps_from_arrays
 
 pytestmark = pytest.mark.gpu
 

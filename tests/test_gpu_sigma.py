@@ -6,7 +6,7 @@ import pytest
 import synth
 from oracle import fci, mpsvec
 
-from helpers import mps_arrays
+from synth import mps_arrays
 
 pytestmark = pytest.mark.gpu
 
