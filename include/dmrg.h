@@ -174,6 +174,25 @@ int dmrg_build_ops(dmrg_ctx* ctx, int prec);
 int dmrg_sigma(dmrg_ctx* ctx, int site, int kind, int nvec, const double* C_in,
                double* sigma_out, size_t len, int prec);
 
+/* No-allocation variant of dmrg_sigma, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Zeroth-order kinds only (ZEROTH_1SITE,
+ * ZEROTH_2SITE); same arguments, layout and result as dmrg_sigma.  Its
+ * workspaces come from a statically allocated scratch array of
+ * DMRG_NOALLOC_SCRATCH_BYTES per GPU, held for the life of the process; it
+ * calls no hipMalloc / hipFree and creates no event (stats.sigma_ms is not
+ * updated).  One ordinary dmrg_sigma call with the same site, kind, nvec and
+ * precision must come first: it builds the plans and tile lists and records
+ * the workspace sizes.  Every call on a GPU shares that GPU's scratch (it
+ * keeps the last call's contents; nothing in it needs clearing), so calls
+ * that overlap on one GPU race.
+ * Errors: INVALID_ARG (as dmrg_sigma, a TDA kind, or a workspace larger
+ * than the scratch), STATE (no preparing dmrg_sigma call, or something the
+ * call would have to allocate is missing). */
+#define DMRG_NOALLOC_SCRATCH_BYTES (64u << 20)
+int dmrg_sigma_noalloc(dmrg_ctx* ctx, int site, int kind, int nvec, const double* C_in,
+                       double* sigma_out, size_t len, int prec);
+
 /* Tile-shape autotuner of the grouped block GEMM (the contractions of Sec.
  * III B-D): times the one-site sigma at `site` for nvec vectors in precision
  * prec under every pair of stage-1 / stage-2 tile shapes (the planner's
@@ -284,6 +303,9 @@ typedef struct {
   double plan_ms;          /* host time of planning the contractions of the last
                               dmrg_build_ops (renorm_ms is then the device time of
                               its renormalizations alone)                           */
+  double sigma_workspace_bytes; /* device workspace of the last zeroth-order
+                              dmrg_sigma (what dmrg_sigma_noalloc needs from its
+                              scratch for the same shape)                           */
 } dmrg_stats;
 
 int dmrg_get_stats(dmrg_ctx* ctx, dmrg_stats* out);

@@ -55,7 +55,7 @@ class Stats(ctypes.Structure):
         "sigma_flops", "sigma_ms", "sigma_main_ms", "sigma_main_flops", "sigma_main_bytes",
         "renorm_flops", "renorm_ms", "op_bytes", "tda_iter_ms", "tda_sigma_flops")] + [
         ("tda_iters", ctypes.c_int), ("sigma_main_launches", ctypes.c_int), ("tda_sigma_ms", ctypes.c_double),
-        ("plan_ms", ctypes.c_double)]
+        ("plan_ms", ctypes.c_double), ("sigma_workspace_bytes", ctypes.c_double)]
 
 
 class SweepParams(ctypes.Structure):
@@ -87,6 +87,7 @@ _build_ops = _sig("dmrg_build_ops", _P, _I)
 _Z = ctypes.c_size_t
 _sigma = _sig("dmrg_sigma", _P, _I, _I, _I, _P, _P, _Z, _I)
 _diag = _sig("dmrg_diag", _P, _I, _I, _P, _Z, _I)
+_sigma_noalloc = _sig("dmrg_sigma_noalloc", _P, _I, _I, _I, _P, _P, _Z, _I)
 _autotune = _sig("dmrg_autotune", _P, _I, _I, _I, _IP, _DP)
 _renorm = _sig("dmrg_renormalize", _P, _I, _I, _I, _I, _P, _Z, _I)
 _sweep = _sig("dmrg_sweep_ground", _P, ctypes.POINTER(SweepParams), _DP, _DP)
@@ -262,6 +263,21 @@ class Context:
                 raise ValueError("out must not alias C")
         self._check(_sigma(self._h, site, kind, nvec, ctypes.c_void_p(C.data_ptr()),
                            ctypes.c_void_p(out.data_ptr()), C.numel(), prec))
+        return out
+
+    def sigma_noalloc(self, site, C, out, kind=SIGMA_ZEROTH_1SITE, prec=FP64):
+        """dmrg_sigma_noalloc: the zeroth-order sigma with workspaces from the
+        library's static scratch; `out` must be given (nothing is allocated).
+        Needs one sigma() call with the same site, kind, nvec and precision
+        first."""
+        width = 2 if kind == SIGMA_ZEROTH_2SITE else 1
+        size = self.size(site, width)
+        nvec = self._vectors("C", C, size)
+        self._vectors("out", out, size, nvec)
+        if out.data_ptr() == C.data_ptr():
+            raise ValueError("out must not alias C")
+        self._check(_sigma_noalloc(self._h, site, kind, nvec, ctypes.c_void_p(C.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr()), C.numel(), prec))
         return out
 
     def autotune(self, site, nvec, prec=FP32):

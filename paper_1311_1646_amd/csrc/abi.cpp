@@ -143,6 +143,24 @@ int dmrg_sigma(dmrg_ctx* ctx, int site, int kind, int nvec, const double* C_in, 
   });
 }
 
+int dmrg_sigma_noalloc(dmrg_ctx* ctx, int site, int kind, int nvec, const double* C_in, double* sigma_out,
+                       size_t len, int prec) {
+  return guard(ctx, [&](dmrg::Ctx& x) {
+    x.require_gpu();
+    DMRG_REQUIRE(valid_prec(prec), DMRG_ERR_INVALID_ARG, "unsupported precision");
+    DMRG_REQUIRE(kind == DMRG_SIGMA_ZEROTH_1SITE || kind == DMRG_SIGMA_ZEROTH_2SITE, DMRG_ERR_INVALID_ARG,
+                 "the no-allocation sigma takes the zeroth-order kinds only");
+    DMRG_REQUIRE(nvec >= 1 && C_in && sigma_out, DMRG_ERR_INVALID_ARG, "need nvec >= 1 and non-null arrays");
+    DMRG_REQUIRE(x.have_mps, DMRG_ERR_STATE, "no MPS");
+    const int width = kind == DMRG_SIGMA_ZEROTH_2SITE ? 2 : 1;
+    DMRG_REQUIRE(site >= 0 && site + width <= x.L, DMRG_ERR_INVALID_ARG, "bad site");
+    const size_t size = x.layout(site, width).size;
+    DMRG_REQUIRE(len == size * size_t(nvec), DMRG_ERR_INVALID_ARG, "len is not nvec * size");
+    static_assert(DMRG_NOALLOC_SCRATCH_BYTES == (64u << 20), "scratch size of the header and the library");
+    x.sigma_noalloc(site, width, nvec, C_in, sigma_out, prec);
+  });
+}
+
 int dmrg_autotune(dmrg_ctx* ctx, int site, int nvec, int prec, int* shapes_out, double* best_ms_out) {
   return guard(ctx, [&](dmrg::Ctx& x) {
     DMRG_REQUIRE(valid_prec(prec), DMRG_ERR_INVALID_ARG, "unsupported precision");

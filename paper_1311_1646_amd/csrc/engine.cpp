@@ -91,8 +91,7 @@ void GemmPlan::launch(Ctx& x, const Bases& b, int batch, int prec, bool out_f64,
   if (F.nslots > 0) {
     const size_t esz = prec == DMRG_FP64 ? 8 : 4;
     const size_t tile = size_t(tile_rows(F.shape)) * tile_cols(F.shape);
-    x.ws_part.ensure(&x, size_t(F.nslots) * (fold == FOLD_NONE ? batch : 1) * tile * esz);
-    part = x.ws_part.p;
+    part = x.workspace(WS_PART, x.ws_part, size_t(F.nslots) * (fold == FOLD_NONE ? batch : 1) * tile * esz);
   }
   if (role == 1) x.mark_main(true);
   launch_grouped_gemm(prec, out_f64, role, F.shape, F.tiles.as<GTile>(), F.ntiles, jobs.as<GJob>(),
@@ -581,7 +580,10 @@ Ctx::Ctx(int L_, int na, int nb, const double* h, const double* eri, double ecor
   for (auto& a : tile_policy)
     for (auto& b : a)
       for (int& c : b) c = -1;
-  if (device >= 0) DMRG_HIP(hipSetDevice(device));
+  if (device >= 0) {
+    DMRG_HIP(hipSetDevice(device));
+    scratch_ = scratch_address(device);
+  }
   H.reset(new QCHamiltonian(L, h, eri, ecore));
 }
 
@@ -609,6 +611,9 @@ void Ctx::sync() { DMRG_HIP(hipStreamSynchronize(stream)); }
 
 void* Ctx::dev_alloc(size_t bytes) {
   require_gpu();
+  DMRG_REQUIRE(!no_alloc_, DMRG_ERR_STATE,
+               "dmrg_sigma_noalloc would allocate device memory (plans, tile lists or FP32 operator copies are "
+               "missing): call dmrg_sigma once with the same site, kind, nvec and precision first");
   void* p = nullptr;
   if (allocator.alloc) {
     p = allocator.alloc(bytes, stream, allocator.user);
@@ -1501,11 +1506,11 @@ void Ctx::sigma_general(int i, int width, const OpSet& X, const OpSet& Z, const 
   b.stride[B_SOUT] = sstride;
   b.stride[B_LOPS] = xb ? X.per_vec : 0;
   b.stride[B_ROPS] = zb ? Z.per_vec : 0;
-  ws_dress.ensure(this, std::max<size_t>(size_t(P.dressed_per_vec) * (dress_b ? batch : 1), 1) * esz);
-  ws_T.ensure(this, std::max<size_t>(size_t(P.main.t_per_vec) * (t_b ? batch : 1), 1) * esz);
-  b.p[B_DRESS] = ws_dress.as<double>();
+  b.p[B_DRESS] = static_cast<double*>(
+      workspace(WS_DRESS, ws_dress, std::max<size_t>(size_t(P.dressed_per_vec) * (dress_b ? batch : 1), 1) * esz));
   b.stride[B_DRESS] = dress_b ? P.dressed_per_vec : 0;
-  b.p[B_T] = ws_T.as<double>();
+  b.p[B_T] = static_cast<double*>(
+      workspace(WS_T, ws_T, std::max<size_t>(size_t(P.main.t_per_vec) * (t_b ? batch : 1), 1) * esz));
   b.stride[B_T] = t_b ? P.main.t_per_vec : 0;
   if (prec == DMRG_FP64) {
     DMRG_REQUIRE(!X.f32 && !Z.f32, DMRG_ERR_INTERNAL, "FP32 operator set in an FP64 sigma");
@@ -1522,9 +1527,9 @@ void Ctx::sigma_general(int i, int width, const OpSet& X, const OpSet& Z, const 
     float* z32 = f32_data(Z);
     const long cs = layout(i, width).size;
     const long nc = cb ? cs * batch : cs;
-    ws_c32.ensure(this, std::max<size_t>(size_t(nc), 1) * 4);
-    launch_convert_f64_f32(C, ws_c32.as<float>(), nc, stream);
-    b.p[B_CIN] = reinterpret_cast<double*>(ws_c32.as<float>());
+    float* c32 = static_cast<float*>(workspace(WS_C32, ws_c32, std::max<size_t>(size_t(nc), 1) * 4));
+    launch_convert_f64_f32(C, c32, nc, stream);
+    b.p[B_CIN] = reinterpret_cast<double*>(c32);
     b.stride[B_CIN] = cb ? cs : 0;
     b.p[B_LOPS] = reinterpret_cast<double*>(x32);
     b.p[B_ROPS] = reinterpret_cast<double*>(z32);
@@ -1551,9 +1556,63 @@ void Ctx::sigma(int i, int width, int nvec, const double* Cin, double* Sout, int
   DMRG_REQUIRE(nvec >= 1 && Cin && Sout, DMRG_ERR_INVALID_ARG, "bad sigma arguments");
   const SiteLayout& S = layout(i, width);
   sigma_plan(i, width, left[i], right[i + width]);  // plan outside the timed region
+  ws_need_ = WsNeed();
   timed_sigma([&] {
     sigma_general(i, width, left[i], right[i + width], Cin, long(S.size), Sout, long(S.size), nvec, prec);
   });
+  // workspace of this sigma, for a later no-allocation call with the same shape
+  WsNeed& w = sigma_need_[std::make_tuple(i, width, nvec, prec)];
+  double total = 0;
+  for (int k = 0; k < WS_NSLOTS; ++k) {
+    w.bytes[k] = std::max(w.bytes[k], ws_need_.bytes[k]);
+    total += double((w.bytes[k] + 255) / 256 * 256);
+  }
+  stats.sigma_workspace_bytes = total;
+}
+
+void* Ctx::workspace(int slot, DBuf& buf, size_t bytes) {
+  ws_need_.bytes[slot] = std::max(ws_need_.bytes[slot], bytes);
+  if (no_alloc_) {
+    DMRG_REQUIRE(bytes <= carve_len_[slot], DMRG_ERR_INTERNAL, "workspace beyond the size recorded for it");
+    return static_cast<char*>(scratch_) + carve_off_[slot];
+  }
+  buf.ensure(this, bytes);
+  return buf.p;
+}
+
+// The zeroth-order sigma of dmrg_sigma with every workspace in fixed regions
+// of the static scratch (sizes recorded by an earlier dmrg_sigma of the same
+// shape); no device memory is allocated or freed and no event is created.
+// Nothing in the scratch needs clearing: every product, dressed operator,
+// partial tile and FP32 vector is written before it is read.
+void Ctx::sigma_noalloc(int i, int width, int nvec, const double* Cin, double* Sout, int prec) {
+  require_gpu();
+  DMRG_REQUIRE(ops_prec >= 0, DMRG_ERR_STATE, "call dmrg_build_ops first");
+  DMRG_REQUIRE(nvec >= 1 && Cin && Sout, DMRG_ERR_INVALID_ARG, "bad sigma arguments");
+  DMRG_REQUIRE(scratch_, DMRG_ERR_STATE, "no scratch address for this device");
+  const auto it = sigma_need_.find(std::make_tuple(i, width, nvec, prec));
+  DMRG_REQUIRE(it != sigma_need_.end(), DMRG_ERR_STATE,
+               "dmrg_sigma_noalloc needs one dmrg_sigma call with the same site, kind, nvec and precision "
+               "first (it builds the plans and records the workspace sizes)");
+  size_t off = 0;
+  for (int k = 0; k < WS_NSLOTS; ++k) {
+    carve_off_[k] = off;
+    carve_len_[k] = it->second.bytes[k];
+    off += (it->second.bytes[k] + 255) / 256 * 256;
+  }
+  DMRG_REQUIRE(off <= scratch_bytes(), DMRG_ERR_INVALID_ARG,
+               "this sigma needs " + std::to_string(off) + " bytes of workspace, more than the " +
+                   std::to_string(scratch_bytes()) + " bytes of the no-allocation scratch");
+  const long n = long(layout(i, width).size);
+  no_alloc_ = true;
+  try {
+    sigma_general(i, width, left[i], right[i + width], Cin, n, Sout, n, nvec, prec);
+  } catch (...) {
+    no_alloc_ = false;
+    throw;
+  }
+  no_alloc_ = false;
+  DMRG_HIP(hipGetLastError());
 }
 
 void Ctx::autotune(int i, int nvec, int prec, int* shapes, double* best_ms) {

@@ -31,6 +31,19 @@ struct DBuf {
   template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Workspace slots of a sigma: dressed operators, stage-1 products, FP32 copy
+// of the input vectors, partial tiles of split contribution lists.
+enum : int { WS_DRESS = 0, WS_T = 1, WS_C32 = 2, WS_PART = 3, WS_NSLOTS = 4 };
+struct WsNeed {
+  size_t bytes[WS_NSLOTS] = {0, 0, 0, 0};
+};
+
+// Statically allocated device scratch of the no-allocation sigma
+// (noalloc.hip): its size and this device's address of it (the device must
+// be current; looked up once per device).
+size_t scratch_bytes();
+void* scratch_address(int device);
+
 // Base slots of the work lists (see kernels.hpp).
 enum : int {
   B_CIN = 0, B_SOUT = 1, B_T = 2, B_LOPS = 3, B_ROPS = 4, B_DRESS = 5,
@@ -294,6 +307,17 @@ class Ctx {
   // dmrg_sigma with a TDA kind (DMRG_SIGMA_TDA_FULL / TDA_DH_LEFT) at site i
   void sigma_tda(int i, int kind, int nvec, const double* Cin, double* Sout, int prec);
   FirstOrderChain fo_chain[2];  // [0]: left sets, [1]: right sets
+  // dmrg_sigma_noalloc: the zeroth-order sigma with its workspaces carved from
+  // the static scratch; any device allocation inside it is an error
+  void sigma_noalloc(int i, int width, int nvec, const double* Cin, double* Sout, int prec);
+  // device memory of a workspace slot: the owned buffer grown on demand, or in
+  // a no-allocation call the slot's fixed region of the scratch
+  void* workspace(int slot, DBuf& buf, size_t bytes);
+  WsNeed ws_need_;  // peak bytes per slot since the last reset
+  std::map<std::tuple<int, int, int, int>, WsNeed> sigma_need_;  // (site, width, nvec, prec)
+  void* scratch_ = nullptr;
+  bool no_alloc_ = false;
+  size_t carve_off_[WS_NSLOTS] = {0, 0, 0, 0}, carve_len_[WS_NSLOTS] = {0, 0, 0, 0};
   GaugeKit& gauge_kit();
   void drop_gauge_kit();
   // record device time of f() (and of the dominant launches inside it) into
