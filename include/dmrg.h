@@ -231,7 +231,8 @@ int dmrg_diag(dmrg_ctx* ctx, int site, int width, double* diag_out, size_t len, 
  *   A1 Q^R = A1 - (A1 R^T) R (right), per symmetry block.  The chain's sets
  *   are held in FP64 for prec FP64 and in FP32 otherwise; they are used by
  *   the TDA sigma kinds of dmrg_sigma and dropped by dmrg_import_mps,
- *   dmrg_build_ops and dmrg_sweep_ground.
+ *   dmrg_build_ops, dmrg_sweep_ground and dmrg_tda_roots (which builds its
+ *   own first-order operators).
  * Errors: STATE (before build_ops, chain at another bond), INVALID_ARG (site,
  * dir, order, nvec or precision class differing from the chain's, len). */
 int dmrg_renormalize(dmrg_ctx* ctx, int site, int dir, int order, int nvec, const double* A1,
@@ -271,14 +272,26 @@ typedef struct {
   int seed;            /* random initial trial vectors                           */
   int prec;            /* contraction precision                                  */
   int verbose;
+  int polish;          /* BF16X3 runs only: 0 (default) finishes with FP32
+                          iterations once the residual reaches the estimated
+                          floor of the split products, L (2^-16 E_0)^2 x 4, or
+                          tol, or stalls near that floor (at least two FP32
+                          iterations; convergence is judged in FP32); -1 keeps
+                          BF16X3 to the end                                   */
 } dmrg_davidson_params;
 
 /* DMRG-TDA roots by the sweep Davidson algorithm (Sec. III, Fig. alg:dmrgtda)
  * on the current MPS (imported or from dmrg_sweep_ground; build_ops first).
+ * A BF16X3 run is polished by FP32 iterations (see dmrg_davidson_params):
+ * the split products carry about 2^-17 relative error per product, which
+ * enters the reduced matrices of eqs. hleft2 / sleft2 to first order, while
+ * the FP32 contractions meet the 1e-5 Eh excitation tolerance;
+ * stats.tda_polish_iters reports how many iterations ran in FP32.
  * Outputs (host, nroots each): omega = E_mu - E_0 with E_0 = <Psi0|H|Psi0>,
  * e_total = E_mu, resid2 = sum over sites of |r_i^mu|^2 of the last
  * iteration; iters = Davidson iterations used.  NOT_CONVERGED fills the
- * outputs with the last iterate. */
+ * outputs with the last iterate.  Releases the first-order chains of
+ * dmrg_renormalize (order 1) before it starts. */
 int dmrg_tda_roots(dmrg_ctx* ctx, int nroots, const dmrg_davidson_params* p, double* omega,
                    double* e_total, double* resid2, int* iters);
 
@@ -306,6 +319,13 @@ typedef struct {
   double sigma_workspace_bytes; /* device workspace of the last zeroth-order
                               dmrg_sigma (what dmrg_sigma_noalloc needs from its
                               scratch for the same shape)                           */
+  int tda_polish_iters;    /* iterations of the last dmrg_tda_roots run in FP32
+                              polish (0: none)                                      */
+  int tda_hist_len;        /* entries of tda_r2_hist                                */
+  double tda_r2_hist[64];  /* max over roots of sum_i |r_i^mu|^2 per iteration of
+                              the last dmrg_tda_roots (first 64 iterations)         */
+  double tda_total_ms;     /* wall time of the last dmrg_tda_roots, including the
+                              initial sweeps                                        */
 } dmrg_stats;
 
 int dmrg_get_stats(dmrg_ctx* ctx, dmrg_stats* out);

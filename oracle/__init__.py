@@ -3,8 +3,8 @@
 Plain, slow, obviously correct reference implementations of what the GPU
 library computes, written from the paper's definitions:
 
-  fci.py     determinant-basis Hamiltonian and exact diagonalization (the
-             Hamiltonian of real orbitals in second quantization; the
+  fci.py     determinant-basis Hamiltonian and exact (dense) diagonalization
+             (the Hamiltonian of real orbitals in second quantization; the
              eigenproblem of the time-independent DMRG equation at full M);
   fock.py    brute-force Jordan-Wigner Fock-space matrices for tiny systems
              (an independent construction used only to pin fci.py);
@@ -13,8 +13,8 @@ library computes, written from the paper's definitions:
              Hamiltonian P^T H P (definition of the site problem, Sec. II A);
   tda.py     the Tamm-Dancoff eigenproblem as Rayleigh-Ritz of H in the MPS
              tangent space with the reference removed (Sec. II C-D);
-  blocksparse.py  a plain per-block numpy sigma used only as the CPU timing
-             baseline of the benchmark.
+  firstorder.py  first-order MPS wavefunctions in the mixed gauge (Sec. II B)
+             and the TDA sigma P_i^T H Psi1 (Sec. III D, eqs. sigv1, sigv2).
 
 Only tests/, the smoke check in __graft_entry__.py and the cpu_baseline leg
 of bench.py may import this package.  The GPU library never does, and this

@@ -19,7 +19,6 @@ import math
 
 import numpy as np
 import scipy.sparse as sp
-import scipy.sparse.linalg as spla
 
 
 def determinants(L, Na, Nb):
@@ -97,16 +96,19 @@ def hamiltonian(h, eri, ecore, Na, Nb):
     return dets, H.tocsr()
 
 
+DENSE_MAX = 6000
+
+
 def fci(h, eri, ecore, Na, Nb, nroots=1):
-    """Lowest eigenpairs of the FCI Hamiltonian (dense eigh when small)."""
+    """Lowest eigenpairs of the FCI Hamiltonian by dense diagonalization
+    (exact to rounding).  Larger spaces are refused: no test needs them, and
+    an iterative eigensolver would be a second, unpinned code path."""
     dets, H = hamiltonian(h, eri, ecore, Na, Nb)
     n = len(dets)
-    if n <= 6000:
-        w, v = np.linalg.eigh(H.toarray())
-        return dets, H, w[:nroots], v[:, :nroots]
-    w, v = spla.eigsh(H, k=nroots, which="SA", tol=1e-12)
-    order = np.argsort(w)
-    return dets, H, w[order], v[:, order]
+    if n > DENSE_MAX:
+        raise ValueError(f"{n} determinants: the oracle diagonalizes at most {DENSE_MAX} densely")
+    w, v = np.linalg.eigh(H.toarray())
+    return dets, H, w[:nroots], v[:, :nroots]
 
 
 def ndeterminants(L, Na, Nb):

@@ -55,7 +55,9 @@ class Stats(ctypes.Structure):
         "sigma_flops", "sigma_ms", "sigma_main_ms", "sigma_main_flops", "sigma_main_bytes",
         "renorm_flops", "renorm_ms", "op_bytes", "tda_iter_ms", "tda_sigma_flops")] + [
         ("tda_iters", ctypes.c_int), ("sigma_main_launches", ctypes.c_int), ("tda_sigma_ms", ctypes.c_double),
-        ("plan_ms", ctypes.c_double), ("sigma_workspace_bytes", ctypes.c_double)]
+        ("plan_ms", ctypes.c_double), ("sigma_workspace_bytes", ctypes.c_double),
+        ("tda_polish_iters", ctypes.c_int), ("tda_hist_len", ctypes.c_int),
+        ("tda_r2_hist", ctypes.c_double * 64), ("tda_total_ms", ctypes.c_double)]
 
 
 class SweepParams(ctypes.Structure):
@@ -65,7 +67,7 @@ class SweepParams(ctypes.Structure):
 
 class DavidsonParams(ctypes.Structure):
     _fields_ = [("max_iter", _I), ("max_space", _I), ("tol", _D), ("seed", _I), ("prec", _I),
-                ("verbose", _I)]
+                ("verbose", _I), ("polish", _I)]
 
 
 def _sig(name, *args):
@@ -322,8 +324,10 @@ class Context:
             self._check(rc)
         return e.value, dw.value, rc == 0
 
-    def tda_roots(self, nroots, max_iter=60, max_space=0, tol=1e-9, seed=7, prec=FP64, verbose=0):
-        p = DavidsonParams(max_iter, max_space, tol, seed, prec, verbose)
+    def tda_roots(self, nroots, max_iter=60, max_space=0, tol=1e-9, seed=7, prec=FP64, verbose=0, polish=True):
+        """DMRG-TDA roots (see dmrg_tda_roots); polish: a BF16X3 run ends with
+        FP32 iterations (stats()["tda_polish_iters"] says how many)."""
+        p = DavidsonParams(max_iter, max_space, tol, seed, prec, verbose, 0 if polish else -1)
         om = np.zeros(nroots)
         et = np.zeros(nroots)
         r2 = np.zeros(nroots)
@@ -336,7 +340,9 @@ class Context:
     def stats(self):
         s = Stats()
         self._check(_stats(self._h, ctypes.byref(s)))
-        return {k: getattr(s, k) for k, _ in Stats._fields_}
+        out = {k: getattr(s, k) for k, _ in Stats._fields_}
+        out["tda_r2_hist"] = list(s.tda_r2_hist[:s.tda_hist_len])
+        return out
 
     def debug_mpo_dense(self, wide_bond=-1, from_right=False):
         out = np.zeros((4 ** self.L, 4 ** self.L))

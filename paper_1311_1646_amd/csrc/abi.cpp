@@ -226,6 +226,7 @@ int dmrg_tda_roots(dmrg_ctx* ctx, int nroots, const dmrg_davidson_params* p, dou
   int rc = guard(ctx, [&](dmrg::Ctx& x) {
     DMRG_REQUIRE(p, DMRG_ERR_INVALID_ARG, "null parameters");
     DMRG_REQUIRE(valid_prec(p->prec), DMRG_ERR_INVALID_ARG, "unsupported precision");
+    DMRG_REQUIRE(p->polish == 0 || p->polish == -1, DMRG_ERR_INVALID_ARG, "polish must be 0 or -1");
     x.tda_roots(nroots, *p, omega, e_total, resid2, iters, &conv);
   });
   if (rc == DMRG_OK && !conv) {

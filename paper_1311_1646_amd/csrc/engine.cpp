@@ -1570,6 +1570,11 @@ void Ctx::sigma(int i, int width, int nvec, const double* Cin, double* Sout, int
   stats.sigma_workspace_bytes = total;
 }
 
+void Ctx::release_workspaces() {
+  sync();
+  for (DBuf* b : {&ws_T, &ws_dress, &ws_blk, &ws_aux, &ws_c32, &ws_part, &ws_a32, &ws_fo, &ws_tda}) b->release();
+}
+
 void* Ctx::workspace(int slot, DBuf& buf, size_t bytes) {
   ws_need_.bytes[slot] = std::max(ws_need_.bytes[slot], bytes);
   if (no_alloc_) {

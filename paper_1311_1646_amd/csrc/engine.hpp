@@ -270,6 +270,9 @@ class Ctx {
   // workspaces
   DBuf ws_T, ws_dress, ws_blk, ws_aux, ws_c32, ws_part, ws_a32;
   DBuf ws_fo, ws_tda;  // projected first-order tensors; partial TDA sigmas
+  // free every grow-only workspace (after a sweep run, whose batched
+  // contractions grow them far beyond what a single sigma needs)
+  void release_workspaces();
 
   dmrg_stats stats{};
 

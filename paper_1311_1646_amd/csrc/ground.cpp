@@ -788,8 +788,11 @@ void Ground::run(double* energy, double* discarded, bool* converged) {
 
 void Ctx::sweep_ground(const dmrg_sweep_params& p, double* energy, double* discarded, bool* converged) {
   require_gpu();
-  Ground g(*this, p);
-  g.run(energy, discarded, converged);
+  {
+    Ground g(*this, p);
+    g.run(energy, discarded, converged);
+  }
+  release_workspaces();
 }
 
 }  // namespace dmrg

@@ -480,6 +480,7 @@ void TdaRunner::backward(int l) {
 namespace dmrg {
 
 void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, bool* converged) {
+  const auto run0 = std::chrono::steady_clock::now();
   // reference energy E0 = <Psi0|H|Psi0> at site 0
   {
     const double* C0 = x_.site[0].C.as<double>();
@@ -500,6 +501,18 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
   std::vector<double> w(64), last_w(n_, 0.0);
   double tda_flops0 = 0;
   (void)tda_flops0;
+  // BF16x3 runs end with FP32 iterations, switched on near the residual
+  // floor of the split products: a relative error of ~2^-16 on sigma vectors
+  // of size ~|E0| at each of the L sites gives sum_i |r_i|^2 ~ L (2^-16 E0)^2
+  // (times 4 for margin); also when the residual meets tol, or stalls for
+  // four iterations within a factor 100 of that floor
+  const bool can_polish = prec_ == DMRG_BF16X3 && p_.polish == 0;
+  const double floor_est = 4.0 * L_ * std::pow(std::ldexp(1.0, -16) * E0_, 2);
+  bool polishing = false;
+  int polish_iters = 0, stall = 0;
+  double best = 1e300;
+  x_.stats.tda_polish_iters = 0;
+  x_.stats.tda_hist_len = 0;
   for (it = 1; it <= p_.max_iter; ++it) {
     auto t0 = std::chrono::steady_clock::now();
     // small generalized eigenproblem H_R a = w S_R a (eq. eigs)
@@ -526,11 +539,30 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
     auto t1 = std::chrono::steady_clock::now();
     x_.stats.tda_iter_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     x_.stats.tda_iters = it;
-    if (p_.verbose) {
-      std::fprintf(stderr, "[tda] it %d l %d max|r|^2 %.3e  w0 %.10f (%.1f ms)\n", it, l, mx, w[0] - E0_,
-                   x_.stats.tda_iter_ms);
+    if (it <= 64) {
+      x_.stats.tda_r2_hist[it - 1] = mx;
+      x_.stats.tda_hist_len = it;
     }
-    if (mx < p_.tol) {
+    if (polishing) x_.stats.tda_polish_iters = ++polish_iters;
+    if (p_.verbose) {
+      std::fprintf(stderr, "[tda] it %d l %d max|r|^2 %.3e  w0 %.10f (%.1f ms)%s\n", it, l, mx, w[0] - E0_,
+                   x_.stats.tda_iter_ms, polishing ? " fp32 polish" : "");
+    }
+    bool done = mx < p_.tol;
+    if (can_polish && !polishing) {
+      if (mx < 0.5 * best) {
+        best = mx;
+        stall = 0;
+      } else {
+        ++stall;
+      }
+      if (done || mx < floor_est || (stall >= 4 && mx < 100.0 * floor_est)) {
+        polishing = true;
+        prec_ = DMRG_FP32;
+        done = false;
+      }
+    }
+    if (done && (!polishing || polish_iters >= 2)) {
       conv = true;
       break;
     }
@@ -547,6 +579,8 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
   }
   *iters = std::min(it, p_.max_iter);
   *converged = conv;
+  x_.stats.tda_total_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - run0).count();
 }
 
 // First-order block operators through the C-ABI (Sec. III B eq. lopr1st,
@@ -686,8 +720,15 @@ void Ctx::tda_roots(int nroots, const dmrg_davidson_params& p, double* omega, do
   DMRG_REQUIRE(ops_prec >= 0, DMRG_ERR_STATE, "call dmrg_build_ops first");
   DMRG_REQUIRE(omega && etot && resid2 && iters && converged, DMRG_ERR_INVALID_ARG, "null outputs");
   DMRG_REQUIRE(p.max_iter >= 1, DMRG_ERR_INVALID_ARG, "max_iter must be >= 1");
-  TdaRunner r(*this, nroots, p);
-  r.run(omega, etot, resid2, iters, converged);
+  // the run builds its own first-order operators; the chains of
+  // dmrg_renormalize (order 1) are released first to bound the peak memory
+  sync();
+  for (auto& f : fo_chain) f.reset();
+  {
+    TdaRunner r(*this, nroots, p);
+    r.run(omega, etot, resid2, iters, converged);
+  }
+  release_workspaces();
 }
 
 }  // namespace dmrg

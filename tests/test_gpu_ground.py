@@ -55,12 +55,17 @@ def test_truncated_sweep_is_variational_and_consistent(config0):
     np.testing.assert_allclose(et, ref, atol=1e-8)
 
 
-def test_fp32_sweep_meets_ground_energy_tolerance(config0):
-    # FP32 sigma and renormalization, FP64 Davidson / SVD: |E - E_FCI| <= 1e-6
+@pytest.mark.parametrize("prec", [1, 2])
+def test_low_precision_sweep_meets_ground_energy_tolerance(config0, prec):
+    # FP32 or BF16x3 sigma and renormalization (BF16x3 builds the zeroth-order
+    # pools in FP32), FP64 Davidson / SVD and the final energy evaluated in
+    # FP64: |E - E_FCI| <= 1e-6 Eh at the full bond dimension (the north-star
+    # ground-energy tolerance).  The energy is variational in the state, so
+    # a contraction error eps in the local solves enters it at O(eps^2).
     import paper_1311_1646_amd as lib
     p, dets, H, w = config0
     ctx = lib.Context(p.L, p.Na, p.Nb, p.h, p.eri, p.ecore, device=0)
     e, dw, ok = ctx.sweep_ground([64, 256, 256, 256], davidson_tol=1e-10, davidson_max_iter=60, seed=1,
-                                 prec=lib.FP32)
-    print(f"fp32 ground: E - E_FCI = {e - w[0]:.2e}")
+                                 prec=prec)
+    print(f"prec {prec} ground: E - E_FCI = {e - w[0]:.2e}")
     assert abs(e - w[0]) < 1e-6

@@ -157,3 +157,11 @@ def test_matrix_free_heff_apply_equals_explicit_heff():
     assert n == len(dets)
     He = mpsvec.heff_apply(H, full, dets, 1, np.eye(n))
     np.testing.assert_allclose(np.linalg.eigvalsh(He), np.linalg.eigvalsh(H.toarray()), atol=1e-11)
+
+
+def test_fci_refuses_spaces_above_the_dense_limit():
+    # L=9, 4+4 electrons: 126^2 = 15876 determinants, above the dense limit
+    L = 9
+    h, eri, _ = synth.random_integrals(L, seed=1, K=2, diag_lo=-1, diag_hi=0)
+    with pytest.raises(ValueError):
+        fci.fci(h, eri, 0.0, 4, 4)
