@@ -171,6 +171,69 @@ def sweep_averaged_sigma(ctx, lib, L, nvec, prec):
     return {"GFLOP/s": round(fl / (ms * 1e-3) / 1e9, 2), "device_ms_all_sites": round(ms, 2), "sites": L}
 
 
+def many_instances(lib, steps, warmup, n=64):
+    """The many-instance workload: n independent seeded problems (L uniform
+    in 8..16, N = L, M uniform in 32..256, random integrals as the small
+    dense check), each with its own random MPS; the zeroth-order sigma of
+    all n at their middle sites for nroots = 4 vectors each, FP32, as one
+    grouped launch per contraction stage (dmrg_group_*) replayed from a HIP
+    graph.  Compared with the same n sigmas issued context by context."""
+    import torch
+
+    import synth
+    from synth import mps_arrays
+    t0 = time.perf_counter()
+    ctxs, sites, Cs, outs = [], [], [], []
+    g = torch.Generator(device="cuda").manual_seed(33)
+    for i in range(n):
+        p = synth.config(3, instance=i)
+        mps = synth.random_mps(p.L, p.Na, p.Nb, p.M, seed=3000 + i)
+        c = lib.Context(p.L, p.Na, p.Nb, p.h, p.eri, p.ecore, device=0)
+        c.import_mps(*mps_arrays(mps))
+        c.build_ops(lib.FP64)
+        site = p.L // 2
+        ctxs.append(c)
+        sites.append(site)
+        Cs.append(torch.randn(p.nroots, c.size(site), dtype=torch.float64, device="cuda", generator=g))
+        outs.append(torch.empty_like(Cs[-1]))
+    setup = time.perf_counter() - t0
+    # context by context (plans and FP32 copies built by the warm-up)
+    for c, i, C, O in zip(ctxs, sites, Cs, outs):
+        c.sigma(i, C, out=O, prec=lib.FP32)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dev = 0.0
+    for _ in range(steps):
+        for c, i, C, O in zip(ctxs, sites, Cs, outs):
+            c.sigma(i, C, out=O, prec=lib.FP32)
+            dev += c.stats()["sigma_ms"]
+    torch.cuda.synchronize()
+    single_wall = (time.perf_counter() - t0) / steps * 1e3
+    grp = lib.Group(ctxs, sites, 4, prec=lib.FP32)
+    for _ in range(max(warmup, 2)):  # eager step, then graph capture
+        grp.sigma(Cs, outs, graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms = 0.0
+    for _ in range(steps):
+        grp.sigma(Cs, outs, graph=True)
+        ms += grp.stats()["ms"]
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps * 1e3
+    st = grp.stats()
+    grp.close()
+    for c in ctxs:
+        c.close()
+    return {"instances": n, "prec": "fp32", "vectors_per_instance": 4,
+            "aggregate_GFLOP/s": round(st["flops"] / (ms / steps * 1e-3) / 1e9, 2),
+            "device_ms_per_step": round(ms / steps, 4), "wall_ms_per_step": round(wall, 4),
+            "launches_per_step": st["launches"], "graph_nodes": st["graph_nodes"],
+            "flops_per_step": st["flops"],
+            "one_context_at_a_time": {"device_ms_per_step": round(dev / steps, 4),
+                                      "wall_ms_per_step": round(single_wall, 4)},
+            "setup_s": round(setup, 1)}
+
+
 def measured_traffic(prec, M):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (profiles/), or None when there is none for this precision and
@@ -208,6 +271,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the planner's tile shapes")
     ap.add_argument("--no-sweep-avg", action="store_true", help="skip the zeroth-order sigma at every site")
+    ap.add_argument("--no-group", action="store_true", help="skip the many-instance grouped sigma")
     a = ap.parse_args()
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only (no multi-GPU path); --gpus must be 1"}))
@@ -265,7 +329,7 @@ def main():
         pr = prec_id(lib, name)
         if not a.no_autotune:
             s1, s2, ms = ctx.autotune(site, a.nroots, pr)
-            names = {-1: "planner", 0: "64x64", 1: "128x64", 2: "64x128"}
+            names = {-1: "planner", 0: "64x64", 1: "128x64", 2: "64x128", 3: "128x128"}
             tuned[name] = {"stage1": names[s1], "stage2": names[s2]}
             log(f"[bench] autotune {name}: {tuned[name]} ({ms:.1f} ms)")
         zeroth = time_sigma(ctx, lib, site, C, S, pr, lib.SIGMA_ZEROTH_1SITE, a.steps, a.warmup)
@@ -335,6 +399,9 @@ def main():
                                                                             prec_id(lib, a.prec))
         log(f"[bench] sweep-averaged sigma: {out['config']['sweep_averaged_zeroth_sigma']}")
     ctx.close()
+    if not a.no_group:
+        out["config"]["many_instances"] = many_instances(lib, a.steps, a.warmup)
+        log(f"[bench] many instances: {out['config']['many_instances']}")
     if not a.no_cpu_baseline:
         try:
             out["cpu_baseline"] = cpu_baseline(4)

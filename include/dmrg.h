@@ -196,12 +196,13 @@ int dmrg_sigma_noalloc(dmrg_ctx* ctx, int site, int kind, int nvec, const double
 /* Tile-shape autotuner of the grouped block GEMM (the contractions of Sec.
  * III B-D): times the one-site sigma at `site` for nvec vectors in precision
  * prec under every pair of stage-1 / stage-2 tile shapes (the planner's
- * choice, 64x64, 128x64, 64x128) and keeps the fastest pair for all later
- * contractions of that precision in this context.  shapes_out[0..1]
- * receives the chosen stage-1 and stage-2 shapes (-1 = planner's choice,
- * 0 = 64x64, 1 = 128x64, 2 = 64x128) and best_ms_out the device time of that
- * sigma.  Allocates two nvec x size FP64 device buffers for the duration of
- * the call.  Errors: STATE before build_ops, INVALID_ARG. */
+ * choice, 64x64, 128x64, 64x128, and 128x128 for FP32 operands) and keeps the
+ * fastest pair for all later contractions of that precision in this context.
+ * shapes_out[0..1] receives the chosen stage-1 and stage-2 shapes (-1 =
+ * planner's choice, 0 = 64x64, 1 = 128x64, 2 = 64x128, 3 = 128x128) and
+ * best_ms_out the device time of that sigma.  Allocates two nvec x size FP64
+ * device buffers for the duration of the call.  Errors: STATE before
+ * build_ops, INVALID_ARG. */
 int dmrg_autotune(dmrg_ctx* ctx, int site, int nvec, int prec, int* shapes_out, double* best_ms_out);
 
 /* Diagonal of the one-site (width 1) or two-site (width 2) effective
@@ -294,6 +295,39 @@ typedef struct {
  * dmrg_renormalize (order 1) before it starts. */
 int dmrg_tda_roots(dmrg_ctx* ctx, int nroots, const dmrg_davidson_params* p, double* omega,
                    double* e_total, double* resid2, int* iters);
+
+/* Grouped sigma of many independent problems.  n member contexts (each with
+ * its MPS imported and dmrg_build_ops done, all on one device and stream)
+ * apply the zeroth-order one-site sigma (Sec. III B, eq. hzero_sb) at their
+ * own sites[i] to nvec vectors each, as one launch per contraction stage for
+ * all members: the members' cached work lists are concatenated, each job
+ * tagged with its member, whose base table the kernels read from device
+ * memory.  The group holds pointers into its members' operator pools: it is
+ * valid while they keep their MPS and operators (a later dmrg_import_mps,
+ * dmrg_build_ops, dmrg_sweep_ground or zeroth-order dmrg_renormalize on a
+ * member makes dmrg_group_sigma fail with STATE), and must be destroyed
+ * before its members.
+ * Errors: INVALID_ARG (sites, nvec, precision, contexts on different
+ * devices or streams), STATE (a member without operators), OOM. */
+typedef struct dmrg_group dmrg_group;
+int dmrg_group_create(dmrg_ctx* const* ctxs, int n, const int* sites, int nvec, int prec, dmrg_group** out);
+/* One grouped sigma step: C_in[i] / sigma_out[i] are member i's device FP64
+ * arrays of lens[i] = nvec * size elements (layout as in dmrg_sigma),
+ * borrowed for the call; enqueued after the members' earlier work and
+ * followed by their later work (their stream waits for it).  use_graph != 0
+ * replays the step from a HIP graph, captured at the second such call (the
+ * first one runs eagerly and builds the tile lists); new buffers re-upload
+ * only the base tables the graph reads.  Synchronizes (the step's device
+ * time is kept for dmrg_group_stats).
+ * Errors: INVALID_ARG (lens, null arrays), STATE (a member changed). */
+int dmrg_group_sigma(dmrg_group* g, const double* const* C_in, double* const* sigma_out, const size_t* lens,
+                     int use_graph);
+/* Algorithmic flops of one step (all members), device time of the last
+ * step, kernel launches per step, and nodes of the captured graph (0 before
+ * capture).  Any output pointer may be NULL. */
+int dmrg_group_stats(dmrg_group* g, double* flops, double* ms, int* launches, int* graph_nodes);
+const char* dmrg_group_last_error(const dmrg_group* g);
+int dmrg_group_destroy(dmrg_group* g);
 
 typedef struct {
   double sigma_flops;      /* algorithmic flops of the last dmrg_sigma call        */

@@ -96,6 +96,12 @@ _sweep = _sig("dmrg_sweep_ground", _P, ctypes.POINTER(SweepParams), _DP, _DP)
 _tda = _sig("dmrg_tda_roots", _P, _I, ctypes.POINTER(DavidsonParams), _DP, _DP, _DP, _IP)
 _stats = _sig("dmrg_get_stats", _P, ctypes.POINTER(Stats))
 _debug_dense = _sig("dmrg_debug_mpo_dense", _P, _I, _I, _DP)
+_group_create = _sig("dmrg_group_create", _P, _I, _IP, _I, _I, ctypes.POINTER(_P))
+_group_sigma = _sig("dmrg_group_sigma", _P, _P, _P, _SP, _I)
+_group_stats = _sig("dmrg_group_stats", _P, _DP, _DP, _IP, _IP)
+_group_destroy = _sig("dmrg_group_destroy", _P)
+_lib.dmrg_group_last_error.argtypes = [_P]
+_lib.dmrg_group_last_error.restype = ctypes.c_char_p
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -348,3 +354,60 @@ class Context:
         out = np.zeros((4 ** self.L, 4 ** self.L))
         self._check(_debug_dense(self._h, wide_bond, int(from_right), _dp(out)))
         return out
+
+
+class Group:
+    """Grouped zeroth-order sigma of many independent contexts (see
+    dmrg_group_create): one launch per contraction stage for all members,
+    optionally replayed from a HIP graph.  Keeps its contexts alive; close()
+    before closing them."""
+
+    def __init__(self, contexts, sites, nvec, prec=FP32):
+        self.ctx = list(contexts)
+        self.sites = [int(x) for x in sites]
+        if len(self.sites) != len(self.ctx):
+            raise ValueError("one site per context")
+        self.nvec, self.prec = int(nvec), prec
+        self.sizes = [c.size(i) for c, i in zip(self.ctx, self.sites)]
+        hs = (_P * len(self.ctx))(*[c._h.value for c in self.ctx])
+        st = np.ascontiguousarray(self.sites, np.int32)
+        self._h = ctypes.c_void_p()
+        rc = _group_create(ctypes.cast(hs, _P), len(self.ctx), _ip(st), self.nvec, prec, ctypes.byref(self._h))
+        if rc != 0:
+            raise DMRGError(rc, _lib.dmrg_group_last_error(None).decode())
+
+    def _check(self, rc):
+        if rc != 0:
+            raise DMRGError(rc, _lib.dmrg_group_last_error(self._h).decode())
+
+    def sigma(self, Cs, outs, graph=True):
+        """One step: outs[i] = H_eff(member i) Cs[i]; each a float64 (nvec,
+        size_i) tensor on the members' GPU."""
+        n = len(self.ctx)
+        if len(Cs) != n or len(outs) != n:
+            raise ValueError(f"need {n} input and output tensors")
+        for i, (c, C, O) in enumerate(zip(self.ctx, Cs, outs)):
+            c._vectors(f"C[{i}]", C, self.sizes[i], self.nvec)
+            c._vectors(f"out[{i}]", O, self.sizes[i], self.nvec)
+        cp = (_P * n)(*[C.data_ptr() for C in Cs])
+        op = (_P * n)(*[O.data_ptr() for O in outs])
+        lens = (ctypes.c_size_t * n)(*[C.numel() for C in Cs])
+        self._check(_group_sigma(self._h, ctypes.cast(cp, _P), ctypes.cast(op, _P), lens, int(bool(graph))))
+        return outs
+
+    def stats(self):
+        fl, ms = ctypes.c_double(), ctypes.c_double()
+        nl, nn = ctypes.c_int(), ctypes.c_int()
+        self._check(_group_stats(self._h, ctypes.byref(fl), ctypes.byref(ms), ctypes.byref(nl), ctypes.byref(nn)))
+        return {"flops": fl.value, "ms": ms.value, "launches": nl.value, "graph_nodes": nn.value}
+
+    def close(self):
+        if self._h:
+            _group_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -10,9 +10,6 @@ int debug_mpo_dense_left(QCHamiltonian& H, int wide_bond, double* out);
 int debug_mpo_dense_right(QCHamiltonian& H, int wide_bond, double* out);
 }  // namespace dmrg
 
-struct dmrg_ctx {
-  dmrg::Ctx* x;
-};
 
 namespace {
 thread_local std::string g_create_error;
@@ -200,6 +197,7 @@ int dmrg_renormalize(dmrg_ctx* ctx, int site, int dir, int order, int nvec, cons
       return;
     }
     DMRG_REQUIRE(nvec == 0 && !A1, DMRG_ERR_INVALID_ARG, "zeroth order takes no tensors (nvec 0, A1 NULL)");
+    ++x.generation;
     if (dir == DMRG_DIR_LEFT) {
       x.renorm(DMRG_DIR_LEFT, site, x.site[site].L.as<double>(), x.site[site].L.as<double>(), 0, x.left[site],
                x.left[site + 1], false, 1, prec);

@@ -233,10 +233,17 @@ struct FirstOrderChain {
   }
 };
 
+class SigmaGroup;
+
 class Ctx {
+  friend class SigmaGroup;
+
  public:
   Ctx(int L, int na, int nb, const double* h, const double* eri, double ecore, int device, void* stream,
       const dmrg_allocator* alloc);
+  // bumped whenever the MPS or the zeroth-order operator pools change
+  // (grouped launches hold pointers into them)
+  unsigned long generation = 0;
   ~Ctx();
 
   int L, Na, Nb;
@@ -397,3 +404,8 @@ void Ctx::timed_sigma(F&& f) {
 }
 
 }  // namespace dmrg
+
+// Opaque handle of the C-ABI (include/dmrg.h).
+struct dmrg_ctx {
+  dmrg::Ctx* x;
+};

@@ -105,9 +105,9 @@ __global__ void lincomb_f64_kernel(const LCTarget* __restrict__ tg, const LCSour
   }
 }
 
-__global__ void diag_add_f64_kernel(const DiagAdd* __restrict__ d, Bases bs) {
+__global__ void diag_add_f64_kernel(const DiagAdd* __restrict__ d, Bases bs, const Bases* __restrict__ ib) {
   const DiagAdd x = d[blockIdx.x];
-  double* o = bptr(bs, x.base, x.off, blockIdx.y);
+  double* o = bptr(ib ? ib[x.inst] : bs, x.base, x.off, blockIdx.y);
   for (int i = threadIdx.x; i < x.dim; i += blockDim.x) o[long(i) * (x.dim + 1)] += x.c;
 }
 
@@ -402,9 +402,11 @@ template <class T>
 __global__ __launch_bounds__(256) void lincomb_grouped_kernel(const LCGroup* __restrict__ groups,
                                                               const LCTarget* __restrict__ tg,
                                                               const LCSource* __restrict__ us,
-                                                              const T* __restrict__ coef, Bases bs) {
+                                                              const T* __restrict__ coef, Bases bs0,
+                                                              const Bases* __restrict__ ib) {
   constexpr int kElems = lc_elems<T>();
   const LCGroup G = groups[blockIdx.y];
+  const Bases& bs = ib ? ib[G.inst] : bs0;
   const long bz = blockIdx.z;
   const long span = long(blockDim.x) * kElems;
   for (long e0 = long(blockIdx.x) * span + threadIdx.x; e0 < G.size; e0 += long(gridDim.x) * span) {
@@ -466,7 +468,7 @@ __global__ __launch_bounds__(256) void lincomb_grouped_kernel(const LCGroup* __r
 
 void launch_lincomb_grouped(int prec, const LCGroup* g, int ngroups, const LCTarget* t, const LCSource* u,
                             const double* coef, const float* coef32, long max_size, const Bases& b, int batch,
-                            hipStream_t s) {
+                            hipStream_t s, const Bases* ib) {
   if (ngroups <= 0 || max_size <= 0 || batch <= 0) return;
   const long span = 256L * (prec == 0 ? lc_elems<double>() : lc_elems<float>());
   long blocks = (max_size + span - 1) / span;
@@ -475,9 +477,9 @@ void launch_lincomb_grouped(int prec, const LCGroup* g, int ngroups, const LCTar
     const int ng = ngroups - g0 < 65535 ? ngroups - g0 : 65535;
     const dim3 grid(unsigned(blocks), ng, batch);
     if (prec == 0)
-      hipLaunchKernelGGL(lincomb_grouped_kernel<double>, grid, dim3(256), 0, s, g + g0, t, u, coef, b);
+      hipLaunchKernelGGL(lincomb_grouped_kernel<double>, grid, dim3(256), 0, s, g + g0, t, u, coef, b, ib);
     else
-      hipLaunchKernelGGL(lincomb_grouped_kernel<float>, grid, dim3(256), 0, s, g + g0, t, u, coef32, b);
+      hipLaunchKernelGGL(lincomb_grouped_kernel<float>, grid, dim3(256), 0, s, g + g0, t, u, coef32, b, ib);
   }
 }
 
@@ -511,9 +513,9 @@ void launch_lincomb_f64(const LCTarget* t, int ntargets, const LCSource* src, lo
   }
 }
 
-void launch_diag_add_f64(const DiagAdd* d, int n, const Bases& b, int batch, hipStream_t s) {
+void launch_diag_add_f64(const DiagAdd* d, int n, const Bases& b, int batch, hipStream_t s, const Bases* ib) {
   if (n <= 0 || batch <= 0) return;
-  hipLaunchKernelGGL(diag_add_f64_kernel, dim3(n, batch), dim3(256), 0, s, d, b);
+  hipLaunchKernelGGL(diag_add_f64_kernel, dim3(n, batch), dim3(256), 0, s, d, b, ib);
 }
 
 void launch_fill_f64(double* p, long n, double v, hipStream_t s) {

@@ -45,6 +45,7 @@ struct GJob {
   int baseC, ldc, m, n;
   int c0, c1;  // contribution range
   int flags, pad;  // pad: start of the job's gather entries
+  int inst;        // instance of a grouped launch (index into its base tables)
 };
 struct GTile {
   int job, tm, tn, pad;
@@ -77,12 +78,13 @@ constexpr int kLCGroup = 16;
 struct LCGroup {
   long size;
   int t0, nt, u0, u1;
+  int inst;  // instance of a grouped launch
 };
 // prec 0: FP64 data and coefficients coef; otherwise FP32 data and the
 // same coefficients rounded to FP32 (coef32)
 void launch_lincomb_grouped(int prec, const LCGroup* g, int ngroups, const LCTarget* t, const LCSource* u,
                             const double* coef, const float* coef32, long max_size, const Bases& b, int batch,
-                            hipStream_t s);
+                            hipStream_t s, const Bases* ib = nullptr);
 
 // Strided 2-D copies dst(r, c) = src(r, c) * scale, element (r, c) at
 // r*ss_r + c*ss_c in the source and r*ds_r + c*ds_c in the destination;
@@ -101,8 +103,12 @@ struct DiagAdd {
   long off;
   int base, dim;
   double c;
+  int inst;  // instance of a grouped launch
 };
-void launch_diag_add_f64(const DiagAdd* d, int n, const Bases& b, int batch, hipStream_t s);
+// ib: per-instance base tables of a grouped launch (indexed by the job's,
+// group's or entry's instance), or null: every entry uses b
+void launch_diag_add_f64(const DiagAdd* d, int n, const Bases& b, int batch, hipStream_t s,
+                         const Bases* ib = nullptr);
 
 void launch_fill_f64(double* p, long n, double v, hipStream_t s);
 void launch_fill_f32(float* p, long n, hipStream_t s);  // p[0..n) = 0

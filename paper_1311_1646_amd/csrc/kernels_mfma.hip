@@ -41,7 +41,18 @@ typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int NTH = 256;
+constexpr int NTH = 256;  // threads of the auxiliary kernels
+
+// Workgroup geometry of a TM x TN output tile: 256 threads (four waves in
+// 2 x 2) up to 128 x 64, 512 threads (eight waves in 2 x 4) for 128 x 128, so
+// that every thread stages the same four elements of each operand per
+// K-chunk while a wave's share of the matrix-core work doubles.  Each wave
+// owns a (TM / 2) x (TN / WN) part of the tile.
+template <int TM, int TN> struct Geo {
+  static constexpr int NT = TM * TN >= 128 * 128 ? 512 : 256;
+  static constexpr int WN = NT / 128;  // waves along N (two along M)
+  static constexpr int WTM = TM / 2, WTN = TN / WN;
+};
 
 template <int MODE> struct Cfg;
 template <> struct Cfg<0> {  // FP64
@@ -74,12 +85,17 @@ template <int MODE, int TM, int TN> struct Lds {
   T a[2][TM][TK + 1];
   T b[2][TN][TK + 1];
 };
+// Rows of the output tile transposed through LDS per pass (write_rows).
+template <int TM, int TN> struct OutPass {
+  static constexpr int ROWS = TM * TN >= 128 * 128 ? TM / 2 : TM;
+};
 template <int TM, int TN> struct Lds<1, TM, TN> {
   static constexpr int TK = 16, LD = TK + 4;
   alignas(16) float a[2][TM][LD];
   alignas(16) float b[2][TN][LD];
-  // the finished tile is transposed through this storage (TM x (TN + 8))
-  float spare[TM * (TN + 8) > 2 * (TM + TN) * LD ? TM * (TN + 8) - 2 * (TM + TN) * LD : 1];
+  // the finished tile is transposed through this storage (ROWS x (TN + 8))
+  static constexpr int O = OutPass<TM, TN>::ROWS * (TN + 8);
+  float spare[O > 2 * (TM + TN) * LD ? O - 2 * (TM + TN) * LD : 1];
 };
 template <int TM, int TN> struct Lds<2, TM, TN> {
   static constexpr int TK = 16, LD = TK + 8;
@@ -134,10 +150,12 @@ template <int MODE, int TM, int TN>
 struct Stage {
   typedef typename Cfg<MODE>::T T;
   static constexpr int TK = Cfg<MODE>::TK;
+  static constexpr int NTH = Geo<TM, TN>::NT;
   static constexpr int RA = TM * TK / NTH / 4;  // runs per thread, op(A)
   static constexpr int RB = TN * TK / NTH / 4;  // and op(B)
   static constexpr int GA = NTH / TM, GB = NTH / TN;
-  T ra[4 * RA], rb[4 * RB];
+  static_assert(RA >= 1 && RB >= 1, "fewer than one run of four k per thread");
+  static constexpr int NA = 4 * RA, NB = 4 * RB;  // staged elements per thread
   gptr<T> pa[RA];
   gptr<T> pb[RB];
   int ia[RA];
@@ -222,8 +240,9 @@ struct Stage {
     }
   }
 
-  // Fetch the K-chunk starting at k0 of the current contribution.
-  __device__ __forceinline__ void load(int k0, int tid) {
+  // Fetch the K-chunk starting at k0 of the current contribution into the
+  // thread's staging registers ra (op(A)) and rb (op(B)).
+  __device__ __forceinline__ void load(int k0, int tid, T* ra, T* rb) const {
     const bool ta = flags & GC_TRANS_A, tb = flags & GC_TRANS_B, aid = flags & GC_A_IDENTITY;
     if (aid) {
 #pragma unroll
@@ -257,8 +276,11 @@ struct Stage {
     }
   }
 
-  __device__ __forceinline__ void store(Lds<MODE, TM, TN>& s, int buf, bool ta, bool tb, int tid) const {
-    const bool arow = ta && !(flags & GC_A_IDENTITY);
+  // Write staged registers of a chunk whose contribution had flags fl.
+  __device__ __forceinline__ static void store(Lds<MODE, TM, TN>& s, int buf, int fl, int tid, const T* ra,
+                                               const T* rb) {
+    const bool ta = fl & GC_TRANS_A, tb = fl & GC_TRANS_B;
+    const bool arow = ta && !(fl & GC_A_IDENTITY);
 #pragma unroll
     for (int q = 0; q < RA; ++q) {
       const int run = tid + q * NTH;
@@ -440,16 +462,7 @@ template <class TOut, int MODE, int TM, int TN, int BM, int BN>
 __device__ __forceinline__ void write_rows(const Acc<MODE, BM, BN>& acc, float* O, const Bases& bo, const GJob& J,
                                           const TileMap<TM, TN>& m, int fold, int wm, int wn, int lane, int tid) {
   typedef Acc<MODE, BM, BN> A;
-  constexpr int MB = Cfg<MODE>::MB, LDO = TN + 8;
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < BM; ++a)
-#pragma unroll
-    for (int b = 0; b < BN; ++b)
-#pragma unroll
-      for (int r = 0; r < A::R; ++r)
-        O[(wm + MB * a + A::row(lane, r)) * LDO + wn + MB * b + A::col(lane, r)] = acc.c[a][b][r];
-  __syncthreads();
+  constexpr int MB = Cfg<MODE>::MB, LDO = TN + 8, NT = Geo<TM, TN>::NT, PR = OutPass<TM, TN>::ROWS;
   typedef float floatx4 __attribute__((ext_vector_type(4)));
   const int c4 = 4 * (tid % (TN / 4));
   const int j0 = m.cj[c4], v0 = m.cv[c4];
@@ -458,24 +471,39 @@ __device__ __forceinline__ void write_rows(const Acc<MODE, BM, BN>& acc, float* 
   TOut* const C = reinterpret_cast<TOut*>(bo.p[J.baseC]) + J.offC;
   const bool accumulate = J.flags & GJ_ACCUMULATE;
 #pragma unroll
-  for (int p = 0; p < TM * TN / 4 / NTH; ++p) {
-    const int row = tid / (TN / 4) + p * (NTH / (TN / 4));
-    const int ii = m.ri[row];
-    if (ii < 0) continue;
-    const floatx4 v = *reinterpret_cast<const floatx4*>(&O[row * LDO + c4]);
-    if (run) {
-      const int vb = fold == 2 ? m.rv[row] : v0;
-      TOut* q = C + long(vb) * sc + long(ii) * J.ldc + j0;
-      if (accumulate) {
+  for (int pass = 0; pass < TM / PR; ++pass) {
+    __syncthreads();
+    if (wm >= pass * PR && wm < (pass + 1) * PR) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) q[e] = TOut(q[e] + TOut(v[e]));
+      for (int a = 0; a < BM; ++a)
+#pragma unroll
+        for (int b = 0; b < BN; ++b)
+#pragma unroll
+          for (int r = 0; r < A::R; ++r)
+            O[(wm - pass * PR + MB * a + A::row(lane, r)) * LDO + wn + MB * b + A::col(lane, r)] = acc.c[a][b][r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < PR * TN / 4 / NT; ++p) {
+      const int lr = tid / (TN / 4) + p * (NT / (TN / 4));
+      const int row = pass * PR + lr;
+      const int ii = m.ri[row];
+      if (ii < 0) continue;
+      const floatx4 v = *reinterpret_cast<const floatx4*>(&O[lr * LDO + c4]);
+      if (run) {
+        const int vb = fold == 2 ? m.rv[row] : v0;
+        TOut* q = C + long(vb) * sc + long(ii) * J.ldc + j0;
+        if (accumulate) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) q[e] = TOut(q[e] + TOut(v[e]));
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) q[e] = TOut(v[e]);
+        }
       } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) q[e] = TOut(v[e]);
+        for (int e = 0; e < 4; ++e) put_out<TOut, TM, TN>(bo, J, m, fold, row, c4 + e, v[e]);
       }
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) put_out<TOut, TM, TN>(bo, J, m, fold, row, c4 + e, v[e]);
     }
   }
 }
@@ -524,11 +552,12 @@ __device__ __forceinline__ void do_tile(int ti, const GTile* __restrict__ tiles,
                                         const GSeg* __restrict__ segs, int nslots,
                                         typename Cfg<MODE>::T* __restrict__ partial, const Bases& bout, int fold,
                                         int batch, int out_f64, Lds<MODE, TM, TN>& s, TileMap<TM, TN>& m,
-                                        Bases& sb, const Bases* bs_copy) {
+                                        Bases& sb, const Bases* bs_copy, const Bases* __restrict__ ib) {
   constexpr int TK = Cfg<MODE>::TK, MB = Cfg<MODE>::MB;
-  constexpr int BM = TM / 2 / MB, BN = TN / 2 / MB;
+  typedef Geo<TM, TN> G;
+  constexpr int BM = G::WTM / MB, BN = G::WTN / MB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * (TM / 2), wn = (wave & 1) * (TN / 2);
+  const int wm = (wave / G::WN) * G::WTM, wn = (wave % G::WN) * G::WTN;
   const GTile t = tiles[ti];
   const GJob J = jobs[t.job];
   int c0 = J.c0, c1 = J.c1, slot = -1;
@@ -542,40 +571,54 @@ __device__ __forceinline__ void do_tile(int ti, const GTile* __restrict__ tiles,
   // built, so that its latency overlaps theirs and the barrier
   GContrib cfirst{};
   if (c0 < c1) cfirst = con[c0];
-  // the base table (kernel argument) is copied to LDS once per workgroup,
-  // after the descriptor loads above are under way
-  if (bs_copy && tid < kMaxBases) {
-    sb.p[tid] = bs_copy->p[tid];
-    sb.stride[tid] = bs_copy->stride[tid];
+  // the base table (kernel argument, or the job's instance table of a
+  // grouped launch) is copied to LDS, after the descriptor loads above are
+  // under way; a grouped launch also writes through it
+  const Bases* bsrc = ib ? ib + J.inst : bs_copy;
+  if (bsrc && tid < kMaxBases) {
+    sb.p[tid] = bsrc->p[tid];
+    sb.stride[tid] = bsrc->stride[tid];
   }
+  const Bases& bo = ib ? sb : bout;
   tile_maps<TM, TN>(m, J, t.tm, t.tn, fold, batch, tid, gather);
   __syncthreads();
   Acc<MODE, BM, BN> acc;
   acc.zero();
   if (c0 < c1) {
-    Stage<MODE, TM, TN> st;
-    int ci = c0, k0 = 0, buf = 0;
+    // The pointer state follows the fetch cursor: chunk q+1 is fetched into
+    // the staging registers while chunk q is multiplied out of LDS.  (A
+    // second set of registers, two chunks in flight, measured no faster on
+    // the FP32 accumulation stage and cost one wave per SIMD.)
+    typedef Stage<MODE, TM, TN> St;
+    typedef typename Cfg<MODE>::T T;
+    St st;
+    T ra[St::NA], rb[St::NB];
+    int kv = 0, fl = 0;     // valid k of the staged chunk (0: none) and its flags
+    int fci = c0, fk = 0;   // next chunk to fetch
     st.begin(cfirst, sb, m, tid, J.flags);
-    st.load(0, tid);
-    for (;;) {
-      const int ck = st.ck, fl = st.flags;
-      st.store(s, buf, fl & GC_TRANS_A, fl & GC_TRANS_B, tid);
+    auto fetch = [&]() {
+      if (fci >= c1) {
+        kv = 0;
+        return;
+      }
+      st.load(fk, tid, ra, rb);
+      kv = st.ck - fk < TK ? st.ck - fk : TK;
+      fl = st.flags;
+      fk += TK;
+      if (fk >= st.ck) {
+        ++fci;
+        fk = 0;
+        if (fci < c1) st.begin(con[fci], sb, m, tid, J.flags);
+      }
+    };
+    fetch();
+    int buf = 0;
+    while (kv > 0) {
+      St::store(s, buf, fl, tid, ra, rb);
       __syncthreads();
-      const int kv = ck - k0 < TK ? ck - k0 : TK;
-      int nci = ci, nk0 = k0 + TK;
-      if (nk0 >= ck) {
-        ++nci;
-        nk0 = 0;
-      }
-      const bool more = nci < c1;
-      if (more) {
-        if (nci != ci) st.begin(con[nci], sb, m, tid, J.flags);
-        st.load(nk0, tid);
-      }
-      mma<TM, TN, BM, BN>(acc, s, buf, kv, wm, wn, lane);
-      if (!more) break;
-      ci = nci;
-      k0 = nk0;
+      const int kq = kv;
+      fetch();
+      mma<TM, TN, BM, BN>(acc, s, buf, kq, wm, wn, lane);
       buf ^= 1;
     }
   }
@@ -583,12 +626,13 @@ __device__ __forceinline__ void do_tile(int ti, const GTile* __restrict__ tiles,
     const long entry = fold == 0 ? long(blockIdx.y) : 0;
     write_partial<MODE, TN>(acc, partial + (entry * nslots + slot) * long(TM * TN), wm, wn, lane);
   } else if constexpr (MODE == 0) {
-    write<MODE, TM, TN>(acc, bout, J, m, fold, wm, wn, lane, true);
+    write<MODE, TM, TN>(acc, bo, J, m, fold, wm, wn, lane, true);
   } else {
-    static_assert(sizeof(Lds<MODE, TM, TN>) >= sizeof(float) * TM * (TN + 8), "output tile does not fit");
+    static_assert(sizeof(Lds<MODE, TM, TN>) >= sizeof(float) * OutPass<TM, TN>::ROWS * (TN + 8),
+                  "output pass does not fit");
     float* O = reinterpret_cast<float*>(&s);
-    if (out_f64) write_rows<double, MODE, TM, TN>(acc, O, bout, J, m, fold, wm, wn, lane, tid);
-    else write_rows<float, MODE, TM, TN>(acc, O, bout, J, m, fold, wm, wn, lane, tid);
+    if (out_f64) write_rows<double, MODE, TM, TN>(acc, O, bo, J, m, fold, wm, wn, lane, tid);
+    else write_rows<float, MODE, TM, TN>(acc, O, bo, J, m, fold, wm, wn, lane, tid);
   }
 }
 
@@ -603,10 +647,10 @@ template <int MODE> struct Persist {
 // ROLE only tags the instantiation (0: products into a workspace, 1: the
 // accumulation into the result), so that profiles separate the two stages.
 template <int MODE, int ROLE, int TM, int TN>
-__global__ __launch_bounds__(NTH, Persist<MODE>::waves) void ggemm_mfma_kernel(
+__global__ __launch_bounds__((Geo<TM, TN>::NT), Persist<MODE>::waves) void ggemm_mfma_kernel(
     const GTile* __restrict__ tiles, int ntiles, const GJob* __restrict__ jobs, const GContrib* __restrict__ con,
     const int* __restrict__ gather, const GSeg* __restrict__ segs, int nslots, typename Cfg<MODE>::T* __restrict__ partial, Bases bs, Bases bout,
-    int fold, int batch, int out_f64) {
+    int fold, int batch, int out_f64, const Bases* __restrict__ ib) {
   __shared__ Lds<MODE, TM, TN> s;
   __shared__ TileMap<TM, TN> m;
   __shared__ Bases sb;  // base table indexed per contribution (LDS, not a private copy)
@@ -623,18 +667,18 @@ __global__ __launch_bounds__(NTH, Persist<MODE>::waves) void ggemm_mfma_kernel(
   }
   if constexpr (Persist<MODE>::on) {
     const int tid = threadIdx.x;
-    if (tid < kMaxBases) {
+    if (!ib && tid < kMaxBases) {
       sb.p[tid] = bs.p[tid];
       sb.stride[tid] = bs.stride[tid];
     }
     for (int ti = bx; ti < ntiles; ti += gridDim.x) {
-      __syncthreads();  // the previous tile is done with the maps
+      __syncthreads();  // the previous tile is done with the maps and bases
       do_tile<MODE, TM, TN>(ti, tiles, jobs, con, gather, segs, nslots, partial, bout, fold, batch, out_f64, s, m,
-                            sb, nullptr);
+                            sb, nullptr, ib);
     }
   } else {
     do_tile<MODE, TM, TN>(bx, tiles, jobs, con, gather, segs, nslots, partial, bout, fold, batch, out_f64, s,
-                          m, sb, &bs);
+                          m, sb, &bs, ib);
   }
 }
 
@@ -643,11 +687,13 @@ __global__ __launch_bounds__(NTH, Persist<MODE>::waves) void ggemm_mfma_kernel(
 template <class PT, int TM, int TN>
 __global__ __launch_bounds__(NTH) void reduce_partials_kernel(const GRed* __restrict__ red,
                                                               const GJob* __restrict__ jobs,
-                                                              const PT* __restrict__ partial, int nslots, Bases bout,
-                                                              int fold, int batch, int out_f64) {
+                                                              const PT* __restrict__ partial, int nslots, Bases bout0,
+                                                              int fold, int batch, int out_f64,
+                                                              const Bases* __restrict__ ib) {
   __shared__ TileMap<TM, TN> m;
   const GRed r = red[blockIdx.x];
   const GJob J = jobs[r.job];
+  const Bases& bout = ib ? ib[J.inst] : bout0;
   const int tid = threadIdx.x;
   tile_maps<TM, TN>(m, J, r.tm, r.tn, fold, batch, tid, nullptr);
   __syncthreads();
@@ -663,8 +709,9 @@ __global__ __launch_bounds__(NTH) void reduce_partials_kernel(const GRed* __rest
   }
 }
 
-__global__ void diag_add_f32_kernel(const DiagAdd* __restrict__ d, Bases bs) {
+__global__ void diag_add_f32_kernel(const DiagAdd* __restrict__ d, Bases bs0, const Bases* __restrict__ ib) {
   const DiagAdd x = d[blockIdx.x];
+  const Bases& bs = ib ? ib[x.inst] : bs0;
   float* o = reinterpret_cast<float*>(bs.p[x.base]) + x.off + long(blockIdx.y) * bs.stride[x.base];
   for (int i = threadIdx.x; i < x.dim; i += blockDim.x) o[long(i) * (x.dim + 1)] += float(x.c);
 }
@@ -674,50 +721,61 @@ __global__ void convert_f64_f32_kernel(const double* __restrict__ in, float* __r
     out[e] = float(in[e]);
 }
 
+__global__ void convert_list_kernel(const ConvJob* __restrict__ jobs) {
+  const ConvJob j = jobs[blockIdx.y];
+  for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < j.n; e += long(gridDim.x) * blockDim.x)
+    j.out[e] = float(j.in[e]);
+}
+
 template <int MODE, int TM, int TN>
 void launch_shape(int role, dim3 grid, hipStream_t s, const GTile* tiles, int ntiles, const GJob* jobs,
                   const GContrib* con, const int* gather, const GSeg* segs, int nslots, void* partial, const Bases& b, const Bases& bout, int fold, int batch,
-                  int of) {
+                  int of, const Bases* ib) {
   typedef typename Cfg<MODE>::T T;
   T* P = static_cast<T*>(partial);
+  constexpr int NT = Geo<TM, TN>::NT;
   if (role == 0)
-    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 0, TM, TN>), grid, dim3(NTH), 0, s, tiles, ntiles, jobs, con,
-                       gather, segs, nslots, P, b, bout, fold, batch, of);
+    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 0, TM, TN>), grid, dim3(NT), 0, s, tiles, ntiles, jobs, con,
+                       gather, segs, nslots, P, b, bout, fold, batch, of, ib);
   else
-    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 1, TM, TN>), grid, dim3(NTH), 0, s, tiles, ntiles, jobs, con,
-                       gather, segs, nslots, P, b, bout, fold, batch, of);
+    hipLaunchKernelGGL((ggemm_mfma_kernel<MODE, 1, TM, TN>), grid, dim3(NT), 0, s, tiles, ntiles, jobs, con,
+                       gather, segs, nslots, P, b, bout, fold, batch, of, ib);
 }
 
 template <int MODE>
 void launch_mode(int shape, int role, dim3 grid, hipStream_t s, const GTile* tiles, int ntiles, const GJob* jobs,
                  const GContrib* con, const int* gather, const GSeg* segs, int nslots, void* partial, const Bases& b, const Bases& bout,
-                 int fold, int batch, int of) {
-  if (shape == TILE_128x64)
+                 int fold, int batch, int of, const Bases* ib) {
+  if (MODE != 0 && shape == TILE_128x128)
+    launch_shape<MODE, 128, 128>(role, grid, s, tiles, ntiles, jobs, con, gather, segs, nslots, partial, b, bout,
+                                 fold, batch, of, ib);
+  else if (shape == TILE_128x64)
     launch_shape<MODE, 128, 64>(role, grid, s, tiles, ntiles, jobs, con, gather, segs, nslots, partial, b, bout, fold,
-                                batch, of);
+                                batch, of, ib);
   else if (shape == TILE_64x128)
     launch_shape<MODE, 64, 128>(role, grid, s, tiles, ntiles, jobs, con, gather, segs, nslots, partial, b, bout, fold,
-                                batch, of);
+                                batch, of, ib);
   else
     launch_shape<MODE, 64, 64>(role, grid, s, tiles, ntiles, jobs, con, gather, segs, nslots, partial, b, bout, fold,
-                               batch, of);
+                               batch, of, ib);
 }
 
 template <class PT, int TM, int TN>
 void launch_reduce(dim3 grid, hipStream_t s, const GRed* red, const GJob* jobs, const void* partial, int nslots,
-                   const Bases& bout, int fold, int batch, int of) {
+                   const Bases& bout, int fold, int batch, int of, const Bases* ib) {
   hipLaunchKernelGGL((reduce_partials_kernel<PT, TM, TN>), grid, dim3(NTH), 0, s, red, jobs,
-                     static_cast<const PT*>(partial), nslots, bout, fold, batch, of);
+                     static_cast<const PT*>(partial), nslots, bout, fold, batch, of, ib);
 }
 
 }  // namespace
 
-int tile_rows(int shape) { return shape == TILE_128x64 ? 128 : 64; }
-int tile_cols(int shape) { return shape == TILE_64x128 ? 128 : 64; }
+int tile_rows(int shape) { return shape == TILE_128x64 || shape == TILE_128x128 ? 128 : 64; }
+int tile_cols(int shape) { return shape == TILE_64x128 || shape == TILE_128x128 ? 128 : 64; }
 
 void launch_grouped_gemm(int prec, bool out_f64, int role, int shape, const GTile* tiles, int ntiles,
                          const GJob* jobs, const GContrib* con, const int* gather, const GSeg* segs, int nslots,
-                         void* partial, const Bases& b, const Bases& bout, int fold, int batch, hipStream_t s) {
+                         void* partial, const Bases& b, const Bases& bout, int fold, int batch, hipStream_t s,
+                         const Bases* ib) {
   if (ntiles <= 0 || batch <= 0) return;
   // FP64 runs persistent workgroups (at most 16 per CU of the 256, a few
   // rounds of the resident capacity); the others one workgroup per tile
@@ -728,36 +786,46 @@ void launch_grouped_gemm(int prec, bool out_f64, int role, int shape, const GTil
   const int of = out_f64 ? 1 : 0;
   if (prec == 0)
     launch_mode<0>(shape, role, grid, s, tiles, ntiles, jobs, con, gather, segs, nslots, partial, b, bout, fold, batch,
-                   1);
+                   1, ib);
   else if (prec == 1)
     launch_mode<1>(shape, role, grid, s, tiles, ntiles, jobs, con, gather, segs, nslots, partial, b, bout, fold, batch,
-                   of);
+                   of, ib);
   else
     launch_mode<2>(shape, role, grid, s, tiles, ntiles, jobs, con, gather, segs, nslots, partial, b, bout, fold, batch,
-                   of);
+                   of, ib);
 }
 
 void launch_reduce_partials(int prec, bool out_f64, int shape, const GRed* red, int nred, const GJob* jobs,
-                            int nslots, const void* partial, const Bases& bout, int fold, int batch, hipStream_t s) {
+                            int nslots, const void* partial, const Bases& bout, int fold, int batch, hipStream_t s,
+                            const Bases* ib) {
   if (nred <= 0 || batch <= 0) return;
   const dim3 grid(nred, fold == 0 ? batch : 1);
   const int of = (prec == 0 || out_f64) ? 1 : 0;
   if (prec == 0) {
-    if (shape == TILE_128x64) launch_reduce<double, 128, 64>(grid, s, red, jobs, partial, nslots, bout, fold, batch, 1);
+    if (shape == TILE_128x64) launch_reduce<double, 128, 64>(grid, s, red, jobs, partial, nslots, bout, fold, batch, 1, ib);
     else if (shape == TILE_64x128)
-      launch_reduce<double, 64, 128>(grid, s, red, jobs, partial, nslots, bout, fold, batch, 1);
-    else launch_reduce<double, 64, 64>(grid, s, red, jobs, partial, nslots, bout, fold, batch, 1);
+      launch_reduce<double, 64, 128>(grid, s, red, jobs, partial, nslots, bout, fold, batch, 1, ib);
+    else launch_reduce<double, 64, 64>(grid, s, red, jobs, partial, nslots, bout, fold, batch, 1, ib);
   } else {
-    if (shape == TILE_128x64) launch_reduce<float, 128, 64>(grid, s, red, jobs, partial, nslots, bout, fold, batch, of);
+    if (shape == TILE_128x128)
+      launch_reduce<float, 128, 128>(grid, s, red, jobs, partial, nslots, bout, fold, batch, of, ib);
+    else if (shape == TILE_128x64) launch_reduce<float, 128, 64>(grid, s, red, jobs, partial, nslots, bout, fold, batch, of, ib);
     else if (shape == TILE_64x128)
-      launch_reduce<float, 64, 128>(grid, s, red, jobs, partial, nslots, bout, fold, batch, of);
-    else launch_reduce<float, 64, 64>(grid, s, red, jobs, partial, nslots, bout, fold, batch, of);
+      launch_reduce<float, 64, 128>(grid, s, red, jobs, partial, nslots, bout, fold, batch, of, ib);
+    else launch_reduce<float, 64, 64>(grid, s, red, jobs, partial, nslots, bout, fold, batch, of, ib);
   }
 }
 
-void launch_diag_add_f32(const DiagAdd* d, int n, const Bases& b, int batch, hipStream_t s) {
+void launch_diag_add_f32(const DiagAdd* d, int n, const Bases& b, int batch, hipStream_t s, const Bases* ib) {
   if (n <= 0 || batch <= 0) return;
-  hipLaunchKernelGGL(diag_add_f32_kernel, dim3(n, batch), dim3(256), 0, s, d, b);
+  hipLaunchKernelGGL(diag_add_f32_kernel, dim3(n, batch), dim3(256), 0, s, d, b, ib);
+}
+
+void launch_convert_list(const ConvJob* jobs, int njobs, long max_n, hipStream_t s) {
+  if (njobs <= 0 || max_n <= 0) return;
+  long blocks = (max_n + 255) / 256;
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(convert_list_kernel, dim3(unsigned(blocks), njobs), dim3(256), 0, s, jobs);
 }
 
 void launch_convert_f64_f32(const double* in, float* out, long n, hipStream_t s) {

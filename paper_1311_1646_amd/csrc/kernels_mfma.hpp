@@ -26,8 +26,9 @@ struct GSeg {
 struct GRed {
   int job, tm, tn, slot0, nseg, pad;
 };
-// Output tile shapes of the matrix-core kernel (rows x columns).
-enum : int { TILE_64x64 = 0, TILE_128x64 = 1, TILE_64x128 = 2 };
+// Output tile shapes of the matrix-core kernel (rows x columns).  128x128
+// (512-thread workgroups) exists for FP32 and BF16x3 operands only.
+enum : int { TILE_64x64 = 0, TILE_128x64 = 1, TILE_64x128 = 2, TILE_128x128 = 3 };
 int tile_rows(int shape);
 int tile_cols(int shape);
 
@@ -37,13 +38,25 @@ int tile_cols(int shape);
 // tiles of the operand type.
 // gather: entries of the jobs with a gathered operand (may be null when no
 // job has one).
+// ib: per-instance base tables of a grouped launch (GJob::inst selects one;
+// the outputs are written through it too), or null (b and bout for all).
 void launch_grouped_gemm(int prec, bool out_f64, int role, int shape, const GTile* tiles, int ntiles,
                          const GJob* jobs, const GContrib* con, const int* gather, const GSeg* segs, int nslots,
-                         void* partial, const Bases& b, const Bases& bout, int fold, int batch, hipStream_t s);
+                         void* partial, const Bases& b, const Bases& bout, int fold, int batch, hipStream_t s,
+                         const Bases* ib = nullptr);
 void launch_reduce_partials(int prec, bool out_f64, int shape, const GRed* red, int nred, const GJob* jobs,
-                            int nslots, const void* partial, const Bases& bout, int fold, int batch, hipStream_t s);
+                            int nslots, const void* partial, const Bases& bout, int fold, int batch, hipStream_t s,
+                            const Bases* ib = nullptr);
 
-void launch_diag_add_f32(const DiagAdd* d, int n, const Bases& b, int batch, hipStream_t s);
+void launch_diag_add_f32(const DiagAdd* d, int n, const Bases& b, int batch, hipStream_t s,
+                         const Bases* ib = nullptr);
 void launch_convert_f64_f32(const double* in, float* out, long n, hipStream_t s);
+// several FP64 -> FP32 conversions in one launch (grid.y = jobs)
+struct ConvJob {
+  const double* in;
+  float* out;
+  long n;
+};
+void launch_convert_list(const ConvJob* jobs, int njobs, long max_n, hipStream_t s);
 
 }  // namespace dmrg

@@ -94,7 +94,7 @@ def test_multi_tile_sigma(ppp12, prec, fp64_gemm, monkeypatch):
     ctx.close()
 
 
-@pytest.mark.parametrize("shape", ["64x64", "128x64", "64x128"])
+@pytest.mark.parametrize("shape", ["64x64", "128x64", "64x128", "128x128"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_every_tile_shape(ppp12, prec, shape, monkeypatch):
     # each matrix-core tile shape (where the batch folding allows it) on
