@@ -268,26 +268,41 @@ int dmrg_sweep_ground(dmrg_ctx* ctx, const dmrg_sweep_params* p, double* energy,
 
 typedef struct {
   int max_iter;        /* Davidson iterations (one forward+backward sweep each) */
-  int max_space;       /* N: maximum number of trial vectors (<= 64; 0: max(3n, n+16)) */
+  int max_space;       /* N: maximum number of trial vectors (<= 64); 0: 64,
+                          lowered to what fits in 60% of the free device
+                          memory as hipMemGetInfo reports it (at least
+                          2n + 2; memory cached by the allocator behind
+                          dmrg_allocator counts as used, so such a caller
+                          releases its cache first, as the Python binding
+                          does); a full space restarts from the lowest
+                          max(n + max(2, n/2), N/2) Ritz vectors; the value
+                          used is in dmrg_stats.tda_space                     */
   double tol;          /* convergence: max_mu sum_i |r_i^mu|^2 < tol             */
   int seed;            /* random initial trial vectors                           */
   int prec;            /* contraction precision                                  */
   int verbose;
-  int polish;          /* BF16X3 runs only: 0 (default) finishes with FP32
+  int polish;          /* FP32 and BF16X3 runs: 0 (default) finishes with FP64
                           iterations once the residual reaches the estimated
-                          floor of the split products, L (2^-16 E_0)^2 x 4, or
-                          tol, or stalls near that floor (at least two FP32
-                          iterations; convergence is judged in FP32); -1 keeps
-                          BF16X3 to the end                                   */
+                          floor of the run's contractions, 4 L (eps E_0)^2
+                          with eps = 2^-16 (BF16X3) or 2^-19 (FP32), or tol,
+                          or stalls near that floor (at least two FP64
+                          iterations; convergence is judged in FP64); -1 keeps
+                          the run's precision to the end                      */
+  int guess;           /* initial trial vectors: 0 (default) unit vectors on the
+                          n lowest diagonal elements of the middle site's
+                          effective Hamiltonian (eq. error's diagonal); 1 seeded
+                          random components at every site (as in Fig.
+                          alg:dmrgtda; the Davidson then spends tens of
+                          iterations on a plateau)                            */
 } dmrg_davidson_params;
 
 /* DMRG-TDA roots by the sweep Davidson algorithm (Sec. III, Fig. alg:dmrgtda)
  * on the current MPS (imported or from dmrg_sweep_ground; build_ops first).
- * A BF16X3 run is polished by FP32 iterations (see dmrg_davidson_params):
- * the split products carry about 2^-17 relative error per product, which
- * enters the reduced matrices of eqs. hleft2 / sleft2 to first order, while
- * the FP32 contractions meet the 1e-5 Eh excitation tolerance;
- * stats.tda_polish_iters reports how many iterations ran in FP32.
+ * FP32 and BF16X3 runs are polished by FP64 iterations (see
+ * dmrg_davidson_params): the contraction error enters the reduced matrices
+ * of eqs. hleft2 / sleft2, hence the excitation energies, to first order and
+ * in proportion to |E_0|; stats.tda_polish_iters reports how many iterations
+ * ran in FP64.
  * Outputs (host, nroots each): omega = E_mu - E_0 with E_0 = <Psi0|H|Psi0>,
  * e_total = E_mu, resid2 = sum over sites of |r_i^mu|^2 of the last
  * iteration; iters = Davidson iterations used.  NOT_CONVERGED fills the
@@ -329,6 +344,14 @@ int dmrg_group_stats(dmrg_group* g, double* flops, double* ms, int* launches, in
 const char* dmrg_group_last_error(const dmrg_group* g);
 int dmrg_group_destroy(dmrg_group* g);
 
+/* Test support: the reduced matrices H_R and S_R (Sec. III B, eqs. hleft2
+ * and sleft2, summed over sites) of the last forward sweep of the last
+ * dmrg_tda_roots, l x l row-major FP64 on the host.  With NULL HR / SR only
+ * l is returned.  Errors: STATE before a TDA run. */
+int dmrg_tda_reduced(dmrg_ctx* ctx, int* l, double* HR, double* SR);
+
+#define DMRG_TDA_HIST 256 /* iterations kept in dmrg_stats.tda_r2_hist */
+
 typedef struct {
   double sigma_flops;      /* algorithmic flops of the last dmrg_sigma call        */
   double sigma_ms;         /* device time of the last dmrg_sigma call              */
@@ -353,16 +376,21 @@ typedef struct {
   double sigma_workspace_bytes; /* device workspace of the last zeroth-order
                               dmrg_sigma (what dmrg_sigma_noalloc needs from its
                               scratch for the same shape)                           */
-  int tda_polish_iters;    /* iterations of the last dmrg_tda_roots run in FP32
+  int tda_polish_iters;    /* iterations of the last dmrg_tda_roots run in FP64
                               polish (0: none)                                      */
   int tda_hist_len;        /* entries of tda_r2_hist                                */
-  double tda_r2_hist[64];  /* max over roots of sum_i |r_i^mu|^2 per iteration of
-                              the last dmrg_tda_roots (first 64 iterations)         */
+  double tda_r2_hist[DMRG_TDA_HIST]; /* max over roots of sum_i |r_i^mu|^2 per
+                              iteration of the last dmrg_tda_roots (first
+                              DMRG_TDA_HIST iterations)                             */
   double tda_total_ms;     /* wall time of the last dmrg_tda_roots, including the
                               initial sweeps                                        */
+  int tda_space;           /* maximum trial space N of the last dmrg_tda_roots      */
 } dmrg_stats;
 
 int dmrg_get_stats(dmrg_ctx* ctx, dmrg_stats* out);
+/* sizeof(dmrg_stats) as compiled into the library, so that a binding can
+ * check its own copy of the layout (host only, needs no context). */
+size_t dmrg_stats_size(void);
 
 /* Test support (host only, L <= 5): contract the channel site operators into
  * the dense 4^L x 4^L Fock-space Hamiltonian, basis index sum_i n_i 4^i.

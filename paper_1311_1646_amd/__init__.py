@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libdmrg.so")
 FP64, FP32, BF16X3 = 0, 1, 2
 SIGMA_ZEROTH_1SITE, SIGMA_ZEROTH_2SITE, SIGMA_TDA_FULL, SIGMA_TDA_DH_LEFT = 0, 1, 2, 3
 ZEROTH, FIRST = 0, 1
+TDA_HIST = 256  # DMRG_TDA_HIST
 DIR_LEFT, DIR_RIGHT = 0, 1
 
 _ERRORS = {
@@ -57,7 +58,8 @@ class Stats(ctypes.Structure):
         ("tda_iters", ctypes.c_int), ("sigma_main_launches", ctypes.c_int), ("tda_sigma_ms", ctypes.c_double),
         ("plan_ms", ctypes.c_double), ("sigma_workspace_bytes", ctypes.c_double),
         ("tda_polish_iters", ctypes.c_int), ("tda_hist_len", ctypes.c_int),
-        ("tda_r2_hist", ctypes.c_double * 64), ("tda_total_ms", ctypes.c_double)]
+        ("tda_r2_hist", ctypes.c_double * TDA_HIST), ("tda_total_ms", ctypes.c_double),
+        ("tda_space", ctypes.c_int)]
 
 
 class SweepParams(ctypes.Structure):
@@ -67,7 +69,7 @@ class SweepParams(ctypes.Structure):
 
 class DavidsonParams(ctypes.Structure):
     _fields_ = [("max_iter", _I), ("max_space", _I), ("tol", _D), ("seed", _I), ("prec", _I),
-                ("verbose", _I), ("polish", _I)]
+                ("verbose", _I), ("polish", _I), ("guess", _I)]
 
 
 def _sig(name, *args):
@@ -95,6 +97,12 @@ _renorm = _sig("dmrg_renormalize", _P, _I, _I, _I, _I, _P, _Z, _I)
 _sweep = _sig("dmrg_sweep_ground", _P, ctypes.POINTER(SweepParams), _DP, _DP)
 _tda = _sig("dmrg_tda_roots", _P, _I, ctypes.POINTER(DavidsonParams), _DP, _DP, _DP, _IP)
 _stats = _sig("dmrg_get_stats", _P, ctypes.POINTER(Stats))
+_stats_size = _lib.dmrg_stats_size
+_stats_size.argtypes = []
+_stats_size.restype = ctypes.c_size_t
+if _stats_size() != ctypes.sizeof(Stats):
+    raise ImportError(f"dmrg_stats layout mismatch: library {_stats_size()} bytes, binding {ctypes.sizeof(Stats)}")
+_tda_reduced = _sig("dmrg_tda_reduced", _P, _IP, _DP, _DP)
 _debug_dense = _sig("dmrg_debug_mpo_dense", _P, _I, _I, _DP)
 _group_create = _sig("dmrg_group_create", _P, _I, _IP, _I, _I, ctypes.POINTER(_P))
 _group_sigma = _sig("dmrg_group_sigma", _P, _P, _P, _SP, _I)
@@ -326,22 +334,41 @@ class Context:
         dw = ctypes.c_double()
         rc = _sweep(self._h, ctypes.byref(p), ctypes.byref(e), ctypes.byref(dw))
         self._sizes = {}
-        if rc not in (0, -3):
-            self._check(rc)
-        return e.value, dw.value, rc == 0
+        self._check(rc)
+        return e.value, dw.value, True
 
-    def tda_roots(self, nroots, max_iter=60, max_space=0, tol=1e-9, seed=7, prec=FP64, verbose=0, polish=True):
-        """DMRG-TDA roots (see dmrg_tda_roots); polish: a BF16X3 run ends with
-        FP32 iterations (stats()["tda_polish_iters"] says how many)."""
-        p = DavidsonParams(max_iter, max_space, tol, seed, prec, verbose, 0 if polish else -1)
+    def tda_roots(self, nroots, max_iter=60, max_space=0, tol=1e-9, seed=7, prec=FP64, verbose=0, polish=True,
+                  guess="diag"):
+        """DMRG-TDA roots (see dmrg_tda_roots); polish: an FP32 or BF16X3 run
+        ends with FP64 iterations (stats()["tda_polish_iters"] says how many); guess:
+        "diag" (lowest diagonal elements at the middle site) or "random"."""
+        if guess not in ("diag", "random"):
+            raise ValueError("guess must be 'diag' or 'random'")
+        p = DavidsonParams(max_iter, max_space, tol, seed, prec, verbose, 0 if polish else -1,
+                           0 if guess == "diag" else 1)
         om = np.zeros(nroots)
         et = np.zeros(nroots)
         r2 = np.zeros(nroots)
         it = ctypes.c_int()
+        if self._alloc is not None and max_space == 0:
+            # the library sizes the trial space from the device's free memory:
+            # hand torch's cached blocks back first so that they count as free
+            import torch
+            torch.cuda.synchronize(self.device)
+            torch.cuda.empty_cache()
         rc = _tda(self._h, nroots, ctypes.byref(p), _dp(om), _dp(et), _dp(r2), ctypes.byref(it))
         if rc not in (0, -3):
             self._check(rc)
         return om, et, r2, it.value, rc == 0
+
+    def tda_reduced(self):
+        """(H_R, S_R) of the last TDA forward sweep (l x l numpy arrays)."""
+        l = ctypes.c_int()
+        self._check(_tda_reduced(self._h, ctypes.byref(l), None, None))
+        HR = np.zeros((l.value, l.value))
+        SR = np.zeros((l.value, l.value))
+        self._check(_tda_reduced(self._h, ctypes.byref(l), _dp(HR), _dp(SR)))
+        return HR, SR
 
     def stats(self):
         s = Stats()

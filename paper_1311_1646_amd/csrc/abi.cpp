@@ -225,6 +225,7 @@ int dmrg_tda_roots(dmrg_ctx* ctx, int nroots, const dmrg_davidson_params* p, dou
     DMRG_REQUIRE(p, DMRG_ERR_INVALID_ARG, "null parameters");
     DMRG_REQUIRE(valid_prec(p->prec), DMRG_ERR_INVALID_ARG, "unsupported precision");
     DMRG_REQUIRE(p->polish == 0 || p->polish == -1, DMRG_ERR_INVALID_ARG, "polish must be 0 or -1");
+    DMRG_REQUIRE(p->guess == 0 || p->guess == 1, DMRG_ERR_INVALID_ARG, "guess must be 0 or 1");
     x.tda_roots(nroots, *p, omega, e_total, resid2, iters, &conv);
   });
   if (rc == DMRG_OK && !conv) {
@@ -234,12 +235,24 @@ int dmrg_tda_roots(dmrg_ctx* ctx, int nroots, const dmrg_davidson_params* p, dou
   return rc;
 }
 
+int dmrg_tda_reduced(dmrg_ctx* ctx, int* l, double* HR, double* SR) {
+  return guard(ctx, [&](dmrg::Ctx& x) {
+    DMRG_REQUIRE(l, DMRG_ERR_INVALID_ARG, "null l");
+    DMRG_REQUIRE(x.tda_l > 0, DMRG_ERR_STATE, "no TDA run yet");
+    *l = x.tda_l;
+    if (HR) std::memcpy(HR, x.tda_hr.data(), x.tda_hr.size() * sizeof(double));
+    if (SR) std::memcpy(SR, x.tda_sr.data(), x.tda_sr.size() * sizeof(double));
+  });
+}
+
 int dmrg_get_stats(dmrg_ctx* ctx, dmrg_stats* out) {
   return guard(ctx, [&](dmrg::Ctx& x) {
     DMRG_REQUIRE(out, DMRG_ERR_INVALID_ARG, "null stats");
     *out = x.stats;
   });
 }
+
+size_t dmrg_stats_size(void) { return sizeof(dmrg_stats); }
 
 int dmrg_debug_mpo_dense(dmrg_ctx* ctx, int wide_bond, int from_right, double* out) {
   return guard(ctx, [&](dmrg::Ctx& x) {

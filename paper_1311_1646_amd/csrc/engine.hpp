@@ -317,6 +317,10 @@ class Ctx {
   // dmrg_sigma with a TDA kind (DMRG_SIGMA_TDA_FULL / TDA_DH_LEFT) at site i
   void sigma_tda(int i, int kind, int nvec, const double* Cin, double* Sout, int prec);
   FirstOrderChain fo_chain[2];  // [0]: left sets, [1]: right sets
+  // reduced matrices H_R, S_R of the last dmrg_tda_roots iteration (host,
+  // row-major l x l)
+  std::vector<double> tda_hr, tda_sr;
+  int tda_l = 0;
   // dmrg_sigma_noalloc: the zeroth-order sigma with its workspaces carved from
   // the static scratch; any device allocation inside it is an error
   void sigma_noalloc(int i, int width, int nvec, const double* Cin, double* Sout, int prec);

@@ -168,7 +168,8 @@ void Ground::svd(const double* T, const SplitSpec& sp, SplitOut& o) {
   DMRG_HIP(hipMemcpy(info.data(), o.info.p, size_t(ns) * sizeof(rocblas_int), hipMemcpyDeviceToHost));
   o.s.assign(ns, {});
   for (int s = 0; s < ns; ++s) {
-    DMRG_REQUIRE(info[s] == 0, DMRG_ERR_NOT_CONVERGED, "SVD of a sector did not converge");
+    // empty sectors run no SVD and leave their info entry unwritten
+    DMRG_REQUIRE(o.kmax[s] == 0 || info[s] == 0, DMRG_ERR_NOT_CONVERGED, "SVD of a sector did not converge");
     o.s[s].assign(sv.begin() + o.s_off[s], sv.begin() + o.s_off[s] + o.kmax[s]);
   }
 }

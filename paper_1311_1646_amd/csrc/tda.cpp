@@ -19,6 +19,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
+#include <string>
 
 #include "engine.hpp"
 
@@ -248,10 +250,12 @@ class TdaRunner {
  public:
   TdaRunner(Ctx& x, int nroots, const dmrg_davidson_params& p) : x_(x), k_(x.gauge_kit()), n_(nroots), p_(p), prec_(p.prec) {
     L_ = x.L;
-    Nmax_ = p.max_space > 0 ? p.max_space : std::min(64, std::max(3 * n_, n_ + 16));
+    const long maxsize = k_.max_size;
+    guess_ = p.guess;
+    Nmax_ = p.max_space > 0 ? p.max_space : auto_space();
     DMRG_REQUIRE(Nmax_ <= 64, DMRG_ERR_INVALID_ARG, "max_space must be <= 64");
     DMRG_REQUIRE(n_ >= 1 && 2 * n_ <= Nmax_, DMRG_ERR_INVALID_ARG, "need 1 <= nroots and 2*nroots <= max_space");
-    const long maxsize = k_.max_size;
+    x.stats.tda_space = Nmax_;
     // per-site storage
     R1_.resize(L_);
     G_.resize(L_);
@@ -292,11 +296,14 @@ class TdaRunner {
   int n_, L_, Nmax_;
   dmrg_davidson_params p_;
   int prec_;  // contraction precision of sigma and renormalization
+  int guess_ = 0;  // initial trial vectors: 0 lowest diagonal at the middle site, 1 random at every site
   std::vector<DBuf> R1_, G_, Ct_, diag_;
   DBuf Cm_, Cprev_, Cb_, Sg_, S0_, Dl_, Wk_, R1r_, Gr_, bm_;
   DBuf HR_, SR_, alpha_, w_, rank_, negw_, ones_, tmpd_, part_, zscale_;
   OpSet FL_[2], FR_[2];
   double E0_ = 0;
+  int lcur_last_ = 0;  // size of the reduced matrices of the last forward sweep
+  int polish_from_ = 0, polish_to_ = -1;
   std::vector<double> hw_;  // host copy of Ritz values
 
   long size(int i) const { return k_.size[i]; }
@@ -320,6 +327,25 @@ class TdaRunner {
       if (sets[k].data.bytes < bytes) sets[k].data.alloc(&x_, bytes);
   }
   void backward(int l);
+  // default maximum space: 64 trial vectors, reduced so
+  // that the per-vector device memory (two first-order sets of the largest
+  // bond and their building blocks, three site vectors per site, nine work
+  // vectors) fits in 60% of the free device memory; at least 2n + 2
+  int auto_space() {
+    long mx = 1;
+    for (int b = 0; b <= L_; ++b) mx = std::max({mx, x_.opset_size(b, 0), x_.opset_size(b, 1)});
+    long sites = 0;
+    for (int i = 0; i < L_; ++i) sites += k_.size[i];
+    // sized for FP64 sets whenever the run may end in FP64 polish
+    const double esz = (prec_ != DMRG_FP64 && p_.polish != 0) ? 4 : 8;
+    const double per = 3.0 * double(mx) * esz + 8.0 * (3.0 * sites + 9.0 * k_.max_size);
+    size_t freeb = 0, total = 0;
+    int cap = 64;
+    if (hipMemGetInfo(&freeb, &total) == hipSuccess) cap = int(std::min(64.0, 0.6 * double(freeb) / per));
+    else (void)hipGetLastError();
+    const int want = 64;
+    return std::max(std::min(want, cap), std::min(64, 2 * n_ + 2));
+  }
 };
 
 void TdaRunner::q_c_project(int i, double* z, int nv) {
@@ -407,7 +433,23 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
       DMRG_HIP(hipGetLastError());
     } else {
       tmp.resize(size_t(n_) * S);
-      for (auto& v : tmp) v = rng.normal();
+      if (guess_ == 1) {
+        for (auto& v : tmp) v = rng.normal();
+      } else {
+        // unit vectors on the n lowest diagonal elements of the middle
+        // site's effective Hamiltonian, zero at the other sites
+        std::fill(tmp.begin(), tmp.end(), 0.0);
+        if (i == L_ / 2) {
+          std::vector<double> d(S);
+          DMRG_HIP(hipMemcpy(d.data(), diag_[i].p, size_t(S) * 8, hipMemcpyDeviceToHost));
+          std::vector<long> idx(S);
+          for (long e = 0; e < S; ++e) idx[e] = e;
+          const long k = std::min<long>(S, n_ + 1);
+          std::partial_sort(idx.begin(), idx.begin() + k, idx.end(), [&](long a, long b) { return d[a] < d[b]; });
+          // the lowest element is mostly the reference itself: skip it
+          for (int v = 0; v < n_; ++v) tmp[size_t(v) * S + idx[std::min<long>(v + 1, k - 1)]] = 1.0;
+        }
+      }
       DMRG_HIP(hipMemcpy(Wk, tmp.data(), tmp.size() * 8, hipMemcpyHostToDevice));
     }
     q_c_project(i, Wk, n_);
@@ -490,7 +532,8 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
   }
   for (int i = 0; i < L_; ++i) x_.diag(i, 1, diag_[i].as<double>());
   std::vector<double> r2;
-  // initial trial vectors: random Q^C-projected components at every site,
+  // initial trial vectors (unit vectors on the lowest diagonal elements of
+  // the middle site, or random components at every site), Q^C projected,
   // then the right-gauge objects and the first reduced matrices
   forward(0, 0, true, uint64_t(p_.seed) * 7919 + 1, r2);
   backward(n_);
@@ -501,16 +544,23 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
   std::vector<double> w(64), last_w(n_, 0.0);
   double tda_flops0 = 0;
   (void)tda_flops0;
-  // BF16x3 runs end with FP32 iterations, switched on near the residual
-  // floor of the split products: a relative error of ~2^-16 on sigma vectors
-  // of size ~|E0| at each of the L sites gives sum_i |r_i|^2 ~ L (2^-16 E0)^2
-  // (times 4 for margin); also when the residual meets tol, or stalls for
-  // four iterations within a factor 100 of that floor
-  const bool can_polish = prec_ == DMRG_BF16X3 && p_.polish == 0;
-  const double floor_est = 4.0 * L_ * std::pow(std::ldexp(1.0, -16) * E0_, 2);
+  // FP32 and BF16x3 runs end with FP64 iterations, switched on near the
+  // residual floor of their contractions: a relative error eps on sigma
+  // vectors of size ~|E0| at each of the L sites gives sum_i |r_i|^2 ~
+  // L (eps E0)^2, with eps = 2^-16 for the split products and 2^-19 for FP32
+  // (unit roundoff grown over sums of ~10^3 terms), times 4 for margin; also
+  // when the residual meets tol, or stalls for four iterations within a
+  // factor 100 of that floor.  The excitation energies are first order in
+  // the contraction error of H_R, so only FP64 iterations reach the 1e-5 Eh
+  // scale when |E0| is hundreds of Eh.
+  const bool can_polish = prec_ != DMRG_FP64 && p_.polish == 0;
+  polish_from_ = prec_;
+  polish_to_ = -1;
   bool polishing = false;
   int polish_iters = 0, stall = 0;
   double best = 1e300;
+  const double eps = prec_ == DMRG_BF16X3 ? std::ldexp(1.0, -16) : std::ldexp(1.0, -19);
+  const double floor_est = 4.0 * L_ * std::pow(eps * E0_, 2);
   x_.stats.tda_polish_iters = 0;
   x_.stats.tda_hist_len = 0;
   for (it = 1; it <= p_.max_iter; ++it) {
@@ -533,20 +583,21 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
     DMRG_HIP(hipMemcpy(zscale_.p, zs.data(), 64 * 8, hipMemcpyHostToDevice));
     forward(m, lcur, false, 0, r2);
     const int l = m + n_;
+    lcur_last_ = l;
     backward(l);
     double mx = 0;
     for (double v : r2) mx = std::max(mx, v);
     auto t1 = std::chrono::steady_clock::now();
     x_.stats.tda_iter_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     x_.stats.tda_iters = it;
-    if (it <= 64) {
+    if (it <= DMRG_TDA_HIST) {
       x_.stats.tda_r2_hist[it - 1] = mx;
       x_.stats.tda_hist_len = it;
     }
     if (polishing) x_.stats.tda_polish_iters = ++polish_iters;
     if (p_.verbose) {
       std::fprintf(stderr, "[tda] it %d l %d max|r|^2 %.3e  w0 %.10f (%.1f ms)%s\n", it, l, mx, w[0] - E0_,
-                   x_.stats.tda_iter_ms, polishing ? " fp32 polish" : "");
+                   x_.stats.tda_iter_ms, polishing ? " fp64 polish" : "");
     }
     bool done = mx < p_.tol;
     if (can_polish && !polishing) {
@@ -558,7 +609,8 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
       }
       if (done || mx < floor_est || (stall >= 4 && mx < 100.0 * floor_est)) {
         polishing = true;
-        prec_ = DMRG_FP32;
+        prec_ = DMRG_FP64;
+        polish_to_ = DMRG_FP64;
         done = false;
       }
     }
@@ -567,10 +619,11 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
       break;
     }
     lcur = l;
-    // thick restart: when the space is full keep, besides the n wanted Ritz
-    // vectors, up to n/2 (at least 2) of the next ones, so that a root close
-    // to the edge of the window keeps its neighbour
-    m = (l + n_ <= Nmax_) ? l : std::min(l, std::min(Nmax_ - n_, n_ + std::max(2, n_ / 2)));
+    // thick restart: when the space is full keep the lowest Ritz vectors,
+    // half of the space (at least the n wanted ones and n/2, at least 2, of
+    // the next, so that a root close to the edge of the window keeps its
+    // neighbour)
+    m = (l + n_ <= Nmax_) ? l : std::min(l, std::min(Nmax_ - n_, std::max(n_ + std::max(2, n_ / 2), Nmax_ / 2)));
   }
   for (int v = 0; v < n_; ++v) {
     etot[v] = last_w[v];
@@ -579,6 +632,17 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
   }
   *iters = std::min(it, p_.max_iter);
   *converged = conv;
+  // reduced matrices of the last forward sweep (test support)
+  {
+    const int l = lcur_last_;
+    x_.tda_l = l;
+    x_.tda_hr.resize(size_t(l) * l);
+    x_.tda_sr.resize(size_t(l) * l);
+    if (l > 0) {
+      DMRG_HIP(hipMemcpy(x_.tda_hr.data(), HR_.p, size_t(l) * l * 8, hipMemcpyDeviceToHost));
+      DMRG_HIP(hipMemcpy(x_.tda_sr.data(), SR_.p, size_t(l) * l * 8, hipMemcpyDeviceToHost));
+    }
+  }
   x_.stats.tda_total_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - run0).count();
 }
