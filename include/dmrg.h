@@ -385,6 +385,13 @@ typedef struct {
   double tda_total_ms;     /* wall time of the last dmrg_tda_roots, including the
                               initial sweeps                                        */
   int tda_space;           /* maximum trial space N of the last dmrg_tda_roots      */
+  double tda_phase_ms[6];  /* device time of the last iteration of a verbose
+                              dmrg_tda_roots by phase: first-order sigma parts
+                              (eq. sigv2), zeroth-order sigma (eqs. sigv1,
+                              hleft2), first-order operators renormalized from
+                              first-order ones, from zeroth-order ones (eqs.
+                              lopr1st, ropr1st), vector work (projections,
+                              gauge, reduced matrices), host waits            */
 } dmrg_stats;
 
 int dmrg_get_stats(dmrg_ctx* ctx, dmrg_stats* out);

@@ -59,7 +59,7 @@ class Stats(ctypes.Structure):
         ("plan_ms", ctypes.c_double), ("sigma_workspace_bytes", ctypes.c_double),
         ("tda_polish_iters", ctypes.c_int), ("tda_hist_len", ctypes.c_int),
         ("tda_r2_hist", ctypes.c_double * TDA_HIST), ("tda_total_ms", ctypes.c_double),
-        ("tda_space", ctypes.c_int)]
+        ("tda_space", ctypes.c_int), ("tda_phase_ms", ctypes.c_double * 6)]
 
 
 class SweepParams(ctypes.Structure):
@@ -375,6 +375,7 @@ class Context:
         self._check(_stats(self._h, ctypes.byref(s)))
         out = {k: getattr(s, k) for k, _ in Stats._fields_}
         out["tda_r2_hist"] = list(s.tda_r2_hist[:s.tda_hist_len])
+        out["tda_phase_ms"] = dict(zip(("sigma1", "sigma0", "ren11", "ren01", "vec", "host"), s.tda_phase_ms))
         return out
 
     def debug_mpo_dense(self, wide_bond=-1, from_right=False):

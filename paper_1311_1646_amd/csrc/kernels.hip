@@ -214,14 +214,25 @@ __global__ void precond_kernel(const double* r, const double* d, const double* w
 
 __global__ void rotate_kernel(const double* __restrict__ X, long ldx, int nin, const double* __restrict__ A, int lda,
                               int nout, double* __restrict__ Y, long ldy, long n) {
+  // outputs in chunks of RC held in registers (constant indices only: a
+  // private array indexed at run time would live in scratch memory); X is
+  // re-read once per chunk, from cache
+  constexpr int RC = 16;
   for (long e = long(blockIdx.x) * blockDim.x + threadIdx.x; e < n; e += long(gridDim.x) * blockDim.x) {
-    double acc[64];
-    for (int v = 0; v < nout; ++v) acc[v] = 0.0;
-    for (int u = 0; u < nin; ++u) {
-      const double xv = X[long(u) * ldx + e];
-      for (int v = 0; v < nout; ++v) acc[v] = fma(xv, A[u + v * lda], acc[v]);
+    for (int v0 = 0; v0 < nout; v0 += RC) {
+      double acc[RC];
+#pragma unroll
+      for (int j = 0; j < RC; ++j) acc[j] = 0.0;
+      for (int u = 0; u < nin; ++u) {
+        const double xv = X[long(u) * ldx + e];
+#pragma unroll
+        for (int j = 0; j < RC; ++j)
+          if (v0 + j < nout) acc[j] = fma(xv, A[u + (v0 + j) * lda], acc[j]);
+      }
+#pragma unroll
+      for (int j = 0; j < RC; ++j)
+        if (v0 + j < nout) Y[long(v0 + j) * ldy + e] = acc[j];
     }
-    for (int v = 0; v < nout; ++v) Y[long(v) * ldy + e] = acc[v];
   }
 }
 

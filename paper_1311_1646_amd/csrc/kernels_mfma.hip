@@ -550,9 +550,9 @@ template <int MODE, int TM, int TN>
 __device__ __forceinline__ void do_tile(int ti, const GTile* __restrict__ tiles, const GJob* __restrict__ jobs,
                                         const GContrib* __restrict__ con, const int* __restrict__ gather,
                                         const GSeg* __restrict__ segs, int nslots,
-                                        typename Cfg<MODE>::T* __restrict__ partial, const Bases& bout, int fold,
-                                        int batch, int out_f64, Lds<MODE, TM, TN>& s, TileMap<TM, TN>& m,
-                                        Bases& sb, const Bases* bs_copy, const Bases* __restrict__ ib) {
+                                        typename Cfg<MODE>::T* __restrict__ partial, int fold, int batch,
+                                        int out_f64, Lds<MODE, TM, TN>& s, TileMap<TM, TN>& m, Bases& sb,
+                                        const Bases& so, const Bases* __restrict__ ib) {
   constexpr int TK = Cfg<MODE>::TK, MB = Cfg<MODE>::MB;
   typedef Geo<TM, TN> G;
   constexpr int BM = G::WTM / MB, BN = G::WTN / MB;
@@ -571,15 +571,14 @@ __device__ __forceinline__ void do_tile(int ti, const GTile* __restrict__ tiles,
   // built, so that its latency overlaps theirs and the barrier
   GContrib cfirst{};
   if (c0 < c1) cfirst = con[c0];
-  // the base table (kernel argument, or the job's instance table of a
-  // grouped launch) is copied to LDS, after the descriptor loads above are
-  // under way; a grouped launch also writes through it
-  const Bases* bsrc = ib ? ib + J.inst : bs_copy;
-  if (bsrc && tid < kMaxBases) {
-    sb.p[tid] = bsrc->p[tid];
-    sb.stride[tid] = bsrc->stride[tid];
+  // a grouped launch reads the job's instance table into LDS (after the
+  // descriptor loads above are under way) and also writes through it; a
+  // plain launch has both tables in LDS already
+  if (ib && tid < kMaxBases) {
+    sb.p[tid] = ib[J.inst].p[tid];
+    sb.stride[tid] = ib[J.inst].stride[tid];
   }
-  const Bases& bo = ib ? sb : bout;
+  const Bases& bo = ib ? sb : so;
   tile_maps<TM, TN>(m, J, t.tm, t.tn, fold, batch, tid, gather);
   __syncthreads();
   Acc<MODE, BM, BN> acc;
@@ -653,7 +652,11 @@ __global__ __launch_bounds__((Geo<TM, TN>::NT), Persist<MODE>::waves) void ggemm
     int fold, int batch, int out_f64, const Bases* __restrict__ ib) {
   __shared__ Lds<MODE, TM, TN> s;
   __shared__ TileMap<TM, TN> m;
-  __shared__ Bases sb;  // base table indexed per contribution (LDS, not a private copy)
+  // The base tables are indexed per contribution and per output job.  They
+  // are copied from the kernel arguments to LDS with constant indices only:
+  // an argument indexed by a run-time value (or passed by address) is first
+  // copied to every lane's private scratch memory.
+  __shared__ Bases sb, so;
   // block-cyclic XCD remap of the products stage: workgroup b runs on XCD
   // b % 8; each XCD takes chunks of C consecutive tiles in turn, so
   // neighbouring tiles (sharing an operand tile) run on one L2 while the
@@ -665,20 +668,25 @@ __global__ __launch_bounds__((Geo<TM, TN>::NT), Persist<MODE>::waves) void ggemm
     const int x = bb & 7, q = bb >> 3;
     bx = ((q / C) * 8 + x) * C + (q % C);
   }
-  if constexpr (Persist<MODE>::on) {
-    const int tid = threadIdx.x;
-    if (!ib && tid < kMaxBases) {
-      sb.p[tid] = bs.p[tid];
-      sb.stride[tid] = bs.stride[tid];
+  if (!ib && threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < kMaxBases; ++k) {
+      sb.p[k] = bs.p[k];
+      sb.stride[k] = bs.stride[k];
+      so.p[k] = bout.p[k];
+      so.stride[k] = bout.stride[k];
     }
+  }
+  // (the barrier after the tile maps orders these writes before any read)
+  if constexpr (Persist<MODE>::on) {
     for (int ti = bx; ti < ntiles; ti += gridDim.x) {
       __syncthreads();  // the previous tile is done with the maps and bases
-      do_tile<MODE, TM, TN>(ti, tiles, jobs, con, gather, segs, nslots, partial, bout, fold, batch, out_f64, s, m,
-                            sb, nullptr, ib);
+      do_tile<MODE, TM, TN>(ti, tiles, jobs, con, gather, segs, nslots, partial, fold, batch, out_f64, s, m, sb,
+                            so, ib);
     }
   } else {
-    do_tile<MODE, TM, TN>(bx, tiles, jobs, con, gather, segs, nslots, partial, bout, fold, batch, out_f64, s,
-                          m, sb, &bs, ib);
+    do_tile<MODE, TM, TN>(bx, tiles, jobs, con, gather, segs, nslots, partial, fold, batch, out_f64, s, m, sb, so,
+                          ib);
   }
 }
 

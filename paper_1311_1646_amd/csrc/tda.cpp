@@ -246,6 +246,44 @@ GaugeKit& Ctx::gauge_kit() {
 
 void Ctx::drop_gauge_kit() { kit_.reset(); }
 
+// Device time of the phases of one Davidson iteration, from events recorded
+// on the context's stream between the phases (only when the run is verbose):
+// the span from one mark to the next is charged to the first mark's phase.
+struct PhaseClock {
+  enum { SIG1, SIG0, REN11, REN01, VEC, HOST, N };
+  hipStream_t s = nullptr;
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> cat;
+  int used = 0;
+  double acc[N] = {};
+  void mark(int c) {
+    if (!on) return;
+    if (used == int(ev.size())) {
+      hipEvent_t e;
+      DMRG_HIP(hipEventCreate(&e));
+      ev.push_back(e);
+      cat.push_back(0);
+    }
+    cat[used] = c;
+    DMRG_HIP(hipEventRecord(ev[used], s));
+    ++used;
+  }
+  // call after the stream has drained past the last mark
+  void collect() {
+    if (!on) return;
+    for (int k = 0; k + 1 < used; ++k) {
+      float ms = 0;
+      DMRG_HIP(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+      acc[cat[k]] += ms;
+    }
+    used = 0;
+  }
+  ~PhaseClock() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+  }
+};
+
 class TdaRunner {
  public:
   TdaRunner(Ctx& x, int nroots, const dmrg_davidson_params& p) : x_(x), k_(x.gauge_kit()), n_(nroots), p_(p), prec_(p.prec) {
@@ -302,6 +340,7 @@ class TdaRunner {
   DBuf HR_, SR_, alpha_, w_, rank_, negw_, ones_, tmpd_, part_, zscale_;
   OpSet FL_[2], FR_[2];
   double E0_ = 0;
+  PhaseClock pc_;
   int lcur_last_ = 0;  // size of the reduced matrices of the last forward sweep
   int polish_from_ = 0, polish_to_ = -1;
   std::vector<double> hw_;  // host copy of Ritz values
@@ -396,13 +435,16 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
       DMRG_HIP(hipEventCreate(&te[1]));
       DMRG_HIP(hipEventRecord(te[0], x_.stream));
     }
+    pc_.mark(PhaseClock::SIG1);
     x_.sigma_general(i, 1, FL_[cur], x_.right[i + 1], C0, 0, Dl, S, l, prec_);
     tfl += x_.stats.sigma_flops;
     double* Wk = Wk_.as<double>();
     if (!init) {
       // sigma (eq. sigv1), residual (eq. rnorm), correction (eqs. error, param)
       double* Sg = Sg_.as<double>();
+      pc_.mark(PhaseClock::SIG0);
       x_.sigma_general(i, 1, x_.left[i], x_.right[i + 1], Cm, S, Sg, S, n_, prec_);
+      pc_.mark(PhaseClock::VEC);
       if (timed) {
         tfl += x_.stats.sigma_flops;
         DMRG_HIP(hipEventRecord(te[1], x_.stream));
@@ -424,7 +466,9 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
       gram(Sg, S, n_, Sg, S, n_, S, tmpd_.as<double>(), n_, 1.0, false);
       tmp.resize(size_t(n_) * n_);
       DMRG_HIP(hipMemcpyAsync(tmp.data(), tmpd_.p, tmp.size() * 8, hipMemcpyDeviceToHost, x_.stream));
+      pc_.mark(PhaseClock::HOST);
       x_.sync();
+      pc_.mark(PhaseClock::VEC);
       for (int v = 0; v < n_; ++v) r2[v] += tmp[size_t(v) * n_ + v];
       launch_precond_f64(Sg, diag_[i].as<double>(), w_.as<double>(), Wk, n_, S, 1e-8, x_.stream);
       // corrections scaled by 1/|r| of the previous iteration so that new
@@ -459,7 +503,9 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
     k_.q_left(i, Cm, Ct, bm_.as<double>(), l);
     // reduced matrices (eqs. hleft2, sleft2)
     double* S0 = S0_.as<double>();
+    pc_.mark(PhaseClock::SIG0);
     x_.sigma_general(i, 1, x_.left[i], x_.right[i + 1], Ct, S, S0, S, l, prec_);
+    pc_.mark(PhaseClock::VEC);
     gram(Ct, S, l, Ct, S, l, S, SR_.as<double>(), l, 1.0, true);
     gram(Ct, S, l, S0, S, l, S, HR_.as<double>(), l, 1.0, true);
     gram(Ct, S, l, Dl, S, l, S, HR_.as<double>(), l, 1.0, true);
@@ -471,10 +517,15 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
     const int nxt = 1 - cur;
     x_.alloc_opset(FL_[nxt], i + 1, 0, l, true, true, prec_ != DMRG_FP64);
     const double* Li = x_.site[i].L.as<double>();
+    pc_.mark(PhaseClock::REN11);
     x_.renorm(DMRG_DIR_LEFT, i, Li, Li, 0, FL_[cur], FL_[nxt], false, l, prec_);
+    pc_.mark(PhaseClock::REN01);
     x_.renorm(DMRG_DIR_LEFT, i, Li, Wk, S, x_.left[i], FL_[nxt], true, l, prec_);
+    pc_.mark(PhaseClock::VEC);
     if (m > 0) copy(Cprev_.as<double>(), Cm, long(m) * S);
+    pc_.mark(PhaseClock::HOST);
     x_.sync();
+    pc_.mark(PhaseClock::VEC);
     cur = nxt;
   }
   x_.sync();
@@ -497,19 +548,26 @@ void TdaRunner::backward(int l) {
     k_.q_right(i, Cb, R1, bm_.as<double>(), l);
     k_.scale(i, true, true, R1, l);
     // first-order right part of the sigma contracted with C^(0)
+    pc_.mark(PhaseClock::SIG1);
     x_.sigma_general(i, 1, x_.left[i], FR_[cur], x_.site[i].C.as<double>(), 0, G_[i].as<double>(), S, l, prec_);
+    pc_.mark(PhaseClock::VEC);
     if (i == 0) break;
     // first-order right operators (eq. ropr1st)
     const int nxt = 1 - cur;
     x_.alloc_opset(FR_[nxt], i, 1, l, true, true, prec_ != DMRG_FP64);
+    pc_.mark(PhaseClock::REN11);
     x_.renorm(DMRG_DIR_RIGHT, i, Ri, Ri, 0, FR_[cur], FR_[nxt], false, l, prec_);
+    pc_.mark(PhaseClock::REN01);
     x_.renorm(DMRG_DIR_RIGHT, i, Ri, R1, S, x_.right[i + 1], FR_[nxt], true, l, prec_);
+    pc_.mark(PhaseClock::VEC);
     // gauge shift to site i-1 (eq. gauge_bwd): C_{i-1} = C~_{i-1} + L_{i-1} (C_i R_i^T)
     double* Wk = Wk_.as<double>();
     copy(Wk, Ct_[i - 1].as<double>(), long(l) * size(i - 1));
     k_.rmul(i - 1, true, x_.site[i - 1].L.as<double>(), 0, bm_.as<double>(), k_.bm_size[i], Wk, l);
     copy(Cb, Wk, long(l) * size(i - 1));
+    pc_.mark(PhaseClock::HOST);
     x_.sync();
+    pc_.mark(PhaseClock::VEC);
     cur = nxt;
   }
   x_.sync();
@@ -563,8 +621,13 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
   const double floor_est = 4.0 * L_ * std::pow(eps * E0_, 2);
   x_.stats.tda_polish_iters = 0;
   x_.stats.tda_hist_len = 0;
+  pc_.s = x_.stream;
+  pc_.on = p_.verbose >= 1;
+  for (int k = 0; k < PhaseClock::N; ++k) x_.stats.tda_phase_ms[k] = 0;
   for (it = 1; it <= p_.max_iter; ++it) {
     auto t0 = std::chrono::steady_clock::now();
+    for (double& a : pc_.acc) a = 0;
+    pc_.mark(PhaseClock::VEC);
     // small generalized eigenproblem H_R a = w S_R a (eq. eigs)
     launch_gep_f64(HR_.as<double>(), SR_.as<double>(), lcur, 1e-10, w_.as<double>(), alpha_.as<double>(),
                    rank_.as<int>(), x_.stream);
@@ -585,6 +648,10 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
     const int l = m + n_;
     lcur_last_ = l;
     backward(l);
+    pc_.mark(PhaseClock::VEC);
+    x_.sync();
+    pc_.collect();
+    for (int k = 0; k < PhaseClock::N; ++k) x_.stats.tda_phase_ms[k] = pc_.acc[k];
     double mx = 0;
     for (double v : r2) mx = std::max(mx, v);
     auto t1 = std::chrono::steady_clock::now();
@@ -596,8 +663,12 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
     }
     if (polishing) x_.stats.tda_polish_iters = ++polish_iters;
     if (p_.verbose) {
-      std::fprintf(stderr, "[tda] it %d l %d max|r|^2 %.3e  w0 %.10f (%.1f ms)%s\n", it, l, mx, w[0] - E0_,
-                   x_.stats.tda_iter_ms, polishing ? " fp64 polish" : "");
+      const double* a = pc_.acc;
+      std::fprintf(stderr,
+                   "[tda] it %d l %d max|r|^2 %.3e  w0 %.10f (%.1f ms: sigma1 %.0f sigma0 %.0f ren11 %.0f ren01 %.0f "
+                   "vec %.0f host %.0f)%s\n",
+                   it, l, mx, w[0] - E0_, x_.stats.tda_iter_ms, a[0], a[1], a[2], a[3], a[4], a[5],
+                   polishing ? " fp64 polish" : "");
     }
     bool done = mx < p_.tol;
     if (can_polish && !polishing) {
