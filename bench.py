@@ -246,7 +246,7 @@ def measured_traffic(prec, M):
     src = open(os.path.join(ROOT, "paper_1311_1646_amd", "csrc", "kernels_mfma.hip"), "rb").read()
     if d.get("kernel_sha256") != hashlib.sha256(src).hexdigest() or d.get("prec") != prec or d.get("M") != M:
         return None
-    return d["hbm_bytes_per_launch"]
+    return d["hbm_bytes_per_launch"], d["source"]
 
 
 def roofline(r, name):
@@ -374,7 +374,10 @@ def main():
     # dominant kernel: the accumulation stage (grouped GEMM, role 1) of the
     # three parts of the TDA sigma; per launch = per sigma / launches
     rl = roofline(head, a.prec)
-    rl["traffic"] = measured_traffic(a.prec, p.M)
+    tr = measured_traffic(a.prec, p.M)
+    rl["traffic"] = tr[0] if tr else None
+    rl["traffic_source"] = (f"committed rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel source, calibrated by a "
+                            f"256 MiB copy ({tr[1]})" if tr else "none for this kernel source / precision / M")
     out["roofline"] = rl
     if tda:
         out["tda_sweep_s"] = tda[a.prec]["iteration_s"]
@@ -391,7 +394,7 @@ def main():
         s = ctx.stats()
         out["tda_converged"] = {"prec": a.prec, "converged": bool(conv), "iterations": its, "tol": 1e-6,
                                 "time_to_convergence_s": round(time.perf_counter() - t0, 1),
-                                "fp32_polish_iterations": s["tda_polish_iters"],
+                                "fp64_polish_iterations": s["tda_polish_iters"],
                                 "omega_Eh": [round(float(x), 8) for x in om]}
         log(f"[bench] TDA converged: {out['tda_converged']}")
     if not a.no_sweep_avg:
