@@ -14,7 +14,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libdmrg.so")
+# DMRG_LIBRARY selects another build of the same library (the host-sanitizer
+# build, libdmrg_san.so, loaded with the sanitizer runtime preloaded)
+LIB_PATH = os.environ.get("DMRG_LIBRARY") or os.path.join(_HERE, "libdmrg.so")
 
 FP64, FP32, BF16X3 = 0, 1, 2
 SIGMA_ZEROTH_1SITE, SIGMA_ZEROTH_2SITE, SIGMA_TDA_FULL, SIGMA_TDA_DH_LEFT = 0, 1, 2, 3
