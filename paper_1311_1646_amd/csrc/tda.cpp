@@ -774,6 +774,9 @@ void Ctx::renorm_first(int i, int dir, int nvec, const double* A1, int prec) {
     renorm(DMRG_DIR_RIGHT, i, Ri, Ri, 0, F.set[F.cur], F.set[nxt], false, nvec, prec);
     renorm(DMRG_DIR_RIGHT, i, Ri, X, S, right[i + 1], F.set[nxt], true, nvec, prec);
   }
+  // only the set at the chain's end is kept between calls (stream-ordered
+  // release: the renormalizations above are enqueued before it)
+  F.set[F.cur].data.release();
   F.cur = nxt;
   F.bond = nb;
   sync();
