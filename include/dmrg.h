@@ -348,6 +348,29 @@ int dmrg_group_destroy(dmrg_group* g);
  * and sleft2, summed over sites) of the last forward sweep of the last
  * dmrg_tda_roots, l x l row-major FP64 on the host.  With NULL HR / SR only
  * l is returned.  Errors: STATE before a TDA run. */
+/* Frequency-dependent linear response to a one-body perturbation
+ * V = sum_pq v_pq E_pq (E_pq the spin-summed excitation operator), Sec. II B,
+ * eqs. realresp and imagresp: the first-order wavefunctions of the +omega
+ * and -omega components (eq. psi1st, gauge of eqs. left-orthoSeb and
+ * right-orthoSeb, orthogonal to Psi0) solve
+ *   (H - (E0 - omega)) Psi1_+ = -Q V Psi0,   (H - (E0 + omega)) Psi1_- = -Q V Psi0
+ * in the tangent space of the imported MPS, E0 = <Psi0|H|Psi0>.  They are
+ * found by the sweep Davidson of dmrg_tda_roots (same sigma, reduced
+ * matrices and Q^C projection) with the reduced linear system solved in the
+ * Ritz basis and residuals (H - z) x + Q P_i^T V Psi0 at every site.
+ * v: host L x L row-major symmetric matrix; omega: real frequency (away
+ * from the poles E_mu - E0).  p: as for dmrg_tda_roots (nroots is 2; the
+ * tolerance applies to both residuals; guess is ignored: the start vectors
+ * are the preconditioned right-hand sides).  chi[0] = <V Psi0 | Psi1_+>,
+ * chi[1] = <V Psi0 | Psi1_->; the dynamic polarizability along v is
+ * alpha(omega) = -(chi[0] + chi[1]).  resid2[0..1]: final residual norms^2.
+ * NOT_CONVERGED fills the outputs of the last iteration.
+ * Errors: STATE before build_ops, INVALID_ARG (v not symmetric or not
+ * finite, omega not finite, parameters), SINGULAR (V Psi0 has no component
+ * in the tangent space). */
+int dmrg_response(dmrg_ctx* ctx, const double* v, double omega, const dmrg_davidson_params* p, double* chi,
+                  double* resid2, int* iters);
+
 int dmrg_tda_reduced(dmrg_ctx* ctx, int* l, double* HR, double* SR);
 
 #define DMRG_TDA_HIST 256 /* iterations kept in dmrg_stats.tda_r2_hist */

@@ -105,6 +105,7 @@ _stats_size.restype = ctypes.c_size_t
 if _stats_size() != ctypes.sizeof(Stats):
     raise ImportError(f"dmrg_stats layout mismatch: library {_stats_size()} bytes, binding {ctypes.sizeof(Stats)}")
 _tda_reduced = _sig("dmrg_tda_reduced", _P, _IP, _DP, _DP)
+_response = _sig("dmrg_response", _P, _DP, _D, ctypes.POINTER(DavidsonParams), _DP, _DP, _IP)
 _debug_dense = _sig("dmrg_debug_mpo_dense", _P, _I, _I, _DP)
 _group_create = _sig("dmrg_group_create", _P, _I, _IP, _I, _I, ctypes.POINTER(_P))
 _group_sigma = _sig("dmrg_group_sigma", _P, _P, _P, _SP, _I)
@@ -362,6 +363,26 @@ class Context:
         if rc not in (0, -3):
             self._check(rc)
         return om, et, r2, it.value, rc == 0
+
+    def response(self, v, omega, max_iter=80, max_space=0, tol=1e-10, prec=FP64, verbose=0, polish=True):
+        """Linear response to the one-body perturbation V = sum_pq v_pq E_pq at
+        frequency omega (see dmrg_response): returns (chi_plus, chi_minus,
+        resid2, iterations, converged) with chi_pm = <V Psi0 | Psi1_pm>."""
+        v = np.ascontiguousarray(v, dtype=np.float64)
+        if v.shape != (self.L, self.L):
+            raise ValueError(f"v must have shape ({self.L}, {self.L})")
+        p = DavidsonParams(max_iter, max_space, tol, 0, prec, verbose, 0 if polish else -1, 0)
+        chi = np.zeros(2)
+        r2 = np.zeros(2)
+        it = ctypes.c_int()
+        if self._alloc is not None and max_space == 0:
+            import torch
+            torch.cuda.synchronize(self.device)
+            torch.cuda.empty_cache()
+        rc = _response(self._h, _dp(v), float(omega), ctypes.byref(p), _dp(chi), _dp(r2), ctypes.byref(it))
+        if rc not in (0, -3):
+            self._check(rc)
+        return float(chi[0]), float(chi[1]), r2, it.value, rc == 0
 
     def tda_reduced(self):
         """(H_R, S_R) of the last TDA forward sweep (l x l numpy arrays)."""

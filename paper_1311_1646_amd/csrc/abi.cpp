@@ -235,6 +235,22 @@ int dmrg_tda_roots(dmrg_ctx* ctx, int nroots, const dmrg_davidson_params* p, dou
   return rc;
 }
 
+int dmrg_response(dmrg_ctx* ctx, const double* v, double omega, const dmrg_davidson_params* p, double* chi,
+                  double* resid2, int* iters) {
+  bool conv = false;
+  int rc = guard(ctx, [&](dmrg::Ctx& x) {
+    DMRG_REQUIRE(p, DMRG_ERR_INVALID_ARG, "null parameters");
+    DMRG_REQUIRE(valid_prec(p->prec), DMRG_ERR_INVALID_ARG, "unsupported precision");
+    DMRG_REQUIRE(p->polish == 0 || p->polish == -1, DMRG_ERR_INVALID_ARG, "polish must be 0 or -1");
+    x.response(v, omega, *p, chi, resid2, iters, &conv);
+  });
+  if (rc == DMRG_OK && !conv) {
+    ctx->x->err = "Davidson iteration limit reached";
+    return DMRG_ERR_NOT_CONVERGED;
+  }
+  return rc;
+}
+
 int dmrg_tda_reduced(dmrg_ctx* ctx, int* l, double* HR, double* SR) {
   return guard(ctx, [&](dmrg::Ctx& x) {
     DMRG_REQUIRE(l, DMRG_ERR_INVALID_ARG, "null l");

@@ -349,6 +349,8 @@ class Ctx {
   void diag(int i, int width, double* out);
   void tda_roots(int nroots, const dmrg_davidson_params& p, double* omega, double* etot, double* resid2,
                  int* iters, bool* converged);
+  void response(const double* v, double omega, const dmrg_davidson_params& p, double* chi, double* resid2,
+                int* iters, bool* converged);
   // ground state by two-site sweeps (ground.cpp); returns <Psi|H|Psi>
   void sweep_ground(const dmrg_sweep_params& p, double* energy, double* discarded, bool* converged);
   // replace the sectors of bond b (and its Schmidt values); drops every

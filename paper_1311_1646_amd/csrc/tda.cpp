@@ -284,9 +284,27 @@ struct PhaseClock {
   }
 };
 
+// Frequency-dependent linear response (Sec. II B, eqs. realresp, imagresp):
+// the first-order wavefunctions of the +omega and -omega components solve
+// (H - z_pm) Psi1_pm = -Q V Psi0 in the tangent space with the reference
+// removed, z_pm = E0 -+ omega.  rhs[i] = P_i^T V Psi0 is the site-i
+// projection of V Psi0 (flat one-site layout, device FP64).
+struct ResponseSpec {
+  std::vector<const double*> rhs;
+  double omega = 0;
+};
+
 class TdaRunner {
  public:
-  TdaRunner(Ctx& x, int nroots, const dmrg_davidson_params& p) : x_(x), k_(x.gauge_kit()), n_(nroots), p_(p), prec_(p.prec) {
+  // nroots TDA roots, or (rs != null) the two response vectors of rs
+  TdaRunner(Ctx& x, int nroots, const dmrg_davidson_params& p, const ResponseSpec* rs = nullptr)
+      : x_(x), k_(x.gauge_kit()), n_(rs ? 2 : nroots), p_(p), prec_(p.prec) {
+    if (rs) {
+      resp_ = true;
+      rhs_ = rs->rhs;
+      omega_ = rs->omega;
+      DMRG_REQUIRE(int(rhs_.size()) == x.L, DMRG_ERR_INTERNAL, "response right-hand side per site");
+    }
     L_ = x.L;
     const long maxsize = k_.max_size;
     guess_ = p.guess;
@@ -318,6 +336,12 @@ class TdaRunner {
     zscale_.alloc(&x, 64 * 8);
     tmpd_.alloc(&x, 64 * 64 * 8);
     part_.alloc(&x, size_t(gram_parts(maxsize) + 1) * 64 * 64 * 8);
+    if (resp_) {
+      bR_.alloc(&x, 64 * 8);
+      cres_.alloc(&x, 64 * 2 * 8);
+      zsh_.alloc(&x, 64 * 8);
+      for (DBuf* b : {&Cx_, &Dx_, &Gx_}) b->alloc(&x, 2 * size_t(maxsize) * 8);
+    }
     std::vector<double> one(64, 1.0);
     DMRG_HIP(hipMemcpy(ones_.p, one.data(), 64 * 8, hipMemcpyHostToDevice));
     for (int k = 0; k < 2; ++k) {
@@ -327,6 +351,8 @@ class TdaRunner {
   }
 
   void run(double* omega, double* etot, double* resid2, int* iters, bool* converged);
+  // response mode: <V Psi0 | Psi1_pm> of the last iteration
+  double chi(int k) const { return chi_[k]; }
 
  private:
   Ctx& x_;
@@ -344,6 +370,13 @@ class TdaRunner {
   int lcur_last_ = 0;  // size of the reduced matrices of the last forward sweep
   int polish_from_ = 0, polish_to_ = -1;
   std::vector<double> hw_;  // host copy of Ritz values
+  // response mode: right-hand sides, frequency, b_R = <trial | V Psi0>, the
+  // coefficients of x_pm in the Ritz basis, the shifts z_pm, and the site
+  // pieces of x_pm
+  bool resp_ = false;
+  std::vector<const double*> rhs_;
+  double omega_ = 0, chi_[2] = {0, 0};
+  DBuf bR_, cres_, zsh_, Cx_, Dx_, Gx_;
 
   long size(int i) const { return k_.size[i]; }
   void copy(double* dst, const double* src, long n) {
@@ -355,6 +388,11 @@ class TdaRunner {
     DMRG_HIP(hipGetLastError());
   }
   void q_c_project(int i, double* z, int nv);  // z -= C0 (C0 . z)
+  // response mode, after the small eigenproblem of an iteration: Ritz-basis
+  // right-hand side, coefficients of x_pm and chi_pm; reorders the Ritz
+  // vectors (alpha, w) by their weight in x_pm so that a restart keeps the
+  // important ones
+  void response_step(int lcur, int rank, int m, std::vector<double>& w);
   void forward(int m, int lprev, bool init, uint64_t seed, std::vector<double>& r2);
   // size both buffers of a ping-pong pair of first-order sets (side 0 left,
   // 1 right) for the largest bond, so that a sweep allocates once
@@ -387,6 +425,49 @@ class TdaRunner {
   }
 };
 
+void TdaRunner::response_step(int lcur, int rank, int m, std::vector<double>& w) {
+  std::vector<double> al(size_t(lcur) * lcur), br(lcur);
+  DMRG_HIP(hipMemcpy(al.data(), alpha_.p, al.size() * 8, hipMemcpyDeviceToHost));
+  DMRG_HIP(hipMemcpy(br.data(), bR_.p, br.size() * 8, hipMemcpyDeviceToHost));
+  const double z[2] = {E0_ - omega_, E0_ + omega_};
+  // b_k = <y_k | V Psi0> for the S_R-orthonormal Ritz vectors y_k (columns of
+  // alpha); in that basis (H_R - z S_R) a = -b_R is diagonal:
+  // c_k = -b_k / (w_k - z)
+  std::vector<double> b(rank, 0.0), c(size_t(rank) * 2);
+  for (int k = 0; k < rank; ++k) {
+    for (int u = 0; u < lcur; ++u) b[k] += al[u + size_t(k) * lcur] * br[u];
+    for (int v = 0; v < 2; ++v) c[k + size_t(v) * rank] = -b[k] / (w[k] - z[v]);
+  }
+  std::vector<int> ord(rank);
+  for (int k = 0; k < rank; ++k) ord[k] = k;
+  std::stable_sort(ord.begin(), ord.end(), [&](int p, int q) {
+    return std::abs(c[p]) + std::abs(c[p + rank]) > std::abs(c[q]) + std::abs(c[q + rank]);
+  });
+  std::vector<double> al2(al), w2(w), cm(size_t(m) * 2);
+  chi_[0] = chi_[1] = 0;
+  for (int j = 0; j < rank; ++j) {
+    const int k = ord[j];
+    for (int u = 0; u < lcur; ++u) al2[u + size_t(j) * lcur] = al[u + size_t(k) * lcur];
+    w2[j] = w[k];
+    if (j < m) {
+      for (int v = 0; v < 2; ++v) {
+        cm[j + size_t(v) * m] = c[k + size_t(v) * rank];
+        chi_[v] += b[k] * c[k + size_t(v) * rank];
+      }
+    }
+  }
+  w = w2;
+  if (p_.verbose >= 1) {
+    double dmin[2] = {1e300, 1e300};
+    for (int k = 0; k < m; ++k)
+      for (int v = 0; v < 2; ++v) dmin[v] = std::min(dmin[v], std::abs(w[k] - z[v]));
+    std::fprintf(stderr, "[response] rank %d kept %d chi %.12f %.12f  min|w-z| %.3e %.3e\n", rank, m, chi_[0],
+                 chi_[1], dmin[0], dmin[1]);
+  }
+  DMRG_HIP(hipMemcpy(alpha_.p, al2.data(), al2.size() * 8, hipMemcpyHostToDevice));
+  DMRG_HIP(hipMemcpy(cres_.p, cm.data(), cm.size() * 8, hipMemcpyHostToDevice));
+}
+
 void TdaRunner::q_c_project(int i, double* z, int nv) {
   const double* C0 = x_.site[i].C.as<double>();
   gram(z, size(i), nv, C0, size(i), 1, size(i), tmpd_.as<double>(), 1, -1.0, false);
@@ -399,6 +480,7 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
   r2.assign(n_, 0.0);
   launch_fill_f64(HR_.as<double>(), long(l) * l, 0.0, x_.stream);
   launch_fill_f64(SR_.as<double>(), long(l) * l, 0.0, x_.stream);
+  if (resp_) launch_fill_f64(bR_.as<double>(), l, 0.0, x_.stream);
   int cur = 0;
   reserve(FL_, 0, l);
   x_.alloc_opset(FL_[cur], 0, 0, l, true, true, prec_ != DMRG_FP64);
@@ -442,8 +524,24 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
     if (!init) {
       // sigma (eq. sigv1), residual (eq. rnorm), correction (eqs. error, param)
       double* Sg = Sg_.as<double>();
+      // the vectors whose residuals are taken: the n lowest Ritz vectors, or
+      // in response mode x_pm = sum_k c_k^pm y_k over the m Ritz vectors y_k
+      // (their zeroth-order coefficients, first-order left parts and stored
+      // right parts rotated alike: the sigma is linear)
+      const double* Xc = Cm;
+      const double* Xd = Dl;
+      const double* Xg = Gr_.as<double>();
+      if (resp_) {
+        launch_rotate_f64(Cm, S, m, cres_.as<double>(), m, 2, Cx_.as<double>(), S, S, x_.stream);
+        launch_rotate_f64(Dl, S, m, cres_.as<double>(), m, 2, Dx_.as<double>(), S, S, x_.stream);
+        launch_rotate_f64(Gr_.as<double>(), S, m, cres_.as<double>(), m, 2, Gx_.as<double>(), S, S, x_.stream);
+        DMRG_HIP(hipGetLastError());
+        Xc = Cx_.as<double>();
+        Xd = Dx_.as<double>();
+        Xg = Gx_.as<double>();
+      }
       pc_.mark(PhaseClock::SIG0);
-      x_.sigma_general(i, 1, x_.left[i], x_.right[i + 1], Cm, S, Sg, S, n_, prec_);
+      x_.sigma_general(i, 1, x_.left[i], x_.right[i + 1], Xc, S, Sg, S, n_, prec_);
       pc_.mark(PhaseClock::VEC);
       if (timed) {
         tfl += x_.stats.sigma_flops;
@@ -456,9 +554,11 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
         (void)hipEventDestroy(te[0]);
         (void)hipEventDestroy(te[1]);
       }
-      launch_axpby_f64(ones_.as<double>(), Dl, S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
-      launch_axpby_f64(ones_.as<double>(), Gr_.as<double>(), S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
-      launch_axpby_f64(negw_.as<double>(), Cm, S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
+      launch_axpby_f64(ones_.as<double>(), Xd, S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
+      launch_axpby_f64(ones_.as<double>(), Xg, S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
+      launch_axpby_f64(negw_.as<double>(), Xc, S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
+      // response: r = (H - z) x + V Psi0 (eqs. realresp, imagresp)
+      if (resp_) launch_axpby_f64(ones_.as<double>(), rhs_[i], 0, ones_.as<double>(), Sg, S, n_, S, x_.stream);
       DMRG_HIP(hipGetLastError());
       // residual restricted to the site's tangent directions (orthogonal to
       // C^(0)); for a stationary reference this projection changes nothing
@@ -470,10 +570,17 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
       x_.sync();
       pc_.mark(PhaseClock::VEC);
       for (int v = 0; v < n_; ++v) r2[v] += tmp[size_t(v) * n_ + v];
-      launch_precond_f64(Sg, diag_[i].as<double>(), w_.as<double>(), Wk, n_, S, 1e-8, x_.stream);
+      launch_precond_f64(Sg, diag_[i].as<double>(), resp_ ? zsh_.as<double>() : w_.as<double>(), Wk, n_, S, 1e-8,
+                         x_.stream);
       // corrections scaled by 1/|r| of the previous iteration so that new
       // trial vectors keep O(1) norm (S_R stays well conditioned near convergence)
       launch_axpby_f64(zscale_.as<double>(), Wk, S, nullptr, Wk, S, n_, S, x_.stream);
+      DMRG_HIP(hipGetLastError());
+    } else if (resp_) {
+      // response: the preconditioned right-hand sides (V Psi0)_i / (diag - z_pm)
+      double* Sg = Sg_.as<double>();
+      launch_axpby_f64(nullptr, rhs_[i], 0, nullptr, Sg, S, n_, S, x_.stream);
+      launch_precond_f64(Sg, diag_[i].as<double>(), zsh_.as<double>(), Wk, n_, S, 1e-8, x_.stream);
       DMRG_HIP(hipGetLastError());
     } else {
       tmp.resize(size_t(n_) * S);
@@ -508,6 +615,9 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
     pc_.mark(PhaseClock::VEC);
     gram(Ct, S, l, Ct, S, l, S, SR_.as<double>(), l, 1.0, true);
     gram(Ct, S, l, S0, S, l, S, HR_.as<double>(), l, 1.0, true);
+    // response: b_R[mu] = <Psi1^mu | V Psi0> (the left-gauge components of
+    // different sites are orthogonal, as for S_R)
+    if (resp_) gram(Ct, S, l, rhs_[i], S, 1, S, bR_.as<double>(), 1, 1.0, true);
     gram(Ct, S, l, Dl, S, l, S, HR_.as<double>(), l, 1.0, true);
     gram(Dl, S, l, Ct, S, l, S, HR_.as<double>(), l, 1.0, true);
     if (i == L_ - 1) break;
@@ -589,6 +699,16 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
     DMRG_HIP(hipMemcpy(&E0_, tmpd_.p, 8, hipMemcpyDeviceToHost));
   }
   for (int i = 0; i < L_; ++i) x_.diag(i, 1, diag_[i].as<double>());
+  if (resp_) {
+    // shifts of the +omega and -omega components (eqs. realresp, imagresp)
+    std::vector<double> z(64, 0.0), nz(64, 0.0);
+    z[0] = E0_ - omega_;
+    z[1] = E0_ + omega_;
+    nz[0] = -z[0];
+    nz[1] = -z[1];
+    DMRG_HIP(hipMemcpy(zsh_.p, z.data(), 64 * 8, hipMemcpyHostToDevice));
+    DMRG_HIP(hipMemcpy(negw_.p, nz.data(), 64 * 8, hipMemcpyHostToDevice));
+  }
   std::vector<double> r2;
   // initial trial vectors (unit vectors on the lowest diagonal elements of
   // the middle site, or random components at every site), Q^C projected,
@@ -635,11 +755,18 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
     int rank = 0;
     DMRG_HIP(hipMemcpy(w.data(), w_.p, size_t(lcur) * 8, hipMemcpyDeviceToHost));
     DMRG_HIP(hipMemcpy(&rank, rank_.p, sizeof(int), hipMemcpyDeviceToHost));
-    DMRG_REQUIRE(rank >= n_, DMRG_ERR_SINGULAR, "trial space lost rank below the number of roots");
+    // (response mode: the Ritz vectors are a basis, not the roots; the two
+    // components coincide at omega = 0 and their corrections are then
+    // dependent, which the rank threshold absorbs)
+    DMRG_REQUIRE(rank >= (resp_ ? 1 : n_), DMRG_ERR_SINGULAR, "trial space lost rank below the number of roots");
     m = std::min(m, rank);
-    std::vector<double> nw(64, 0.0);
-    for (int v = 0; v < n_; ++v) nw[v] = -w[v];
-    DMRG_HIP(hipMemcpy(negw_.p, nw.data(), 64 * 8, hipMemcpyHostToDevice));
+    if (resp_) {
+      response_step(lcur, rank, m, w);
+    } else {
+      std::vector<double> nw(64, 0.0);
+      for (int v = 0; v < n_; ++v) nw[v] = -w[v];
+      DMRG_HIP(hipMemcpy(negw_.p, nw.data(), 64 * 8, hipMemcpyHostToDevice));
+    }
     for (int v = 0; v < n_; ++v) last_w[v] = w[v];
     std::vector<double> zs(64, 1.0);
     for (int v = 0; v < n_; ++v) zs[v] = r2.empty() ? 1.0 : 1.0 / std::sqrt(std::max(r2[v], 1e-300));
@@ -866,6 +993,63 @@ void Ctx::tda_roots(int nroots, const dmrg_davidson_params& p, double* omega, do
     TdaRunner r(*this, nroots, p);
     r.run(omega, etot, resid2, iters, converged);
   }
+  release_workspaces();
+}
+
+// Frequency-dependent linear response to a one-body perturbation
+// V = sum_pq v_pq E_pq (Sec. II B, eqs. realresp and imagresp; first-order
+// wavefunction of eq. psi1st in the gauge of eqs. left-orthoSeb and
+// right-orthoSeb).  The right-hand side V Psi0, projected on every site, is
+// the zeroth-order sigma of a second context that holds V (no two-body part)
+// on the same MPS.  chi[0] = <V Psi0 | Psi1_+omega>, chi[1] = <V Psi0 |
+// Psi1_-omega>, with (H - (E0 -+ omega)) Psi1_pm = -Q V Psi0 in the tangent
+// space.
+void Ctx::response(const double* v, double omega, const dmrg_davidson_params& p, double* chi, double* resid2,
+                   int* iters, bool* converged) {
+  require_gpu();
+  DMRG_REQUIRE(ops_prec >= 0, DMRG_ERR_STATE, "call dmrg_build_ops first");
+  DMRG_REQUIRE(v && chi && resid2 && iters && converged, DMRG_ERR_INVALID_ARG, "null arguments");
+  DMRG_REQUIRE(p.max_iter >= 1, DMRG_ERR_INVALID_ARG, "max_iter must be >= 1");
+  DMRG_REQUIRE(std::isfinite(omega), DMRG_ERR_INVALID_ARG, "omega must be finite");
+  double vmax = 0;
+  for (int a = 0; a < L * L; ++a) {
+    DMRG_REQUIRE(std::isfinite(v[a]), DMRG_ERR_INVALID_ARG, "non-finite entry in v");
+    vmax = std::max(vmax, std::abs(v[a]));
+  }
+  for (int a = 0; a < L; ++a)
+    for (int b = a + 1; b < L; ++b)
+      DMRG_REQUIRE(std::abs(v[a * L + b] - v[b * L + a]) <= 1e-12 * std::max(vmax, 1.0), DMRG_ERR_INVALID_ARG,
+                   "v must be symmetric");
+  sync();
+  for (auto& f : fo_chain) f.reset();
+  std::vector<long> off(L + 1, 0);
+  for (int i = 0; i < L; ++i) off[i + 1] = off[i] + layout(i, 1).size;
+  DBuf rhs;
+  rhs.alloc(this, size_t(std::max<long>(off[L], 1)) * 8);
+  {
+    size_t sz[4] = {0, 0, 0, 0};
+    export_mps(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, sz);
+    std::vector<int> nsec(L + 1), sec(3 * sz[0]);
+    std::vector<double> Ld(sz[1]), Rd(sz[1]), Cd(sz[1]), lamd(sz[3]);
+    export_mps(nsec.data(), sec.data(), Ld.data(), Rd.data(), Cd.data(), lamd.data(), sz);
+    const std::vector<double> zero(size_t(L) * L * L * L, 0.0);
+    Ctx vc(L, Na, Nb, v, zero.data(), 0.0, device, stream, &allocator);
+    vc.import_mps(nsec.data(), sec.data(), Ld.data(), Rd.data(), Cd.data(), lamd.data());
+    vc.build_ops(DMRG_FP64);
+    for (int i = 0; i < L; ++i) vc.sigma(i, 1, 1, site[i].C.as<double>(), rhs.as<double>() + off[i], DMRG_FP64);
+    vc.sync();
+  }
+  ResponseSpec rs;
+  rs.omega = omega;
+  for (int i = 0; i < L; ++i) rs.rhs.push_back(rhs.as<double>() + off[i]);
+  {
+    TdaRunner r(*this, 2, p, &rs);
+    double om[2], et[2];
+    r.run(om, et, resid2, iters, converged);
+    chi[0] = r.chi(0);
+    chi[1] = r.chi(1);
+  }
+  sync();
   release_workspaces();
 }
 
