@@ -8,10 +8,13 @@
 #include "kernels_mfma.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <thread>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <set>
 #include <unordered_map>
 
@@ -679,6 +682,7 @@ const SiteLayout& Ctx::layout(int i, int width) {
 }
 
 const OpLayout* Ctx::op_layout(int bond, int dna, int dnb) {
+  std::lock_guard<std::mutex> lock(op_layout_mu_);
   auto key = std::make_tuple(bond, dna, dnb);
   auto it = op_layouts_.find(key);
   if (it != op_layouts_.end()) return it->second.get();
@@ -967,6 +971,16 @@ ContractionPlan& Ctx::renorm_plan(int dir, int i, const OpSet& src, const OpSet&
   auto key = std::make_tuple(dir, i, src.first_order ? 1 : 0, bra_first ? 1 : 0);
   auto it = renorm_plans_.find(key);
   if (it != renorm_plans_.end()) return *it->second;
+  return *(renorm_plans_[key] = make_renorm_plan(dir, i, src, dst, bra_first));
+}
+
+// Builds a renormalization plan without touching the plan cache, so that
+// several can be built at once (build_ops): it reads the channel tables, the
+// site layout and site operator of site i (prepared beforehand), and the
+// operator-layout cache (guarded by its mutex); its device lists are
+// uploaded through the allocator, which is safe from several threads.
+std::unique_ptr<ContractionPlan> Ctx::make_renorm_plan(int dir, int i, const OpSet& src, const OpSet& dst,
+                                                       bool bra_first) {
   auto P = std::make_unique<ContractionPlan>();
   P->bra_first = bra_first;
   const bool leftdir = dir == DMRG_DIR_LEFT;
@@ -1184,7 +1198,7 @@ ContractionPlan& Ctx::renorm_plan(int dir, int i, const OpSet& src, const OpSet&
   }
   post.finish(*this, P->post);
   if (std::getenv("DMRG_PLAN_STATS")) print_plan_stats(dir == 0 ? "renorm-L" : "renorm-R", i, 1, *P);
-  return *(renorm_plans_[key] = std::move(P));
+  return P;
 }
 
 void Ctx::renorm(int dir, int i, const double* Abra, const double* Aket, long aket_stride, const OpSet& src,
@@ -1274,8 +1288,26 @@ void Ctx::build_ops(int prec) {
     alloc_opset(left[b], b, 0, 1, false);
     alloc_opset(right[b], b, 1, 1, false);
   }
-  for (int i = 0; i < L; ++i) renorm_plan(DMRG_DIR_LEFT, i, left[i], left[i + 1], false);
-  for (int i = L - 1; i >= 0; --i) renorm_plan(DMRG_DIR_RIGHT, i, right[i + 1], right[i], false);
+  // the 2L plans are independent: built on a pool of host threads after the
+  // shared lazily built objects they read (site layouts and site
+  // operators) exist, then entered into the cache
+  for (int i = 0; i < L; ++i) {
+    layout(i, 1);
+    H->site_op(i, 1, H->mode_left(i), H->mode_left(i + 1));
+    H->site_op(i, 1, H->mode_right(i), H->mode_right(i + 1));
+  }
+  {
+    std::vector<std::function<std::unique_ptr<ContractionPlan>()>> fns;
+    for (int i = 0; i < L; ++i)
+      fns.push_back([this, i]() { return make_renorm_plan(DMRG_DIR_LEFT, i, left[i], left[i + 1], false); });
+    for (int i = L - 1; i >= 0; --i)
+      fns.push_back([this, i]() { return make_renorm_plan(DMRG_DIR_RIGHT, i, right[i + 1], right[i], false); });
+    auto built = build_parallel(fns);
+    for (int t = 0; t < 2 * L; ++t) {
+      const int i = t < L ? t : 2 * L - 1 - t;
+      renorm_plans_[std::make_tuple(t < L ? DMRG_DIR_LEFT : DMRG_DIR_RIGHT, i, 0, 0)] = std::move(built[t]);
+    }
+  }
   stats.plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
   hipEvent_t e0, e1;
   DMRG_HIP(hipEventCreate(&e0));
@@ -1396,6 +1428,13 @@ ContractionPlan& Ctx::sigma_plan(int i, int width, const OpSet& X, const OpSet& 
   auto key = std::make_tuple(i, width, (X.first_order ? 1 : 0) + (left_first ? 2 : 0), Z.first_order ? 1 : 0);
   auto it = sigma_plans_.find(key);
   if (it != sigma_plans_.end()) return *it->second;
+  return *(sigma_plans_[key] = make_sigma_plan(i, width, X, Z, left_first));
+}
+
+// As make_renorm_plan: no cache access, safe on the plan threads once the
+// site layout and site operator of (i, width) exist.
+std::unique_ptr<ContractionPlan> Ctx::make_sigma_plan(int i, int width, const OpSet& X, const OpSet& Z,
+                                                      bool left_first) {
   auto P = std::make_unique<ContractionPlan>();
   P->left_first = left_first;
   const SiteLayout& S = layout(i, width);
@@ -1508,7 +1547,86 @@ ContractionPlan& Ctx::sigma_plan(int i, int width, const OpSet& X, const OpSet& 
   }
   finish_two_stage(*this, TB, P->main, true);
   if (std::getenv("DMRG_PLAN_STATS")) print_plan_stats("sigma", i, width, *P);
-  return *(sigma_plans_[key] = std::move(P));
+  return P;
+}
+
+std::vector<std::unique_ptr<ContractionPlan>> Ctx::build_parallel(
+    const std::vector<std::function<std::unique_ptr<ContractionPlan>()>>& fns) {
+  const int n = int(fns.size());
+  std::vector<std::unique_ptr<ContractionPlan>> built(n);
+  std::vector<std::exception_ptr> err(n);
+  std::atomic<int> next{0};
+  auto work = [&]() {
+    // the current device is per host thread
+    if (hipSetDevice(device) != hipSuccess) (void)hipGetLastError();
+    for (int t = next++; t < n; t = next++) {
+      try {
+        built[t] = fns[t]();
+      } catch (...) {
+        err[t] = std::current_exception();
+      }
+    }
+  };
+  const int nth = std::max(1, std::min(plan_threads(), n));
+  std::vector<std::thread> pool;
+  for (int k = 1; k < nth; ++k) pool.emplace_back(work);
+  work();
+  for (auto& th : pool) th.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+  return built;
+}
+
+// All plans of the DMRG-TDA sweeps (Fig. alg:dmrgtda) built up front on the
+// plan threads: per site the two first-order renormalizations of each sweep
+// direction (eqs. lopr1st, ropr1st) and the three sigmas (first-order left
+// part, zeroth order, first-order right part), against layout-only
+// first-order sets (their layouts depend only on bond and side).
+void Ctx::prebuild_tda_plans() {
+  std::vector<OpSet> fl(L + 1), fr(L + 1);
+  for (int b = 0; b <= L; ++b) {
+    alloc_opset(fl[b], b, 0, 0, true);
+    alloc_opset(fr[b], b, 1, 0, true);
+  }
+  for (int i = 0; i < L; ++i) {
+    layout(i, 1);
+    H->site_op(i, 1, H->mode_left(i), H->mode_left(i + 1));
+    H->site_op(i, 1, H->mode_right(i), H->mode_right(i + 1));
+    H->site_op(i, 1, H->mode_left(i), H->mode_right(i + 1));
+  }
+  typedef std::tuple<int, int, int, int> Key;
+  std::vector<std::function<std::unique_ptr<ContractionPlan>()>> fns;
+  std::vector<std::pair<int, Key>> dest;  // 0: renorm cache, 1: sigma cache
+  auto add_r = [&](int dir, int i, const OpSet& src, const OpSet& dst, bool bf) {
+    const Key k(dir, i, src.first_order ? 1 : 0, bf ? 1 : 0);
+    if (renorm_plans_.count(k)) return;
+    fns.push_back([this, dir, i, &src, &dst, bf]() { return make_renorm_plan(dir, i, src, dst, bf); });
+    dest.push_back({0, k});
+  };
+  auto add_s = [&](int i, const OpSet& X, const OpSet& Z, bool lf) {
+    const Key k(i, 1, (X.first_order ? 1 : 0) + (lf ? 2 : 0), Z.first_order ? 1 : 0);
+    if (sigma_plans_.count(k)) return;
+    fns.push_back([this, i, &X, &Z, lf]() { return make_sigma_plan(i, 1, X, Z, lf); });
+    dest.push_back({1, k});
+  };
+  for (int i = 0; i < L; ++i) {
+    add_s(i, fl[i], right[i + 1], false);
+    add_s(i, left[i], right[i + 1], false);
+    add_s(i, left[i], fr[i + 1], true);
+    if (i + 1 < L) {
+      add_r(DMRG_DIR_LEFT, i, fl[i], fl[i + 1], false);
+      add_r(DMRG_DIR_LEFT, i, left[i], fl[i + 1], true);
+    }
+    if (i > 0) {
+      add_r(DMRG_DIR_RIGHT, i, fr[i + 1], fr[i], false);
+      add_r(DMRG_DIR_RIGHT, i, right[i + 1], fr[i], true);
+    }
+  }
+  auto built = build_parallel(fns);
+  for (size_t t = 0; t < built.size(); ++t) {
+    if (dest[t].first == 0) renorm_plans_[dest[t].second] = std::move(built[t]);
+    else sigma_plans_[dest[t].second] = std::move(built[t]);
+  }
 }
 
 float* Ctx::f32_data(const OpSet& S) {

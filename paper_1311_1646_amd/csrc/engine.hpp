@@ -1,6 +1,9 @@
 // Context, operator sets and the contraction planners (host side).
 #pragma once
+#include <functional>
 #include <map>
+#include <thread>
+#include <mutex>
 #include <memory>
 #include <string>
 #include <tuple>
@@ -351,6 +354,8 @@ class Ctx {
                  int* iters, bool* converged);
   void response(const double* v, double omega, const dmrg_davidson_params& p, double* chi, double* resid2,
                 int* iters, bool* converged);
+  // all plans of the TDA sweeps, built on the plan threads
+  void prebuild_tda_plans();
   // ground state by two-site sweeps (ground.cpp); returns <Psi|H|Psi>
   void sweep_ground(const dmrg_sweep_params& p, double* energy, double* discarded, bool* converged);
   // replace the sectors of bond b (and its Schmidt values); drops every
@@ -363,10 +368,23 @@ class Ctx {
   std::unique_ptr<GaugeKit> kit_;
   std::map<std::pair<int, int>, std::unique_ptr<SiteLayout>> layouts_;
   std::map<std::tuple<int, int, int>, std::unique_ptr<OpLayout>> op_layouts_;
+  std::mutex op_layout_mu_;  // op_layout() is called from the plan threads
   std::map<std::tuple<int, int, int, int>, std::unique_ptr<ContractionPlan>> renorm_plans_;
   std::map<std::tuple<int, int, int, int>, std::unique_ptr<ContractionPlan>> sigma_plans_;
   std::map<std::pair<int, int>, std::unique_ptr<DiagPlan>> diag_plans_;
   ContractionPlan& renorm_plan(int dir, int i, const OpSet& src, const OpSet& dst, bool bra_first);
+  std::unique_ptr<ContractionPlan> make_renorm_plan(int dir, int i, const OpSet& src, const OpSet& dst,
+                                                   bool bra_first);
+  std::unique_ptr<ContractionPlan> make_sigma_plan(int i, int width, const OpSet& X, const OpSet& Z, bool left_first);
+  // runs plan builders on the plan threads (results in the order given)
+  std::vector<std::unique_ptr<ContractionPlan>> build_parallel(
+      const std::vector<std::function<std::unique_ptr<ContractionPlan>()>>& fns);
+  // host threads for plan construction: DMRG_PLAN_THREADS, else up to 16
+  static int plan_threads() {
+    if (const char* e = std::getenv("DMRG_PLAN_THREADS")) return std::max(1, std::atoi(e));
+    const unsigned h = std::thread::hardware_concurrency();
+    return int(std::min(16u, std::max(1u, h)));
+  }
   ContractionPlan& sigma_plan(int i, int width, const OpSet& X, const OpSet& Z, bool left_first = false);
   void clear_plans();
 };

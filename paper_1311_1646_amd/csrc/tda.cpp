@@ -699,6 +699,7 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
     DMRG_HIP(hipMemcpy(&E0_, tmpd_.p, 8, hipMemcpyDeviceToHost));
   }
   for (int i = 0; i < L_; ++i) x_.diag(i, 1, diag_[i].as<double>());
+  x_.prebuild_tda_plans();
   if (resp_) {
     // shifts of the +omega and -omega components (eqs. realresp, imagresp)
     std::vector<double> z(64, 0.0), nz(64, 0.0);
