@@ -9,7 +9,9 @@ oracle cannot run: properties that hold at any size.
 * Precision ladder: FP32 and BF16x3 sigmas agree with the FP64 sigma within
   the bounds derived in test_gpu_precision.
 * One-site vs two-site: projecting the two-site sigma of C_i R_{i+1} back
-  with R_{i+1} gives the one-site sigma of C_i."""
+  with R_{i+1} gives the one-site sigma of C_i.
+* One DMRG-TDA iteration (16 roots): symmetric reduced matrices, positive
+  definite S_R, FP32 Ritz values within the FP32 error of the FP64 ones."""
 import numpy as np
 import pytest
 
@@ -115,3 +117,37 @@ def test_two_site_sigma_projects_to_one_site_full_size(big):
     err = np.linalg.norm(proj - s1) / np.linalg.norm(s1)
     print(f"one-site vs projected two-site: {err:.2e}")
     assert err < 1e-12
+
+
+@pytest.mark.timeout(600)
+def test_tda_iteration_full_size_fp64_vs_fp32(big):
+    # One DMRG-TDA Davidson iteration (16 roots, 32 trial vectors, the bench
+    # launch) in FP64 and in FP32 from the same deterministic start: the
+    # reduced matrices H_R, S_R of eq. eigs are symmetric with S_R positive
+    # definite, and the Ritz values agree within the FP32 contraction error,
+    # which enters H_R to first order: |d omega| < 1e-5 |E| (FP32 relative
+    # error a few 2^-24 grown over sums of ~10^3 terms; measured 1.4e-7 |E|:
+    # 6.5e-5 Eh at |E| = 474 Eh)
+    p, mps, ctx = big
+    res = {}
+    for prec in (0, 1):
+        om, et, r2, it, conv = ctx.tda_roots(16, max_iter=1, tol=0.0, seed=7, prec=prec, polish=False)
+        HR, SR = ctx.tda_reduced()
+        assert it == 1 and HR.shape == (32, 32)
+        # rounding in H_R scales with |E| |x_mu| |x_nu| (norms from diag S_R)
+        nrm = np.sqrt(np.abs(np.diag(SR)))
+        scale = np.abs(et).max() * np.outer(nrm, nrm)
+        asym = np.abs(HR - HR.T) / scale
+        print(f"prec {prec}: max |H_R| {np.abs(HR).max():.3e}, max diag S_R {np.diag(SR).max():.3e}, "
+              f"|E| {np.abs(et).max():.1f}, asymmetry {asym.max():.2e} of |E||x||x|")
+        # FP64 measured 2.6e-16; FP32 contractions 2.0e-7 (FP32 rounding of
+        # the sigma parts that enter H_R)
+        assert asym.max() < {0: 1e-12, 1: 1e-5}[prec]
+        assert np.abs(SR - SR.T).max() < 1e-12 * np.abs(SR).max()
+        assert np.linalg.eigvalsh(0.5 * (SR + SR.T)).min() > 0
+        assert np.all(np.isfinite(om)) and np.all(np.diff(om) >= 0)
+        res[prec] = (om, et)
+    d = np.abs(res[1][0] - res[0][0])
+    print(f"one TDA iteration at M=1000: max |d omega| FP32 vs FP64 {d.max():.2e} Eh "
+          f"(|E| ~ {np.abs(res[0][1]).max():.1f})")
+    assert np.all(d < 1e-5 * np.abs(res[0][1]))
