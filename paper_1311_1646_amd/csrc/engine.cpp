@@ -682,13 +682,20 @@ const SiteLayout& Ctx::layout(int i, int width) {
 }
 
 const OpLayout* Ctx::op_layout(int bond, int dna, int dnb) {
-  std::lock_guard<std::mutex> lock(op_layout_mu_);
   auto key = std::make_tuple(bond, dna, dnb);
-  auto it = op_layouts_.find(key);
-  if (it != op_layouts_.end()) return it->second.get();
+  {
+    std::lock_guard<std::mutex> lock(op_layout_mu_);
+    auto it = op_layouts_.find(key);
+    if (it != op_layouts_.end()) return it->second.get();
+  }
+  // built outside the lock; a concurrent builder of the same key keeps the
+  // first entry
   auto O = std::make_unique<OpLayout>();
   build_op_layout(*O, bonds[bond], dna, dnb);
-  return (op_layouts_[key] = std::move(O)).get();
+  std::lock_guard<std::mutex> lock(op_layout_mu_);
+  auto& slot = op_layouts_[key];
+  if (!slot) slot = std::move(O);
+  return slot.get();
 }
 
 long Ctx::bond_offset(int b, int sector) const {
@@ -1284,18 +1291,20 @@ void Ctx::build_ops(int prec) {
   // all sets and plans first (host planning, timed apart), then the
   // renormalizations back to back on the stream
   const auto h0 = std::chrono::steady_clock::now();
-  for (int b = 0; b <= L; ++b) {
-    alloc_opset(left[b], b, 0, 1, false);
-    alloc_opset(right[b], b, 1, 1, false);
-  }
+  parallel_for(2 * (L + 1), [&](int t) {
+    const int b = t / 2;
+    if (t % 2 == 0) alloc_opset(left[b], b, 0, 1, false);
+    else alloc_opset(right[b], b, 1, 1, false);
+  });
   // the 2L plans are independent: built on a pool of host threads after the
   // shared lazily built objects they read (site layouts and site
   // operators) exist, then entered into the cache
-  for (int i = 0; i < L; ++i) {
-    layout(i, 1);
-    H->site_op(i, 1, H->mode_left(i), H->mode_left(i + 1));
-    H->site_op(i, 1, H->mode_right(i), H->mode_right(i + 1));
-  }
+  for (int i = 0; i < L; ++i) layout(i, 1);
+  parallel_for(2 * L, [&](int t) {
+    const int i = t / 2;
+    if (t % 2 == 0) H->site_op(i, 1, H->mode_left(i), H->mode_left(i + 1));
+    else H->site_op(i, 1, H->mode_right(i), H->mode_right(i + 1));
+  });
   {
     std::vector<std::function<std::unique_ptr<ContractionPlan>()>> fns;
     for (int i = 0; i < L; ++i)
@@ -1550,18 +1559,14 @@ std::unique_ptr<ContractionPlan> Ctx::make_sigma_plan(int i, int width, const Op
   return P;
 }
 
-std::vector<std::unique_ptr<ContractionPlan>> Ctx::build_parallel(
-    const std::vector<std::function<std::unique_ptr<ContractionPlan>()>>& fns) {
-  const int n = int(fns.size());
-  std::vector<std::unique_ptr<ContractionPlan>> built(n);
+void Ctx::parallel_for(int n, const std::function<void(int)>& fn) {
   std::vector<std::exception_ptr> err(n);
   std::atomic<int> next{0};
   auto work = [&]() {
-    // the current device is per host thread
     if (hipSetDevice(device) != hipSuccess) (void)hipGetLastError();
     for (int t = next++; t < n; t = next++) {
       try {
-        built[t] = fns[t]();
+        fn(t);
       } catch (...) {
         err[t] = std::current_exception();
       }
@@ -1574,6 +1579,43 @@ std::vector<std::unique_ptr<ContractionPlan>> Ctx::build_parallel(
   for (auto& th : pool) th.join();
   for (auto& e : err)
     if (e) std::rethrow_exception(e);
+}
+
+std::vector<std::unique_ptr<ContractionPlan>> Ctx::build_parallel(
+    const std::vector<std::function<std::unique_ptr<ContractionPlan>()>>& fns) {
+  const int n = int(fns.size());
+  std::vector<std::unique_ptr<ContractionPlan>> built(n);
+  std::vector<std::exception_ptr> err(n);
+  std::atomic<int> next{0};
+  std::vector<double> ms(n, 0.0);
+  auto work = [&]() {
+    // the current device is per host thread
+    if (hipSetDevice(device) != hipSuccess) (void)hipGetLastError();
+    for (int t = next++; t < n; t = next++) {
+      const auto t0 = std::chrono::steady_clock::now();
+      try {
+        built[t] = fns[t]();
+      } catch (...) {
+        err[t] = std::current_exception();
+      }
+      ms[t] = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+  };
+  const int nth = std::max(1, std::min(plan_threads(), n));
+  std::vector<std::thread> pool;
+  for (int k = 1; k < nth; ++k) pool.emplace_back(work);
+  work();
+  for (auto& th : pool) th.join();
+  for (auto& e : err)
+    if (e) std::rethrow_exception(e);
+  if (std::getenv("DMRG_PLAN_TIMING")) {
+    double sum = 0, mx = 0;
+    for (double v : ms) {
+      sum += v;
+      mx = std::max(mx, v);
+    }
+    std::fprintf(stderr, "[plan] %d plans on %d threads: %.1f ms of plan work, longest %.1f ms\n", n, nth, sum, mx);
+  }
   return built;
 }
 
@@ -1588,12 +1630,13 @@ void Ctx::prebuild_tda_plans() {
     alloc_opset(fl[b], b, 0, 0, true);
     alloc_opset(fr[b], b, 1, 0, true);
   }
-  for (int i = 0; i < L; ++i) {
-    layout(i, 1);
-    H->site_op(i, 1, H->mode_left(i), H->mode_left(i + 1));
-    H->site_op(i, 1, H->mode_right(i), H->mode_right(i + 1));
-    H->site_op(i, 1, H->mode_left(i), H->mode_right(i + 1));
-  }
+  for (int i = 0; i < L; ++i) layout(i, 1);
+  parallel_for(3 * L, [&](int t) {
+    const int i = t / 3, k = t % 3;
+    if (k == 0) H->site_op(i, 1, H->mode_left(i), H->mode_left(i + 1));
+    else if (k == 1) H->site_op(i, 1, H->mode_right(i), H->mode_right(i + 1));
+    else H->site_op(i, 1, H->mode_left(i), H->mode_right(i + 1));
+  });
   typedef std::tuple<int, int, int, int> Key;
   std::vector<std::function<std::unique_ptr<ContractionPlan>()>> fns;
   std::vector<std::pair<int, Key>> dest;  // 0: renorm cache, 1: sigma cache

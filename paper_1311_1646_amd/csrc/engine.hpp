@@ -376,6 +376,8 @@ class Ctx {
   std::unique_ptr<ContractionPlan> make_renorm_plan(int dir, int i, const OpSet& src, const OpSet& dst,
                                                    bool bra_first);
   std::unique_ptr<ContractionPlan> make_sigma_plan(int i, int width, const OpSet& X, const OpSet& Z, bool left_first);
+  // fn(0 .. n-1) on the plan threads (exceptions rethrown afterwards)
+  void parallel_for(int n, const std::function<void(int)>& fn);
   // runs plan builders on the plan threads (results in the order given)
   std::vector<std::unique_ptr<ContractionPlan>> build_parallel(
       const std::vector<std::function<std::unique_ptr<ContractionPlan>()>>& fns);

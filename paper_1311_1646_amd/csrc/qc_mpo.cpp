@@ -238,8 +238,13 @@ const BondChannels& QCHamiltonian::channels(int b, int mode) const {
 
 const SiteOp& QCHamiltonian::site_op(int b, int width, int m0, int m1) {
   const int64_t ck = int64_t(b) * 16 + width * 4 + m0 * 2 + m1;
-  auto it = cache_.find(ck);
-  if (it != cache_.end()) return it->second;
+  {
+    // built outside the lock; a concurrent builder of the same key keeps the
+    // first entry (element references stay valid across rehashing)
+    std::lock_guard<std::mutex> lock(cache_mu_);
+    auto it = cache_.find(ck);
+    if (it != cache_.end()) return it->second;
+  }
   if (width < 1 || width > 2 || b < 0 || b + width > L_ || m0 > m1) throw std::invalid_argument("bad dot");
   const BondChannels& B0 = channels(b, m0);
   const BondChannels& B1 = channels(b + width, m1);
@@ -327,6 +332,7 @@ const SiteOp& QCHamiltonian::site_op(int b, int width, int m0, int m1) {
     if (kv.second.c == 0.0) continue;
     op.e.push_back({std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), kv.second.c});
   }
+  std::lock_guard<std::mutex> lock(cache_mu_);
   return cache_.emplace(ck, std::move(op)).first->second;
 }
 

@@ -32,6 +32,7 @@
 #pragma once
 #include <cstdint>
 #include <string>
+#include <mutex>
 #include <unordered_map>
 #include <vector>
 
@@ -131,6 +132,7 @@ class QCHamiltonian {
   std::vector<DotString> strings_[2];
   std::unordered_map<int, int> string_index_[2];
   std::unordered_map<int64_t, SiteOp> cache_;
+  std::mutex cache_mu_;  // site_op() may be called from several plan threads
 
   void build_terms(const double* h, const double* eri, double screen);
   void build_channels();
