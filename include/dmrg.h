@@ -417,6 +417,10 @@ typedef struct {
                               gauge, reduced matrices), host waits            */
 } dmrg_stats;
 
+/* Metrics log: when the environment variable DMRG_LOG_JSONL names a file,
+ * dmrg_sweep_ground appends one JSON object per sweep ("ground_sweep") and
+ * dmrg_tda_roots / dmrg_response one per Davidson iteration
+ * ("tda_iteration" / "response_iteration"), one object per line. */
 int dmrg_get_stats(dmrg_ctx* ctx, dmrg_stats* out);
 /* sizeof(dmrg_stats) as compiled into the library, so that a binding can
  * check its own copy of the layout (host only, needs no context). */

@@ -548,6 +548,18 @@ void finish_two_stage(Ctx& x, TwoStageBuilder& B, TwoStagePlan& P, bool overwrit
 
 }  // namespace
 
+void log_jsonl(const std::string& json_object) {
+  const char* path = std::getenv("DMRG_LOG_JSONL");
+  if (!path || !*path) return;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lock(mu);
+  if (FILE* f = std::fopen(path, "a")) {
+    std::fputs(json_object.c_str(), f);
+    std::fputc('\n', f);
+    std::fclose(f);
+  }
+}
+
 void build_gemm_plan(Ctx& x, GemmPlan& P, std::vector<GJob>& jobs, std::vector<std::vector<GContrib>>& per,
                      const std::vector<int>& gather) {
   make_gemm_plan(x, P, jobs, per, gather);

@@ -236,6 +236,10 @@ struct FirstOrderChain {
   }
 };
 
+// Appends one JSON object as a line to the file named by DMRG_LOG_JSONL, if
+// set (per-sweep / per-iteration metrics of the drivers); thread-safe.
+void log_jsonl(const std::string& json_object);
+
 class SigmaGroup;
 
 class Ctx {

@@ -753,6 +753,7 @@ void Ground::run(double* energy, double* discarded, bool* converged) {
   build_right_ops();
   double e = 0, last = 0, dwmax = 0;
   for (int sw = 0; sw < p_.nsweeps; ++sw) {
+    const auto t0 = std::chrono::steady_clock::now();
     const int M = p_.M_schedule[sw];
     dwmax = 0;
     for (int i = 0; i + 1 < L; ++i) {
@@ -767,6 +768,15 @@ void Ground::run(double* energy, double* discarded, bool* converged) {
     }
     if (p_.verbose >= 1)
       std::fprintf(stderr, "[ground] sweep %d M %d E %.12f dE %.2e max discarded %.2e\n", sw, M, e, e - last, dwmax);
+    {
+      char buf[320];
+      std::snprintf(buf, sizeof buf,
+                    "{\"event\": \"ground_sweep\", \"sweep\": %d, \"M\": %d, \"energy\": %.15g, \"dE\": %.6g, "
+                    "\"max_discarded\": %.6g, \"prec\": %d, \"seconds\": %.4f}",
+                    sw, M, e, sw ? e - last : 0.0, dwmax, p_.prec,
+                    std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+      log_jsonl(buf);
+    }
     last = e;
   }
   final_pass();

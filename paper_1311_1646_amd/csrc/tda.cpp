@@ -790,6 +790,26 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
       x_.stats.tda_hist_len = it;
     }
     if (polishing) x_.stats.tda_polish_iters = ++polish_iters;
+    {
+      std::string js = resp_ ? "{\"event\": \"response_iteration\"" : "{\"event\": \"tda_iteration\"";
+      char buf[512];
+      std::snprintf(buf, sizeof buf,
+                    ", \"iteration\": %d, \"trial_vectors\": %d, \"max_r2\": %.6g, \"%s\": %.15g, \"%s\": %.15g, "
+                    "\"prec\": %d, \"fp64_polish\": %s, \"ms\": %.3f",
+                    it, l, mx, resp_ ? "chi_plus" : "omega0", resp_ ? chi_[0] : w[0] - E0_,
+                    resp_ ? "chi_minus" : "E0", resp_ ? chi_[1] : E0_, prec_, polishing ? "true" : "false",
+                    x_.stats.tda_iter_ms);
+      js += buf;
+      if (pc_.on) {
+        const double* a = pc_.acc;
+        std::snprintf(buf, sizeof buf,
+                      ", \"phase_ms\": {\"sigma1\": %.3f, \"sigma0\": %.3f, \"ren11\": %.3f, \"ren01\": %.3f, "
+                      "\"vec\": %.3f, \"host\": %.3f}",
+                      a[0], a[1], a[2], a[3], a[4], a[5]);
+        js += buf;
+      }
+      log_jsonl(js + "}");
+    }
     if (p_.verbose) {
       const double* a = pc_.acc;
       std::fprintf(stderr,

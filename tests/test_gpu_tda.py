@@ -88,3 +88,25 @@ def test_tda_low_precision_with_chunked_workspace(prec, monkeypatch):
     assert conv, (it, r2)
     np.testing.assert_allclose(et, ref, atol=1e-5)
     np.testing.assert_allclose(om, ref - E0, atol=1e-5)
+
+
+def test_jsonl_metrics_log(tmp_path, monkeypatch):
+    # DMRG_LOG_JSONL: one JSON line per ground-state sweep and per Davidson
+    # iteration, consistent with what the calls return
+    import json
+
+    import paper_1311_1646_amd as lib
+    path = tmp_path / "metrics.jsonl"
+    monkeypatch.setenv("DMRG_LOG_JSONL", str(path))
+    L, Na, Nb = 6, 3, 3
+    h, eri, _ = synth.random_integrals(L, seed=11, K=6, diag_lo=-2, diag_hi=0)
+    ctx = lib.Context(L, Na, Nb, h, eri, 0.0, device=0)
+    e, dw, _ = ctx.sweep_ground([16, 16, 16], davidson_tol=1e-12, davidson_max_iter=40, seed=1)
+    om, et, r2, it, conv = ctx.tda_roots(2, max_iter=60, tol=1e-10, seed=3)
+    rows = [json.loads(x) for x in path.read_text().splitlines()]
+    sweeps = [r for r in rows if r["event"] == "ground_sweep"]
+    iters = [r for r in rows if r["event"] == "tda_iteration"]
+    assert [r["sweep"] for r in sweeps] == [0, 1, 2] and all(r["M"] == 16 for r in sweeps)
+    assert abs(sweeps[-1]["energy"] - e) < 1e-6
+    assert conv and [r["iteration"] for r in iters] == list(range(1, it + 1))
+    assert iters[-1]["max_r2"] < 1e-10 and abs(iters[-1]["omega0"] - om[0]) < 1e-10
