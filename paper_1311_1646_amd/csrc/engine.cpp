@@ -278,7 +278,7 @@ struct LinCombBuilder {
             c[k] += s[j].c;
           }
         }
-        LCGroup G{kv.first, int(tg.size()), n, int(us.size()), 0};
+        LCGroup G{kv.first, int(tg.size()), n, int(us.size()), 0, 0};
         for (int k = 0; k < n; ++k) tg.push_back(t[v[g0 + k]]);
         for (auto& u : uni) {
           us.push_back({u.first.second, u.first.first, 0, 0.0});
@@ -604,9 +604,10 @@ void print_plan_stats(const char* what, int i, int width, const ContractionPlan&
   }
   std::fprintf(stderr,
                "[plan] %s site %d width %d: form targets %d elems %.3g reads %.3g | chunks %zu | stage1 jobs %ld "
-               "kchunks %ld flops %.3g | stage2 jobs %ld contribs %ld kchunks %ld max/job %ld flops %.3g | post "
-               "targets %d reads %.3g\n",
-               what, i, width, P.form.nt, P.form.elems, P.form.reads, P.main.chunks.size(), jobs1, kc1, P.main.flops1,
+               "contribs %ld kchunks %ld flops %.3g | stage2 jobs %ld contribs %ld kchunks %ld max/job %ld flops %.3g | "
+               "post targets %d reads %.3g\n",
+               what, i, width, P.form.nt, P.form.elems, P.form.reads, P.main.chunks.size(), jobs1, con1, kc1,
+               P.main.flops1,
                jobs2, con2, kc2, kmax2, P.main.flops2, P.post.nt, P.post.reads);
 }
 
@@ -964,7 +965,7 @@ void emit_formation(LinCombBuilder& lc, const ORef& out, const Sources& srcs) {
   if (cid != 0.0) {
     DMRG_REQUIRE(out.lay->dna == 0 && out.lay->dnb == 0, DMRG_ERR_INTERNAL, "identity in a shifted class");
     for (auto& b : out.lay->blk)
-      if (b.ket == b.bra) lc.d.push_back({out.off + long(b.off), out.base, b.rows, cid});
+      if (b.ket == b.bra) lc.d.push_back({out.off + long(b.off), out.base, b.rows, cid, 0});
   }
 }
 

@@ -368,7 +368,6 @@ class TdaRunner {
   double E0_ = 0;
   PhaseClock pc_;
   int lcur_last_ = 0;  // size of the reduced matrices of the last forward sweep
-  int polish_from_ = 0, polish_to_ = -1;
   std::vector<double> hw_;  // host copy of Ritz values
   // response mode: right-hand sides, frequency, b_R = <trial | V Psi0>, the
   // coefficients of x_pm in the Ritz basis, the shifts z_pm, and the site
@@ -721,8 +720,6 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
   bool conv = false;
   int it = 0;
   std::vector<double> w(64), last_w(n_, 0.0);
-  double tda_flops0 = 0;
-  (void)tda_flops0;
   // FP32 and BF16x3 runs end with FP64 iterations, switched on near the
   // residual floor of their contractions: a relative error eps on sigma
   // vectors of size ~|E0| at each of the L sites gives sum_i |r_i|^2 ~
@@ -733,8 +730,6 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
   // the contraction error of H_R, so only FP64 iterations reach the 1e-5 Eh
   // scale when |E0| is hundreds of Eh.
   const bool can_polish = prec_ != DMRG_FP64 && p_.polish == 0;
-  polish_from_ = prec_;
-  polish_to_ = -1;
   bool polishing = false;
   int polish_iters = 0, stall = 0;
   double best = 1e300;
@@ -829,7 +824,6 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
       if (done || mx < floor_est || (stall >= 4 && mx < 100.0 * floor_est)) {
         polishing = true;
         prec_ = DMRG_FP64;
-        polish_to_ = DMRG_FP64;
         done = false;
       }
     }
