@@ -132,3 +132,30 @@ def test_chunked_workspace_gives_identical_sigma_at_every_site(monkeypatch):
     for i in range(L):
         a, b = outs[0][i], outs[1][i]
         assert np.abs(a - b).max() < 1e-13 * np.abs(a).max(), i
+
+
+def test_plans_built_on_threads_give_identical_results(monkeypatch):
+    # the contraction plans of build_ops and of the TDA sweeps are built on a
+    # pool of host threads; built on one thread they must give bit-identical
+    # sigmas and TDA roots
+    import paper_1311_1646_amd as lib
+    L, Na, Nb = 8, 4, 4
+    h, eri, _ = synth.random_integrals(L, seed=21, K=8, diag_lo=-2, diag_hi=0)
+    mps = synth.random_mps(L, Na, Nb, 48, seed=22)
+    res = []
+    for threads in ("1", "16"):
+        monkeypatch.setenv("DMRG_PLAN_THREADS", threads)
+        ctx = lib.Context(L, Na, Nb, h, eri, 0.0, device=0)
+        ctx.import_mps(*mps_arrays(mps))
+        ctx.build_ops()
+        rng = np.random.default_rng(1)
+        sig = []
+        for i in range(L):
+            C = torch.tensor(rng.normal(size=(2, mps.site_size(i))), device="cuda")
+            sig.append(ctx.sigma(i, C).cpu().numpy())
+        om, et, r2, it, conv = ctx.tda_roots(2, max_iter=40, tol=1e-10, seed=3)
+        res.append((sig, om, it))
+        ctx.close()
+    for a, b in zip(res[0][0], res[1][0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(res[0][1], res[1][1]) and res[0][2] == res[1][2]
