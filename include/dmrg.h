@@ -348,6 +348,18 @@ int dmrg_group_destroy(dmrg_group* g);
  * and sleft2, summed over sites) of the last forward sweep of the last
  * dmrg_tda_roots, l x l row-major FP64 on the host.  With NULL HR / SR only
  * l is returned.  Errors: STATE before a TDA run. */
+/* DMRG-TDA roots (as dmrg_tda_roots, same arguments and errors) and their
+ * one-particle transition density matrices (Sec. VI A)
+ *   gamma^nu_pq = <Psi^nu | E_pq | Psi0>,  E_pq = sum_sigma a+_{p sigma} a_{q sigma},
+ * for the nroots roots Psi^nu (unit norm in the tangent space, orthogonal
+ * to Psi0; the overall sign of each root is arbitrary).  gamma: host array
+ * of nroots * L * L doubles, gamma[(nu L + p) L + q].  Cost: after the TDA,
+ * L^2 evaluations of E_pq Psi0 projected on every site (each the zeroth-order
+ * sigma of a one-body operator on the same MPS), meant for the diagnostic
+ * sum_pq gamma_pq^2 on small and medium systems. */
+int dmrg_tda_transition(dmrg_ctx* ctx, int nroots, const dmrg_davidson_params* p, double* omega,
+                        double* e_total, double* resid2, int* iters, double* gamma);
+
 /* Frequency-dependent linear response to a one-body perturbation
  * V = sum_pq v_pq E_pq (E_pq the spin-summed excitation operator), Sec. II B,
  * eqs. realresp and imagresp: the first-order wavefunctions of the +omega

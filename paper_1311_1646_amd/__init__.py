@@ -106,6 +106,7 @@ if _stats_size() != ctypes.sizeof(Stats):
     raise ImportError(f"dmrg_stats layout mismatch: library {_stats_size()} bytes, binding {ctypes.sizeof(Stats)}")
 _tda_reduced = _sig("dmrg_tda_reduced", _P, _IP, _DP, _DP)
 _response = _sig("dmrg_response", _P, _DP, _D, ctypes.POINTER(DavidsonParams), _DP, _DP, _IP)
+_tda_transition = _sig("dmrg_tda_transition", _P, _I, ctypes.POINTER(DavidsonParams), _DP, _DP, _DP, _IP, _DP)
 _debug_dense = _sig("dmrg_debug_mpo_dense", _P, _I, _I, _DP)
 _group_create = _sig("dmrg_group_create", _P, _I, _IP, _I, _I, ctypes.POINTER(_P))
 _group_sigma = _sig("dmrg_group_sigma", _P, _P, _P, _SP, _I)
@@ -363,6 +364,30 @@ class Context:
         if rc not in (0, -3):
             self._check(rc)
         return om, et, r2, it.value, rc == 0
+
+    def tda_transition(self, nroots, max_iter=60, max_space=0, tol=1e-9, seed=7, prec=FP64, verbose=0, polish=True,
+                       guess="diag"):
+        """DMRG-TDA roots and their transition densities (see
+        dmrg_tda_transition): returns (omega, e_total, resid2, iterations,
+        converged, gamma) with gamma[nu, p, q] = <Psi^nu | E_pq | Psi0>."""
+        if guess not in ("diag", "random"):
+            raise ValueError("guess must be 'diag' or 'random'")
+        p = DavidsonParams(max_iter, max_space, tol, seed, prec, verbose, 0 if polish else -1,
+                           0 if guess == "diag" else 1)
+        om = np.zeros(nroots)
+        et = np.zeros(nroots)
+        r2 = np.zeros(nroots)
+        gamma = np.zeros((nroots, self.L, self.L))
+        it = ctypes.c_int()
+        if self._alloc is not None and max_space == 0:
+            import torch
+            torch.cuda.synchronize(self.device)
+            torch.cuda.empty_cache()
+        rc = _tda_transition(self._h, nroots, ctypes.byref(p), _dp(om), _dp(et), _dp(r2), ctypes.byref(it),
+                             _dp(gamma))
+        if rc not in (0, -3):
+            self._check(rc)
+        return om, et, r2, it.value, rc == 0, gamma
 
     def response(self, v, omega, max_iter=80, max_space=0, tol=1e-10, prec=FP64, verbose=0, polish=True):
         """Linear response to the one-body perturbation V = sum_pq v_pq E_pq at

@@ -235,6 +235,23 @@ int dmrg_tda_roots(dmrg_ctx* ctx, int nroots, const dmrg_davidson_params* p, dou
   return rc;
 }
 
+int dmrg_tda_transition(dmrg_ctx* ctx, int nroots, const dmrg_davidson_params* p, double* omega, double* e_total,
+                        double* resid2, int* iters, double* gamma) {
+  bool conv = false;
+  int rc = guard(ctx, [&](dmrg::Ctx& x) {
+    DMRG_REQUIRE(p, DMRG_ERR_INVALID_ARG, "null parameters");
+    DMRG_REQUIRE(valid_prec(p->prec), DMRG_ERR_INVALID_ARG, "unsupported precision");
+    DMRG_REQUIRE(p->polish == 0 || p->polish == -1, DMRG_ERR_INVALID_ARG, "polish must be 0 or -1");
+    DMRG_REQUIRE(p->guess == 0 || p->guess == 1, DMRG_ERR_INVALID_ARG, "guess must be 0 or 1");
+    x.tda_transition(nroots, *p, omega, e_total, resid2, iters, &conv, gamma);
+  });
+  if (rc == DMRG_OK && !conv) {
+    ctx->x->err = "Davidson iteration limit reached";
+    return DMRG_ERR_NOT_CONVERGED;
+  }
+  return rc;
+}
+
 int dmrg_response(dmrg_ctx* ctx, const double* v, double omega, const dmrg_davidson_params* p, double* chi,
                   double* resid2, int* iters) {
   bool conv = false;

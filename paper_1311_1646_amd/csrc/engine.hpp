@@ -240,6 +240,12 @@ struct FirstOrderChain {
 // set (per-sweep / per-iteration metrics of the drivers); thread-safe.
 void log_jsonl(const std::string& json_object);
 
+// Host copy of an MPS in the import / export format.
+struct MpsHostCopy {
+  std::vector<int> nsec, sec;
+  std::vector<double> L, R, C, lam;
+};
+
 class SigmaGroup;
 
 class Ctx {
@@ -358,6 +364,11 @@ class Ctx {
                  int* iters, bool* converged);
   void response(const double* v, double omega, const dmrg_davidson_params& p, double* chi, double* resid2,
                 int* iters, bool* converged);
+  void export_host(MpsHostCopy& m);
+  void onebody_rhs(const double* v, const MpsHostCopy& m, double* rhs, const std::vector<long>& off);
+  // DMRG-TDA roots and their one-particle transition densities
+  void tda_transition(int nroots, const dmrg_davidson_params& p, double* omega, double* etot, double* resid2,
+                      int* iters, bool* converged, double* gamma);
   // all plans of the TDA sweeps, built on the plan threads
   void prebuild_tda_plans();
   // ground state by two-site sweeps (ground.cpp); returns <Psi|H|Psi>

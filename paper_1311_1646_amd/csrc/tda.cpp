@@ -353,6 +353,15 @@ class TdaRunner {
   void run(double* omega, double* etot, double* resid2, int* iters, bool* converged);
   // response mode: <V Psi0 | Psi1_pm> of the last iteration
   double chi(int k) const { return chi_[k]; }
+  // after run(): out[nu] = <Psi^nu | v> for the n roots of the last
+  // iteration, v given by its site projections P_i^T v (rhs[i]); the roots'
+  // left-gauge components are the first n trial vectors of the last forward
+  // sweep (S_R-orthonormal Ritz vectors, unit norm)
+  void root_overlaps(const std::vector<const double*>& rhs, double* out) {
+    for (int i = 0; i < L_; ++i)
+      gram(Ct_[i].as<double>(), size(i), n_, rhs[i], size(i), 1, size(i), tmpd_.as<double>(), 1, 1.0, i > 0);
+    DMRG_HIP(hipMemcpy(out, tmpd_.p, size_t(n_) * 8, hipMemcpyDeviceToHost));
+  }
 
  private:
   Ctx& x_;
@@ -1011,6 +1020,69 @@ void Ctx::tda_roots(int nroots, const dmrg_davidson_params& p, double* omega, do
   release_workspaces();
 }
 
+void Ctx::export_host(MpsHostCopy& m) {
+  size_t sz[4] = {0, 0, 0, 0};
+  export_mps(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, sz);
+  m.nsec.assign(L + 1, 0);
+  m.sec.assign(3 * sz[0], 0);
+  m.L.assign(sz[1], 0.0);
+  m.R.assign(sz[1], 0.0);
+  m.C.assign(sz[1], 0.0);
+  m.lam.assign(sz[3], 0.0);
+  export_mps(m.nsec.data(), m.sec.data(), m.L.data(), m.R.data(), m.C.data(), m.lam.data(), sz);
+}
+
+// V Psi0 projected on every site, P_i^T V Psi0 (flat one-site layouts at the
+// offsets off[i]), for the one-body operator V = sum_pq v_pq E_pq (v need not
+// be symmetric): the zeroth-order sigma of a second context that holds V
+// (no two-body part) on the same MPS, applied to C_i^(0).
+void Ctx::onebody_rhs(const double* v, const MpsHostCopy& m, double* rhs, const std::vector<long>& off) {
+  const std::vector<double> zero(size_t(L) * L * L * L, 0.0);
+  Ctx vc(L, Na, Nb, v, zero.data(), 0.0, device, stream, &allocator);
+  vc.import_mps(m.nsec.data(), m.sec.data(), m.L.data(), m.R.data(), m.C.data(), m.lam.data());
+  vc.build_ops(DMRG_FP64);
+  for (int i = 0; i < L; ++i) vc.sigma(i, 1, 1, site[i].C.as<double>(), rhs + off[i], DMRG_FP64);
+  vc.sync();
+}
+
+// DMRG-TDA roots and their one-particle transition densities
+// gamma^nu_pq = <Psi^nu | E_pq | Psi0> (E_pq the spin-summed excitation
+// operator; Sec. VI A): the TDA run of dmrg_tda_roots, then for every (p, q)
+// the site projections of E_pq Psi0 contracted with the roots' left-gauge
+// components.  gamma[(nu L + p) L + q].
+void Ctx::tda_transition(int nroots, const dmrg_davidson_params& p, double* omega, double* etot, double* resid2,
+                         int* iters, bool* converged, double* gamma) {
+  require_gpu();
+  DMRG_REQUIRE(ops_prec >= 0, DMRG_ERR_STATE, "call dmrg_build_ops first");
+  DMRG_REQUIRE(omega && etot && resid2 && iters && converged && gamma, DMRG_ERR_INVALID_ARG, "null outputs");
+  DMRG_REQUIRE(p.max_iter >= 1, DMRG_ERR_INVALID_ARG, "max_iter must be >= 1");
+  sync();
+  for (auto& f : fo_chain) f.reset();
+  std::vector<long> off(L + 1, 0);
+  for (int i = 0; i < L; ++i) off[i + 1] = off[i] + layout(i, 1).size;
+  MpsHostCopy mc;
+  export_host(mc);
+  DBuf rhs;
+  rhs.alloc(this, size_t(std::max<long>(off[L], 1)) * 8);
+  std::vector<const double*> ptr;
+  for (int i = 0; i < L; ++i) ptr.push_back(rhs.as<double>() + off[i]);
+  {
+    TdaRunner r(*this, nroots, p);
+    r.run(omega, etot, resid2, iters, converged);
+    std::vector<double> e(size_t(L) * L, 0.0), ov(nroots);
+    for (int a = 0; a < L; ++a)
+      for (int b = 0; b < L; ++b) {
+        std::fill(e.begin(), e.end(), 0.0);
+        e[size_t(a) * L + b] = 1.0;
+        onebody_rhs(e.data(), mc, rhs.as<double>(), off);
+        r.root_overlaps(ptr, ov.data());
+        for (int nu = 0; nu < nroots; ++nu) gamma[(size_t(nu) * L + a) * L + b] = ov[nu];
+      }
+  }
+  sync();
+  release_workspaces();
+}
+
 // Frequency-dependent linear response to a one-body perturbation
 // V = sum_pq v_pq E_pq (Sec. II B, eqs. realresp and imagresp; first-order
 // wavefunction of eq. psi1st in the gauge of eqs. left-orthoSeb and
@@ -1041,19 +1113,9 @@ void Ctx::response(const double* v, double omega, const dmrg_davidson_params& p,
   for (int i = 0; i < L; ++i) off[i + 1] = off[i] + layout(i, 1).size;
   DBuf rhs;
   rhs.alloc(this, size_t(std::max<long>(off[L], 1)) * 8);
-  {
-    size_t sz[4] = {0, 0, 0, 0};
-    export_mps(nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, sz);
-    std::vector<int> nsec(L + 1), sec(3 * sz[0]);
-    std::vector<double> Ld(sz[1]), Rd(sz[1]), Cd(sz[1]), lamd(sz[3]);
-    export_mps(nsec.data(), sec.data(), Ld.data(), Rd.data(), Cd.data(), lamd.data(), sz);
-    const std::vector<double> zero(size_t(L) * L * L * L, 0.0);
-    Ctx vc(L, Na, Nb, v, zero.data(), 0.0, device, stream, &allocator);
-    vc.import_mps(nsec.data(), sec.data(), Ld.data(), Rd.data(), Cd.data(), lamd.data());
-    vc.build_ops(DMRG_FP64);
-    for (int i = 0; i < L; ++i) vc.sigma(i, 1, 1, site[i].C.as<double>(), rhs.as<double>() + off[i], DMRG_FP64);
-    vc.sync();
-  }
+  MpsHostCopy mc;
+  export_host(mc);
+  onebody_rhs(v, mc, rhs.as<double>(), off);
   ResponseSpec rs;
   rs.omega = omega;
   for (int i = 0; i < L; ++i) rs.rhs.push_back(rhs.as<double>() + off[i]);
