@@ -49,3 +49,24 @@ def test_invalid_arguments_raise():
         ctx.debug_mpo_dense(7)
     with pytest.raises(lib.DMRGError):
         ctx.build_ops()   # host-only context refuses device work
+
+
+@pytest.mark.parametrize("L", [3, 4])
+def test_nonsymmetric_one_body_operator_factorizes_exactly(L):
+    # the transition densities use contexts that hold a single E_pq (or any
+    # non-symmetric one-body matrix): its channel factorization must equal the
+    # Fock-space operator sum_pq v_pq a+_p a_q (spin-summed)
+    rng = np.random.default_rng(L)
+    v = rng.normal(size=(L, L))
+    zero = np.zeros((L,) * 4)
+    cases = [v]
+    for p, q in ((0, L - 1), (L - 1, 0), (1, 1)):
+        e = np.zeros((L, L))
+        e[p, q] = 1.0
+        cases.append(e)
+    for m in cases:
+        ctx = lib.Context(L, L // 2, L - L // 2, m, zero, 0.0, device=-1)
+        Hf = fock.fock_hamiltonian(m, zero, 0.0)
+        for wide in [-1] + list(range(L - 1)):
+            for right in (False, True):
+                assert np.abs(ctx.debug_mpo_dense(wide, right) - Hf).max() < 1e-12
