@@ -440,34 +440,57 @@ void TdaRunner::response_step(int lcur, int rank, int m, std::vector<double>& w)
   const double z[2] = {E0_ - omega_, E0_ + omega_};
   // b_k = <y_k | V Psi0> for the S_R-orthonormal Ritz vectors y_k (columns of
   // alpha); in that basis (H_R - z S_R) a = -b_R is diagonal:
-  // c_k = -b_k / (w_k - z)
+  // c_k = -b_k / (w_k - z); x_pm = sum_k c_k y_k over all of them
   std::vector<double> b(rank, 0.0), c(size_t(rank) * 2);
+  chi_[0] = chi_[1] = 0;
   for (int k = 0; k < rank; ++k) {
     for (int u = 0; u < lcur; ++u) b[k] += al[u + size_t(k) * lcur] * br[u];
-    for (int v = 0; v < 2; ++v) c[k + size_t(v) * rank] = -b[k] / (w[k] - z[v]);
+    for (int v = 0; v < 2; ++v) {
+      c[k + size_t(v) * rank] = -b[k] / (w[k] - z[v]);
+      chi_[v] += b[k] * c[k + size_t(v) * rank];
+    }
   }
+  // Ritz vectors by their weight in x_pm
   std::vector<int> ord(rank);
   for (int k = 0; k < rank; ++k) ord[k] = k;
   std::stable_sort(ord.begin(), ord.end(), [&](int p, int q) {
     return std::abs(c[p]) + std::abs(c[p + rank]) > std::abs(c[q]) + std::abs(c[q + rank]);
   });
-  std::vector<double> al2(al), w2(w), cm(size_t(m) * 2);
-  chi_[0] = chi_[1] = 0;
-  for (int j = 0; j < rank; ++j) {
-    const int k = ord[j];
-    for (int u = 0; u < lcur; ++u) al2[u + size_t(j) * lcur] = al[u + size_t(k) * lcur];
-    w2[j] = w[k];
-    if (j < m) {
-      for (int v = 0; v < 2; ++v) {
-        cm[j + size_t(v) * m] = c[k + size_t(v) * rank];
-        chi_[v] += b[k] * c[k + size_t(v) * rank];
+  std::vector<double> al2(size_t(lcur) * lcur, 0.0), w2(w), cm(size_t(m) * 2, 0.0);
+  if (m >= rank) {
+    // the whole Ritz basis is kept: x_pm by their coefficients
+    for (int j = 0; j < rank; ++j) {
+      const int k = ord[j];
+      for (int u = 0; u < lcur; ++u) al2[u + size_t(j) * lcur] = al[u + size_t(k) * lcur];
+      w2[j] = w[k];
+      for (int v = 0; v < 2; ++v) cm[j + size_t(v) * m] = c[k + size_t(v) * rank];
+    }
+  } else {
+    // restart: the kept space holds x_pm themselves (first columns, so the
+    // current solution survives the restart exactly) and the m - 2 (or
+    // m - 1 when x_+ = x_-, at omega = 0) Ritz vectors of largest weight
+    int col = 0;
+    for (int v = 0; v < 2; ++v) {
+      if (v == 1 && omega_ == 0.0) break;
+      for (int u = 0; u < lcur; ++u) {
+        double a = 0;
+        for (int k = 0; k < rank; ++k) a += al[u + size_t(k) * lcur] * c[k + size_t(v) * rank];
+        al2[u + size_t(col) * lcur] = a;
       }
+      cm[col + size_t(v) * m] = 1.0;
+      ++col;
+    }
+    if (omega_ == 0.0) cm[0 + size_t(1) * m] = 1.0;
+    for (int j = 0; col < m && j < rank; ++j, ++col) {
+      const int k = ord[j];
+      for (int u = 0; u < lcur; ++u) al2[u + size_t(col) * lcur] = al[u + size_t(k) * lcur];
+      w2[col] = w[k];
     }
   }
   w = w2;
   if (p_.verbose >= 1) {
     double dmin[2] = {1e300, 1e300};
-    for (int k = 0; k < m; ++k)
+    for (int k = 0; k < rank; ++k)
       for (int v = 0; v < 2; ++v) dmin[v] = std::min(dmin[v], std::abs(w[k] - z[v]));
     std::fprintf(stderr, "[response] rank %d kept %d chi %.12f %.12f  min|w-z| %.3e %.3e\n", rank, m, chi_[0],
                  chi_[1], dmin[0], dmin[1]);

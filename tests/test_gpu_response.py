@@ -62,6 +62,22 @@ def test_ground_state_response_below_the_first_excitation(ground8):
     _check(ctx, mps, dets, H, _v(p.L, 5), p.Na, p.Nb, [0.0, 0.3 * w1, 0.6 * w1])
 
 
+def test_ground_state_response_through_restarts(ground8):
+    # a 10-vector space restarts every few iterations; the restarted space
+    # keeps the current solutions x_pm themselves, so the solve still
+    # converges to the oracle's
+    p, ctx, mps, dets, H, w1 = ground8
+    v = _v(p.L, 5)
+    V = response.onebody(v, p.Na, p.Nb)
+    om = 0.3 * w1
+    cp, cm, r2, it, conv = ctx.response(v, om, max_iter=400, max_space=10, tol=1e-11)
+    rp, rm = response.response(mps, dets, H, V, om)
+    print(f"restarted (space 10): chi+ {cp:.12f} ({rp:.12f}) chi- {cm:.12f} ({rm:.12f}) in {it} iterations")
+    assert conv, (it, r2)
+    assert ctx.stats()["tda_space"] == 10
+    assert abs(cp - rp) < 1e-8 * max(1.0, abs(rp)) and abs(cm - rm) < 1e-8 * max(1.0, abs(rm))
+
+
 @pytest.mark.parametrize("prec", [1, 2])
 def test_ground_state_response_low_precision_with_polish(ground8, prec):
     # FP32 / BF16x3 contractions finish with FP64 polish iterations, as in the TDA
