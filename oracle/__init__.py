@@ -15,6 +15,12 @@ library computes, written from the paper's definitions:
              tangent space with the reference removed (Sec. II C-D);
   firstorder.py  first-order MPS wavefunctions in the mixed gauge (Sec. II B)
              and the TDA sigma P_i^T H Psi1 (Sec. III D, eqs. sigv1, sigv2).
+  response.py    frequency-dependent linear response in the tangent space
+             (Sec. II B, eqs. realresp, imagresp);
+  transition.py  one-particle transition densities of the TDA roots (Sec. VI A);
+  rpa.py     DMRG-RPA: the second-order matrix W of the non-redundant
+             mixed-canonical parameterization (Sec. II C-D, eq. bmatrix) and
+             the RPA roots (eqs. dmrgrpa, reducedrpa).
 
 Only tests/, the smoke check in __graft_entry__.py and the cpu_baseline leg
 of bench.py may import this package.  The GPU library never does, and this
