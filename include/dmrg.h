@@ -385,6 +385,50 @@ int dmrg_tda_transition(dmrg_ctx* ctx, int nroots, const dmrg_davidson_params* p
 int dmrg_response(dmrg_ctx* ctx, const double* v, double omega, const dmrg_davidson_params* p, double* chi,
                   double* resid2, int* iters);
 
+/* DMRG-RPA roots (Sec. II C eq. dmrgrpa; Sec. III E eqs. reducedrpa and
+ * bmatrix) of the current MPS, which is taken to be a stationary point of
+ * the energy on the MPS manifold (a converged ground state).  The Davidson
+ * sweeps of dmrg_tda_roots run over trial first-order wavefunctions U; the
+ * reduced matrices are H_R and S_R of eqs. hleft2 / sleft2 and the
+ * second-order matrix W_R = W(U, U), accumulated in the backward sweep from
+ * the left-gauge pieces of one vector and the first-order right block
+ * states of the other (eq. bmatrix, both orders); the forward and backward
+ * amplitudes are X = U a, Y = U b and the reduced problem
+ *   [[A, W_R], [W_R, A]] (a, b) = omega [[S_R, 0], [0, -S_R]] (a, b),
+ *   A = H_R - E0 S_R,
+ * is solved on the host after canonical orthogonalization of S_R, through
+ * the symmetric form of (A - W)(A + W).  Per root two residuals are formed
+ * at every site: r_X = (H - E0 - omega) X + W Y and
+ * r_Y = (H - E0 + omega) Y + W X, with the site-i part of W v taken as
+ * <U_v n r|H|Psi0> + <l n V_v|H|Psi0> (U_v, V_v the first-order left /
+ * right block states of v, first-order operator chains with the
+ * first-order tensor on the bra side); this is the exact gradient of W at
+ * a stationary reference.  Both corrections join the space, so it grows by
+ * 2 nroots vectors per iteration (max_space >= 4 nroots); a full space
+ * keeps X and Y of the lowest roots.  p: as for dmrg_tda_roots (guess 0:
+ * unit vectors on the 2 nroots lowest diagonal elements of the middle
+ * site).  omega receives the nroots lowest RPA excitation energies, e_total
+ * E0 + omega, resid2 per root the larger of max sum_i |r_i|^2 of its X and
+ * Y residuals.  NOT_CONVERGED fills the outputs of the last iteration.
+ * Errors: STATE before build_ops, INVALID_ARG (parameters), SINGULAR (the
+ * trial space lost rank below nroots, or A - W / A + W is not positive
+ * definite on it: an unstable reference). */
+int dmrg_rpa_roots(dmrg_ctx* ctx, int nroots, const dmrg_davidson_params* p, double* omega, double* e_total,
+                   double* resid2, int* iters);
+
+/* The reduced DMRG-RPA problem of eq. reducedrpa alone, on the host (no
+ * context, no device): HR, SR, WR are l x l symmetric host arrays (the
+ * matrices of dmrg_rpa_roots over l trial vectors), e0 the reference
+ * energy.  Writes the nroots lowest roots omega_out[nroots] and, when x_out
+ * / y_out are not NULL, the amplitudes a (x_out) and b (y_out) of each root
+ * in the trial basis (l x nroots, column k = root k, element u + k*l),
+ * normalized to a^T S_R a - b^T S_R b = 1.  Directions with S_R eigenvalue
+ * below 1e-10 of the largest are dropped.  Returns the rank kept, or
+ * INVALID_ARG (l < 1, l > 4096, null inputs) or SINGULAR (rank below nroots,
+ * A - W or A + W not positive definite). */
+int dmrg_rpa_reduced(int l, const double* HR, const double* SR, const double* WR, double e0, int nroots,
+                     double* omega_out, double* x_out, double* y_out);
+
 int dmrg_tda_reduced(dmrg_ctx* ctx, int* l, double* HR, double* SR);
 
 #define DMRG_TDA_HIST 256 /* iterations kept in dmrg_stats.tda_r2_hist */

@@ -98,6 +98,8 @@ _autotune = _sig("dmrg_autotune", _P, _I, _I, _I, _IP, _DP)
 _renorm = _sig("dmrg_renormalize", _P, _I, _I, _I, _I, _P, _Z, _I)
 _sweep = _sig("dmrg_sweep_ground", _P, ctypes.POINTER(SweepParams), _DP, _DP)
 _tda = _sig("dmrg_tda_roots", _P, _I, ctypes.POINTER(DavidsonParams), _DP, _DP, _DP, _IP)
+_rpa = _sig("dmrg_rpa_roots", _P, _I, ctypes.POINTER(DavidsonParams), _DP, _DP, _DP, _IP)
+_rpa_reduced = _sig("dmrg_rpa_reduced", _I, _DP, _DP, _DP, _D, _I, _DP, _DP, _DP)
 _stats = _sig("dmrg_get_stats", _P, ctypes.POINTER(Stats))
 _stats_size = _lib.dmrg_stats_size
 _stats_size.argtypes = []
@@ -152,6 +154,22 @@ def _dp(a):
 
 def _ip(a):
     return a.ctypes.data_as(_IP)
+
+
+def rpa_reduced(HR, SR, WR, e0, nroots):
+    """The reduced DMRG-RPA problem alone, on the host (see dmrg_rpa_reduced):
+    returns (omega[nroots], a, b, rank) with a, b of shape (l, nroots)."""
+    HR, SR, WR = (np.ascontiguousarray(m, dtype=np.float64) for m in (HR, SR, WR))
+    l = HR.shape[0]
+    if HR.shape != (l, l) or SR.shape != (l, l) or WR.shape != (l, l):
+        raise ValueError("HR, SR, WR must be square and of one size")
+    om = np.zeros(nroots)
+    a = np.zeros((nroots, l))
+    b = np.zeros((nroots, l))
+    rc = _rpa_reduced(l, _dp(HR), _dp(SR), _dp(WR), float(e0), nroots, _dp(om), _dp(a), _dp(b))
+    if rc < 0:
+        raise DMRGError(rc, "dmrg_rpa_reduced failed")
+    return om, a.T.copy(), b.T.copy(), rc
 
 
 class Context:
@@ -361,6 +379,27 @@ class Context:
             torch.cuda.synchronize(self.device)
             torch.cuda.empty_cache()
         rc = _tda(self._h, nroots, ctypes.byref(p), _dp(om), _dp(et), _dp(r2), ctypes.byref(it))
+        if rc not in (0, -3):
+            self._check(rc)
+        return om, et, r2, it.value, rc == 0
+
+    def rpa_roots(self, nroots, max_iter=60, max_space=0, tol=1e-9, seed=7, prec=FP64, verbose=0, polish=True,
+                  guess="diag"):
+        """DMRG-RPA roots (see dmrg_rpa_roots): returns (omega, e_total,
+        resid2, iterations, converged)."""
+        if guess not in ("diag", "random"):
+            raise ValueError("guess must be 'diag' or 'random'")
+        p = DavidsonParams(max_iter, max_space, tol, seed, prec, verbose, 0 if polish else -1,
+                           0 if guess == "diag" else 1)
+        om = np.zeros(nroots)
+        et = np.zeros(nroots)
+        r2 = np.zeros(nroots)
+        it = ctypes.c_int()
+        if self._alloc is not None and max_space == 0:
+            import torch
+            torch.cuda.synchronize(self.device)
+            torch.cuda.empty_cache()
+        rc = _rpa(self._h, nroots, ctypes.byref(p), _dp(om), _dp(et), _dp(r2), ctypes.byref(it))
         if rc not in (0, -3):
             self._check(rc)
         return om, et, r2, it.value, rc == 0

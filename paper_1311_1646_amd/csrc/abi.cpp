@@ -4,6 +4,7 @@
 #include <string>
 
 #include "engine.hpp"
+#include "rpa_reduced.hpp"
 
 namespace dmrg {
 int debug_mpo_dense_left(QCHamiltonian& H, int wide_bond, double* out);
@@ -266,6 +267,48 @@ int dmrg_response(dmrg_ctx* ctx, const double* v, double omega, const dmrg_david
     return DMRG_ERR_NOT_CONVERGED;
   }
   return rc;
+}
+
+int dmrg_rpa_roots(dmrg_ctx* ctx, int nroots, const dmrg_davidson_params* p, double* omega, double* e_total,
+                   double* resid2, int* iters) {
+  bool conv = false;
+  int rc = guard(ctx, [&](dmrg::Ctx& x) {
+    DMRG_REQUIRE(p, DMRG_ERR_INVALID_ARG, "null parameters");
+    DMRG_REQUIRE(valid_prec(p->prec), DMRG_ERR_INVALID_ARG, "unsupported precision");
+    DMRG_REQUIRE(p->polish == 0 || p->polish == -1, DMRG_ERR_INVALID_ARG, "polish must be 0 or -1");
+    DMRG_REQUIRE(p->guess == 0 || p->guess == 1, DMRG_ERR_INVALID_ARG, "guess must be 0 or 1");
+    x.rpa_roots(nroots, *p, omega, e_total, resid2, iters, &conv);
+  });
+  if (rc == DMRG_OK && !conv) {
+    ctx->x->err = "Davidson iteration limit reached";
+    return DMRG_ERR_NOT_CONVERGED;
+  }
+  return rc;
+}
+
+int dmrg_rpa_reduced(int l, const double* HR, const double* SR, const double* WR, double e0, int nroots,
+                     double* omega_out, double* x_out, double* y_out) {
+  if (l < 1 || l > 4096 || nroots < 1 || !HR || !SR || !WR || !omega_out) return DMRG_ERR_INVALID_ARG;
+  try {
+    dmrg::RpaReduced red;
+    if (dmrg::rpa_reduced_solve(l, HR, SR, WR, e0, 1e-10, red) != 0) return DMRG_ERR_SINGULAR;
+    if (red.r < nroots) return DMRG_ERR_SINGULAR;
+    for (int k = 0; k < nroots; ++k) {
+      omega_out[k] = red.omega[k];
+      for (int u = 0; u < l; ++u) {
+        double a = 0, b = 0;
+        for (int t = 0; t < red.r; ++t) {
+          a += red.T[u + size_t(t) * l] * red.x[t + size_t(k) * red.r];
+          b += red.T[u + size_t(t) * l] * red.y[t + size_t(k) * red.r];
+        }
+        if (x_out) x_out[u + size_t(k) * l] = a;
+        if (y_out) y_out[u + size_t(k) * l] = b;
+      }
+    }
+    return red.r;
+  } catch (...) {
+    return DMRG_ERR_INTERNAL;
+  }
 }
 
 int dmrg_tda_reduced(dmrg_ctx* ctx, int* l, double* HR, double* SR) {

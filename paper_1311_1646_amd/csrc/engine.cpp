@@ -1222,17 +1222,21 @@ std::unique_ptr<ContractionPlan> Ctx::make_renorm_plan(int dir, int i, const OpS
 }
 
 void Ctx::renorm(int dir, int i, const double* Abra, const double* Aket, long aket_stride, const OpSet& src,
-                 OpSet& dst, bool accumulate, int batch, int prec) {
-  const bool src_b = src.nvec > 1, ket_b = aket_stride != 0;
+                 OpSet& dst, bool accumulate, int batch, int prec, long abra_stride) {
+  const bool src_b = src.nvec > 1, ket_b = aket_stride != 0, bra_b = abra_stride != 0;
+  DMRG_REQUIRE(!bra_b || (!ket_b && !src_b), DMRG_ERR_INTERNAL, "batched bra with a batched ket or source");
+  // a batched bra takes the plan that forms T = X A_ket (shared here) in
+  // stage 1 and applies the bra in stage 2, where each entry reads its own
   ContractionPlan& P = renorm_plan(dir, i, src, dst, ket_b && !src_b && batch > 1);
   // stage-1 products: per ket unless formed from the bra (shared); the
-  // results (and the building blocks) are per entry whenever a source or
-  // the ket is
+  // results (and the building blocks) are per entry whenever a source, the
+  // ket or the bra is
   const bool t_b = P.bra_first ? src_b : (src_b || ket_b);
-  const bool o_b = src_b || ket_b;
+  const bool o_b = src_b || ket_b || bra_b;
   const size_t esz = prec == DMRG_FP64 ? 8 : 4;
   Bases b{};
   b.p[B_ABRA] = const_cast<double*>(Abra);
+  b.stride[B_ABRA] = abra_stride;
   b.p[B_AKET] = const_cast<double*>(Aket);
   b.stride[B_AKET] = aket_stride;
   b.p[B_SRC] = src.ptr();
@@ -1256,13 +1260,17 @@ void Ctx::renorm(int dir, int i, const double* Abra, const double* Aket, long ak
     b.p[B_SRC] = reinterpret_cast<double*>(f32_data(src));
     const long S = long(layout(i, 1).size);
     const long nket = ket_b ? S * batch : S;
-    ws_a32.ensure(this, size_t(S + nket) * 4);
+    const long nbra = bra_b ? S * batch : S;
+    DMRG_REQUIRE((!ket_b || aket_stride == S) && (!bra_b || abra_stride == S), DMRG_ERR_INTERNAL,
+                 "batched site tensors must be contiguous in FP32 renormalization");
+    ws_a32.ensure(this, size_t(nbra + nket) * 4);
     float* abra = ws_a32.as<float>();
-    float* aket = abra + S;
-    launch_convert_f64_f32(Abra, abra, S, stream);
+    float* aket = abra + nbra;
+    launch_convert_f64_f32(Abra, abra, nbra, stream);
     launch_convert_f64_f32(Aket, aket, nket, stream);
     b.p[B_ABRA] = reinterpret_cast<double*>(abra);
     b.p[B_AKET] = reinterpret_cast<double*>(aket);
+    b.stride[B_ABRA] = bra_b ? S : 0;
     b.stride[B_AKET] = ket_b ? S : 0;
   }
   dst.f32_valid = false;

@@ -312,12 +312,13 @@ class Ctx {
   long opset_size(int bond, int side);  // elements per vector of the set at (bond, side)
 
   // Renormalization across site i into dst (left: bond i -> i+1; right:
-  // bond i+1 -> i).  bra tensor Abra (unbatched), ket tensor Aket with batch
-  // stride aket_stride (0 = shared), src / dst operator sets (batched sets
-  // carry their own stride).  accumulate: add into dst instead of
-  // overwriting it.
+  // bond i+1 -> i).  bra tensor Abra with batch stride abra_stride and ket
+  // tensor Aket with batch stride aket_stride (0 = shared; at most one of the
+  // two tensors, and then not the source set, is batched), src / dst operator
+  // sets (batched sets carry their own stride).  accumulate: add into dst
+  // instead of overwriting it.
   void renorm(int dir, int i, const double* Abra, const double* Aket, long aket_stride, const OpSet& src,
-              OpSet& dst, bool accumulate, int batch, int prec = 0);
+              OpSet& dst, bool accumulate, int batch, int prec = 0, long abra_stride = 0);
   // sigma = H_eff C with the left set X and the right set Z on the dot
   // (i, width); C has batch stride cstride (0 = shared), outputs have stride
   // sstride; batch = number of outputs.
@@ -361,6 +362,8 @@ class Ctx {
   int main_events_used_ = 0;
   void diag(int i, int width, double* out);
   void tda_roots(int nroots, const dmrg_davidson_params& p, double* omega, double* etot, double* resid2,
+                 int* iters, bool* converged);
+  void rpa_roots(int nroots, const dmrg_davidson_params& p, double* omega, double* etot, double* resid2,
                  int* iters, bool* converged);
   void response(const double* v, double omega, const dmrg_davidson_params& p, double* chi, double* resid2,
                 int* iters, bool* converged);

@@ -23,6 +23,7 @@
 #include <string>
 
 #include "engine.hpp"
+#include "rpa_reduced.hpp"
 
 namespace dmrg {
 
@@ -296,9 +297,12 @@ struct ResponseSpec {
 
 class TdaRunner {
  public:
-  // nroots TDA roots, or (rs != null) the two response vectors of rs
-  TdaRunner(Ctx& x, int nroots, const dmrg_davidson_params& p, const ResponseSpec* rs = nullptr)
-      : x_(x), k_(x.gauge_kit()), n_(rs ? 2 : nroots), p_(p), prec_(p.prec) {
+  // nroots TDA roots, or (rs != null) the two response vectors of rs, or
+  // (rpa) nroots RPA roots, each with a forward and a backward component
+  TdaRunner(Ctx& x, int nroots, const dmrg_davidson_params& p, const ResponseSpec* rs = nullptr, bool rpa = false)
+      : x_(x), k_(x.gauge_kit()), n_(rs ? 2 : (rpa ? 2 * nroots : nroots)), p_(p), prec_(p.prec) {
+    rpa_ = rpa && !rs;
+    nr_ = nroots;
     if (rs) {
       resp_ = true;
       rhs_ = rs->rhs;
@@ -341,6 +345,18 @@ class TdaRunner {
       cres_.alloc(&x, 64 * 2 * 8);
       zsh_.alloc(&x, 64 * 8);
       for (DBuf* b : {&Cx_, &Dx_, &Gx_}) b->alloc(&x, 2 * size_t(maxsize) * 8);
+    }
+    if (rpa_) {
+      // the second-order parts: Gamma^R per site (eq. bmatrix, backward
+      // sweep), Gamma^L of the current site, the W half-matrix, and the
+      // coefficients of X and Y (and of Y and X) in the rotated basis
+      GB_.resize(L_);
+      for (int i = 0; i < L_; ++i) GB_[i].alloc(&x, size_t(Nmax_) * k_.size[i] * 8);
+      for (DBuf* b : {&GL_, &GBr_, &Cx_, &Dx_, &Gx_, &Xw_}) b->alloc(&x, vs);
+      WR_.alloc(&x, 64 * 64 * 8);
+      cres_.alloc(&x, 64 * 64 * 8);
+      cswap_.alloc(&x, 64 * 64 * 8);
+      zsh_.alloc(&x, 64 * 8);
     }
     std::vector<double> one(64, 1.0);
     DMRG_HIP(hipMemcpy(ones_.p, one.data(), 64 * 8, hipMemcpyHostToDevice));
@@ -385,6 +401,21 @@ class TdaRunner {
   std::vector<const double*> rhs_;
   double omega_ = 0, chi_[2] = {0, 0};
   DBuf bR_, cres_, zsh_, Cx_, Dx_, Gx_;
+  // RPA mode (Sec. II C eq. dmrgrpa, Sec. III E): nr_ roots; the residual
+  // vectors are the n_ = 2 nr_ components X_k, Y_k; first-order operator
+  // chains with the first-order tensor on the bra side (FLB_, FRB_) give
+  // Gamma^L_i[v] = <U_v n r| H |Psi0> and Gamma^R_i[v] = <l n V_v| H |Psi0>
+  // (U_v, V_v the first-order left / right block states of trial vector v)
+  bool rpa_ = false;
+  int nr_ = 0;
+  std::vector<DBuf> GB_;
+  DBuf GL_, GBr_, Xw_, WR_, cswap_;
+  OpSet FLB_[2], FRB_[2];
+  std::vector<double> rpa_omega_;
+  // RPA: solve the reduced problem of the l = lcur trial vectors (eq.
+  // reducedrpa) and set the basis rotation (alpha_, m columns), the
+  // coefficients of the residual vectors and their shifts
+  int rpa_step(int lcur, int& m, std::vector<double>& r2);
 
   long size(int i) const { return k_.size[i]; }
   void copy(double* dst, const double* src, long n) {
@@ -423,7 +454,8 @@ class TdaRunner {
     for (int i = 0; i < L_; ++i) sites += k_.size[i];
     // sized for FP64 sets whenever the run may end in FP64 polish
     const double esz = (prec_ != DMRG_FP64 && p_.polish != 0) ? 4 : 8;
-    const double per = 3.0 * double(mx) * esz + 8.0 * (3.0 * sites + 9.0 * k_.max_size);
+    const double per = (rpa_ ? 5.0 : 3.0) * double(mx) * esz +
+                       8.0 * ((rpa_ ? 4.0 : 3.0) * sites + (rpa_ ? 14.0 : 9.0) * k_.max_size);
     size_t freeb = 0, total = 0;
     int cap = 64;
     if (hipMemGetInfo(&freeb, &total) == hipSuccess) cap = int(std::min(64.0, 0.6 * double(freeb) / per));
@@ -499,6 +531,107 @@ void TdaRunner::response_step(int lcur, int rank, int m, std::vector<double>& w)
   DMRG_HIP(hipMemcpy(cres_.p, cm.data(), cm.size() * 8, hipMemcpyHostToDevice));
 }
 
+int TdaRunner::rpa_step(int lcur, int& m, std::vector<double>& r2) {
+  (void)r2;
+  const size_t ll = size_t(lcur) * lcur;
+  std::vector<double> hr(ll), sr(ll), wh(ll), wr(ll);
+  DMRG_HIP(hipMemcpy(hr.data(), HR_.p, ll * 8, hipMemcpyDeviceToHost));
+  DMRG_HIP(hipMemcpy(sr.data(), SR_.p, ll * 8, hipMemcpyDeviceToHost));
+  DMRG_HIP(hipMemcpy(wh.data(), WR_.p, ll * 8, hipMemcpyDeviceToHost));
+  // W_R = W_half + W_half^T (eq. bmatrix, both orders of the pair); the gram
+  // layout is W_half[u * lcur + v], symmetric sums need no transpose care
+  for (int u = 0; u < lcur; ++u)
+    for (int v = 0; v < lcur; ++v) wr[u + size_t(v) * lcur] = wh[u * size_t(lcur) + v] + wh[v * size_t(lcur) + u];
+  // H_R and S_R of the gram kernel are [u * lcur + v] too; they are
+  // symmetric up to rounding, which the solver symmetrizes
+  RpaReduced red;
+  const int st = rpa_reduced_solve(lcur, hr.data(), sr.data(), wr.data(), E0_, 1e-10, red);
+  DMRG_REQUIRE(st == 0, DMRG_ERR_SINGULAR,
+               "RPA stability matrix is not positive definite on the trial space (unstable reference)");
+  const int r = red.r;
+  DMRG_REQUIRE(r >= nr_, DMRG_ERR_SINGULAR, "trial space lost rank below the number of roots");
+  rpa_omega_.assign(red.omega.begin(), red.omega.begin() + nr_);
+  // kept basis (coordinates in the orthonormal basis U T, r-vectors): the
+  // whole space when it fits, else X' and Y' of the lowest roots,
+  // orthonormalized (a restart keeps the current roots exactly)
+  std::vector<double> K;  // r x mk, column-major
+  int mk = 0;
+  if (m >= r) {
+    K.assign(size_t(r) * r, 0.0);
+    for (int j = 0; j < r; ++j) K[j + size_t(j) * r] = 1.0;
+    mk = r;
+  } else {
+    const int kk = std::min(r, std::max(nr_, m / 2));
+    std::vector<double> cand;
+    for (int k = 0; k < kk; ++k)
+      for (const std::vector<double>* src : {&red.x, &red.y})
+        cand.insert(cand.end(), src->begin() + size_t(k) * r, src->begin() + size_t(k + 1) * r);
+    const int nc = int(cand.size() / r);
+    for (int c = 0; c < nc && mk < m; ++c) {
+      std::vector<double> v(cand.begin() + size_t(c) * r, cand.begin() + size_t(c + 1) * r);
+      double n0 = 0;
+      for (double e : v) n0 += e * e;
+      n0 = std::sqrt(n0);
+      for (int pass = 0; pass < 2; ++pass)
+        for (int j = 0; j < mk; ++j) {
+          double d = 0;
+          for (int e = 0; e < r; ++e) d += K[e + size_t(j) * r] * v[e];
+          for (int e = 0; e < r; ++e) v[e] -= d * K[e + size_t(j) * r];
+        }
+      double nv = 0;
+      for (double e : v) nv += e * e;
+      nv = std::sqrt(nv);
+      if (nv <= 1e-8 * std::max(n0, 1e-300)) continue;
+      for (double& e : v) e /= nv;
+      K.insert(K.end(), v.begin(), v.end());
+      ++mk;
+    }
+  }
+  m = mk;
+  // alpha = T K (lcur x m): the new trial vectors U T K are S-orthonormal
+  std::vector<double> al(size_t(lcur) * m, 0.0);
+  for (int j = 0; j < m; ++j)
+    for (int t = 0; t < r; ++t) {
+      const double kv = K[t + size_t(j) * r];
+      if (kv == 0.0) continue;
+      for (int u = 0; u < lcur; ++u) al[u + size_t(j) * lcur] += red.T[u + size_t(t) * lcur] * kv;
+    }
+  // residual vectors v < nr_: X_v, v >= nr_: Y_{v - nr_}; coefficients in
+  // the new basis K^T X', and the swapped set (Y for the X residuals, X for
+  // the Y residuals) that multiplies the W gradients
+  std::vector<double> c(size_t(m) * n_, 0.0), cs(size_t(m) * n_, 0.0);
+  for (int v = 0; v < nr_; ++v)
+    for (int j = 0; j < m; ++j) {
+      double dx = 0, dy = 0;
+      for (int t = 0; t < r; ++t) {
+        dx += K[t + size_t(j) * r] * red.x[t + size_t(v) * r];
+        dy += K[t + size_t(j) * r] * red.y[t + size_t(v) * r];
+      }
+      c[j + size_t(v) * m] = dx;
+      c[j + size_t(v + nr_) * m] = dy;
+      cs[j + size_t(v) * m] = dy;
+      cs[j + size_t(v + nr_) * m] = dx;
+    }
+  // shifts: X residual (H - (E0 + omega)), Y residual (H - (E0 - omega))
+  std::vector<double> z(64, 0.0), nz(64, 0.0);
+  for (int v = 0; v < nr_; ++v) {
+    z[v] = E0_ + rpa_omega_[v];
+    z[v + nr_] = E0_ - rpa_omega_[v];
+  }
+  for (int v = 0; v < n_; ++v) nz[v] = -z[v];
+  if (p_.verbose >= 1) {
+    std::fprintf(stderr, "[rpa] rank %d kept %d omega", r, m);
+    for (int v = 0; v < nr_; ++v) std::fprintf(stderr, " %.10f", rpa_omega_[v]);
+    std::fprintf(stderr, "\n");
+  }
+  DMRG_HIP(hipMemcpy(alpha_.p, al.data(), al.size() * 8, hipMemcpyHostToDevice));
+  DMRG_HIP(hipMemcpy(cres_.p, c.data(), c.size() * 8, hipMemcpyHostToDevice));
+  DMRG_HIP(hipMemcpy(cswap_.p, cs.data(), cs.size() * 8, hipMemcpyHostToDevice));
+  DMRG_HIP(hipMemcpy(zsh_.p, z.data(), 64 * 8, hipMemcpyHostToDevice));
+  DMRG_HIP(hipMemcpy(negw_.p, nz.data(), 64 * 8, hipMemcpyHostToDevice));
+  return r;
+}
+
 void TdaRunner::q_c_project(int i, double* z, int nv) {
   const double* C0 = x_.site[i].C.as<double>();
   gram(z, size(i), nv, C0, size(i), 1, size(i), tmpd_.as<double>(), 1, -1.0, false);
@@ -515,6 +648,10 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
   int cur = 0;
   reserve(FL_, 0, l);
   x_.alloc_opset(FL_[cur], 0, 0, l, true, true, prec_ != DMRG_FP64);
+  if (rpa_) {
+    reserve(FLB_, 0, l);
+    x_.alloc_opset(FLB_[cur], 0, 0, l, true, true, prec_ != DMRG_FP64);
+  }
   HostRng rng(seed);
   std::vector<double> tmp;
   for (int i = 0; i < L_; ++i) {
@@ -528,6 +665,9 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
                         x_.stream);
       launch_rotate_f64(G_[i].as<double>(), S, lprev, alpha_.as<double>(), lprev, m, Gr_.as<double>(), S, S,
                         x_.stream);
+      if (rpa_)
+        launch_rotate_f64(GB_[i].as<double>(), S, lprev, alpha_.as<double>(), lprev, m, GBr_.as<double>(), S, S,
+                          x_.stream);
       DMRG_HIP(hipGetLastError());
       copy(Cm, R1r_.as<double>(), long(m) * S);
       k_.scale(i, true, false, Cm, m);
@@ -551,6 +691,9 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
     pc_.mark(PhaseClock::SIG1);
     x_.sigma_general(i, 1, FL_[cur], x_.right[i + 1], C0, 0, Dl, S, l, prec_);
     tfl += x_.stats.sigma_flops;
+    // RPA: Gamma^L_i[v] = <U_v n r| H |Psi0> (the conjugate first-order
+    // superblock operator of eq. bmatrix applied to C^(0))
+    if (rpa_) x_.sigma_general(i, 1, FLB_[cur], x_.right[i + 1], C0, 0, GL_.as<double>(), S, l, prec_);
     double* Wk = Wk_.as<double>();
     if (!init) {
       // sigma (eq. sigv1), residual (eq. rnorm), correction (eqs. error, param)
@@ -562,14 +705,25 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
       const double* Xc = Cm;
       const double* Xd = Dl;
       const double* Xg = Gr_.as<double>();
-      if (resp_) {
-        launch_rotate_f64(Cm, S, m, cres_.as<double>(), m, 2, Cx_.as<double>(), S, S, x_.stream);
-        launch_rotate_f64(Dl, S, m, cres_.as<double>(), m, 2, Dx_.as<double>(), S, S, x_.stream);
-        launch_rotate_f64(Gr_.as<double>(), S, m, cres_.as<double>(), m, 2, Gx_.as<double>(), S, S, x_.stream);
+      if (resp_ || rpa_) {
+        launch_rotate_f64(Cm, S, m, cres_.as<double>(), m, n_, Cx_.as<double>(), S, S, x_.stream);
+        launch_rotate_f64(Dl, S, m, cres_.as<double>(), m, n_, Dx_.as<double>(), S, S, x_.stream);
+        launch_rotate_f64(Gr_.as<double>(), S, m, cres_.as<double>(), m, n_, Gx_.as<double>(), S, S, x_.stream);
         DMRG_HIP(hipGetLastError());
         Xc = Cx_.as<double>();
         Xd = Dx_.as<double>();
         Xg = Gx_.as<double>();
+      }
+      if (rpa_) {
+        // site-i gradient of W(., v) for the m rotated vectors, Gamma^L_i +
+        // Gamma^R_i (the second derivative of the mixed-canonical MPS at
+        // site i paired with every first-order piece of v), combined with
+        // the swapped coefficients: the X residual takes W Y, the Y
+        // residual W X
+        launch_axpby_f64(ones_.as<double>(), GBr_.as<double>(), S, ones_.as<double>(), GL_.as<double>(), S, m, S,
+                         x_.stream);
+        launch_rotate_f64(GL_.as<double>(), S, m, cswap_.as<double>(), m, n_, Xw_.as<double>(), S, S, x_.stream);
+        DMRG_HIP(hipGetLastError());
       }
       pc_.mark(PhaseClock::SIG0);
       x_.sigma_general(i, 1, x_.left[i], x_.right[i + 1], Xc, S, Sg, S, n_, prec_);
@@ -590,6 +744,8 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
       launch_axpby_f64(negw_.as<double>(), Xc, S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
       // response: r = (H - z) x + V Psi0 (eqs. realresp, imagresp)
       if (resp_) launch_axpby_f64(ones_.as<double>(), rhs_[i], 0, ones_.as<double>(), Sg, S, n_, S, x_.stream);
+      // RPA: r_X = (H - E0 - omega) X + W Y, r_Y = (H - E0 + omega) Y + W X (eq. dmrgrpa)
+      if (rpa_) launch_axpby_f64(ones_.as<double>(), Xw_.as<double>(), S, ones_.as<double>(), Sg, S, n_, S, x_.stream);
       DMRG_HIP(hipGetLastError());
       // residual restricted to the site's tangent directions (orthogonal to
       // C^(0)); for a stationary reference this projection changes nothing
@@ -601,8 +757,8 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
       x_.sync();
       pc_.mark(PhaseClock::VEC);
       for (int v = 0; v < n_; ++v) r2[v] += tmp[size_t(v) * n_ + v];
-      launch_precond_f64(Sg, diag_[i].as<double>(), resp_ ? zsh_.as<double>() : w_.as<double>(), Wk, n_, S, 1e-8,
-                         x_.stream);
+      launch_precond_f64(Sg, diag_[i].as<double>(), (resp_ || rpa_) ? zsh_.as<double>() : w_.as<double>(), Wk, n_,
+                         S, 1e-8, x_.stream);
       // corrections scaled by 1/|r| of the previous iteration so that new
       // trial vectors keep O(1) norm (S_R stays well conditioned near convergence)
       launch_axpby_f64(zscale_.as<double>(), Wk, S, nullptr, Wk, S, n_, S, x_.stream);
@@ -662,6 +818,14 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
     x_.renorm(DMRG_DIR_LEFT, i, Li, Li, 0, FL_[cur], FL_[nxt], false, l, prec_);
     pc_.mark(PhaseClock::REN01);
     x_.renorm(DMRG_DIR_LEFT, i, Li, Wk, S, x_.left[i], FL_[nxt], true, l, prec_);
+    if (rpa_) {
+      // <U_v(i+1)| O |L(i+1)> = L^T [<U_v(i)|O|L(i)> x h] L + L^(1)T [<L(i)|O|L(i)> x h] L
+      x_.alloc_opset(FLB_[nxt], i + 1, 0, l, true, true, prec_ != DMRG_FP64);
+      pc_.mark(PhaseClock::REN11);
+      x_.renorm(DMRG_DIR_LEFT, i, Li, Li, 0, FLB_[cur], FLB_[nxt], false, l, prec_);
+      pc_.mark(PhaseClock::REN01);
+      x_.renorm(DMRG_DIR_LEFT, i, Wk, Li, 0, x_.left[i], FLB_[nxt], true, l, prec_, S);
+    }
     pc_.mark(PhaseClock::VEC);
     if (m > 0) copy(Cprev_.as<double>(), Cm, long(m) * S);
     pc_.mark(PhaseClock::HOST);
@@ -672,12 +836,18 @@ void TdaRunner::forward(int m, int lprev, bool init, uint64_t seed, std::vector<
   x_.sync();
   FL_[0].data.release();
   FL_[1].data.release();
+  FLB_[0].data.release();
+  FLB_[1].data.release();
 }
 
 void TdaRunner::backward(int l) {
   int cur = 0;
   reserve(FR_, 1, l);
   x_.alloc_opset(FR_[cur], L_, 1, l, true, true, prec_ != DMRG_FP64);
+  if (rpa_) {
+    reserve(FRB_, 1, l);
+    x_.alloc_opset(FRB_[cur], L_, 1, l, true, true, prec_ != DMRG_FP64);
+  }
   double* Cb = Cb_.as<double>();
   copy(Cb, Ct_[L_ - 1].as<double>(), long(l) * size(L_ - 1));
   for (int i = L_ - 1; i >= 0; --i) {
@@ -691,6 +861,16 @@ void TdaRunner::backward(int l) {
     // first-order right part of the sigma contracted with C^(0)
     pc_.mark(PhaseClock::SIG1);
     x_.sigma_general(i, 1, x_.left[i], FR_[cur], x_.site[i].C.as<double>(), 0, G_[i].as<double>(), S, l, prec_);
+    if (rpa_) {
+      // Gamma^R_i[v] = <l n V_v| H |Psi0>, and eq. bmatrix: the pairs with
+      // the first-order left piece of u at site i and every first-order
+      // right piece of v at sites > i, W_half[u][v] += C~_i^u . Gamma^R_i[v]
+      // (C~ the Q^L-projected coefficients of eq. cwfn1st of the forward
+      // sweep); W = W_half + W_half^T
+      x_.sigma_general(i, 1, x_.left[i], FRB_[cur], x_.site[i].C.as<double>(), 0, GB_[i].as<double>(), S, l,
+                       prec_);
+      gram(Ct_[i].as<double>(), S, l, GB_[i].as<double>(), S, l, S, WR_.as<double>(), l, 1.0, i != L_ - 1);
+    }
     pc_.mark(PhaseClock::VEC);
     if (i == 0) break;
     // first-order right operators (eq. ropr1st)
@@ -700,6 +880,13 @@ void TdaRunner::backward(int l) {
     x_.renorm(DMRG_DIR_RIGHT, i, Ri, Ri, 0, FR_[cur], FR_[nxt], false, l, prec_);
     pc_.mark(PhaseClock::REN01);
     x_.renorm(DMRG_DIR_RIGHT, i, Ri, R1, S, x_.right[i + 1], FR_[nxt], true, l, prec_);
+    if (rpa_) {
+      x_.alloc_opset(FRB_[nxt], i, 1, l, true, true, prec_ != DMRG_FP64);
+      pc_.mark(PhaseClock::REN11);
+      x_.renorm(DMRG_DIR_RIGHT, i, Ri, Ri, 0, FRB_[cur], FRB_[nxt], false, l, prec_);
+      pc_.mark(PhaseClock::REN01);
+      x_.renorm(DMRG_DIR_RIGHT, i, R1, Ri, 0, x_.right[i + 1], FRB_[nxt], true, l, prec_, S);
+    }
     pc_.mark(PhaseClock::VEC);
     // gauge shift to site i-1 (eq. gauge_bwd): C_{i-1} = C~_{i-1} + L_{i-1} (C_i R_i^T)
     double* Wk = Wk_.as<double>();
@@ -714,6 +901,8 @@ void TdaRunner::backward(int l) {
   x_.sync();
   FR_[0].data.release();
   FR_[1].data.release();
+  FRB_[0].data.release();
+  FRB_[1].data.release();
 }
 
 }  // namespace dmrg
@@ -776,26 +965,33 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
     auto t0 = std::chrono::steady_clock::now();
     for (double& a : pc_.acc) a = 0;
     pc_.mark(PhaseClock::VEC);
-    // small generalized eigenproblem H_R a = w S_R a (eq. eigs)
-    launch_gep_f64(HR_.as<double>(), SR_.as<double>(), lcur, 1e-10, w_.as<double>(), alpha_.as<double>(),
-                   rank_.as<int>(), x_.stream);
-    DMRG_HIP(hipGetLastError());
-    int rank = 0;
-    DMRG_HIP(hipMemcpy(w.data(), w_.p, size_t(lcur) * 8, hipMemcpyDeviceToHost));
-    DMRG_HIP(hipMemcpy(&rank, rank_.p, sizeof(int), hipMemcpyDeviceToHost));
-    // (response mode: the Ritz vectors are a basis, not the roots; the two
-    // components coincide at omega = 0 and their corrections are then
-    // dependent, which the rank threshold absorbs)
-    DMRG_REQUIRE(rank >= (resp_ ? 1 : n_), DMRG_ERR_SINGULAR, "trial space lost rank below the number of roots");
-    m = std::min(m, rank);
-    if (resp_) {
-      response_step(lcur, rank, m, w);
+    if (rpa_) {
+      // reduced RPA problem (eq. reducedrpa) on the host; sets alpha, the
+      // residual coefficients and shifts, and m
+      rpa_step(lcur, m, r2);
+      for (int v = 0; v < nr_; ++v) w[v] = E0_ + rpa_omega_[v];
     } else {
-      std::vector<double> nw(64, 0.0);
-      for (int v = 0; v < n_; ++v) nw[v] = -w[v];
-      DMRG_HIP(hipMemcpy(negw_.p, nw.data(), 64 * 8, hipMemcpyHostToDevice));
+      // small generalized eigenproblem H_R a = w S_R a (eq. eigs)
+      launch_gep_f64(HR_.as<double>(), SR_.as<double>(), lcur, 1e-10, w_.as<double>(), alpha_.as<double>(),
+                     rank_.as<int>(), x_.stream);
+      DMRG_HIP(hipGetLastError());
+      int rank = 0;
+      DMRG_HIP(hipMemcpy(w.data(), w_.p, size_t(lcur) * 8, hipMemcpyDeviceToHost));
+      DMRG_HIP(hipMemcpy(&rank, rank_.p, sizeof(int), hipMemcpyDeviceToHost));
+      // (response mode: the Ritz vectors are a basis, not the roots; the two
+      // components coincide at omega = 0 and their corrections are then
+      // dependent, which the rank threshold absorbs)
+      DMRG_REQUIRE(rank >= (resp_ ? 1 : n_), DMRG_ERR_SINGULAR, "trial space lost rank below the number of roots");
+      m = std::min(m, rank);
+      if (resp_) {
+        response_step(lcur, rank, m, w);
+      } else {
+        std::vector<double> nw(64, 0.0);
+        for (int v = 0; v < n_; ++v) nw[v] = -w[v];
+        DMRG_HIP(hipMemcpy(negw_.p, nw.data(), 64 * 8, hipMemcpyHostToDevice));
+      }
     }
-    for (int v = 0; v < n_; ++v) last_w[v] = w[v];
+    for (int v = 0; v < (rpa_ ? nr_ : n_); ++v) last_w[v] = w[v];
     std::vector<double> zs(64, 1.0);
     for (int v = 0; v < n_; ++v) zs[v] = r2.empty() ? 1.0 : 1.0 / std::sqrt(std::max(r2[v], 1e-300));
     DMRG_HIP(hipMemcpy(zscale_.p, zs.data(), 64 * 8, hipMemcpyHostToDevice));
@@ -870,10 +1066,11 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
     // neighbour)
     m = (l + n_ <= Nmax_) ? l : std::min(l, std::min(Nmax_ - n_, std::max(n_ + std::max(2, n_ / 2), Nmax_ / 2)));
   }
-  for (int v = 0; v < n_; ++v) {
+  // (RPA: per root, the larger of the X and Y residuals)
+  for (int v = 0; v < (rpa_ ? nr_ : n_); ++v) {
     etot[v] = last_w[v];
     omega[v] = last_w[v] - E0_;
-    resid2[v] = r2.empty() ? 0.0 : r2[v];
+    resid2[v] = r2.empty() ? 0.0 : (rpa_ ? std::max(r2[v], r2[v + nr_]) : r2[v]);
   }
   *iters = std::min(it, p_.max_iter);
   *converged = conv;
@@ -1038,6 +1235,25 @@ void Ctx::tda_roots(int nroots, const dmrg_davidson_params& p, double* omega, do
   for (auto& f : fo_chain) f.reset();
   {
     TdaRunner r(*this, nroots, p);
+    r.run(omega, etot, resid2, iters, converged);
+  }
+  release_workspaces();
+}
+
+// DMRG-RPA roots (Sec. II C eq. dmrgrpa, Sec. III E): the TDA sweeps with
+// the second-order matrix W accumulated in the backward sweep (eq.
+// bmatrix) and the reduced non-Hermitian problem of eq. reducedrpa.
+void Ctx::rpa_roots(int nroots, const dmrg_davidson_params& p, double* omega, double* etot, double* resid2,
+                    int* iters, bool* converged) {
+  require_gpu();
+  DMRG_REQUIRE(ops_prec >= 0, DMRG_ERR_STATE, "call dmrg_build_ops first");
+  DMRG_REQUIRE(omega && etot && resid2 && iters && converged, DMRG_ERR_INVALID_ARG, "null outputs");
+  DMRG_REQUIRE(p.max_iter >= 1, DMRG_ERR_INVALID_ARG, "max_iter must be >= 1");
+  DMRG_REQUIRE(nroots >= 1, DMRG_ERR_INVALID_ARG, "need nroots >= 1");
+  sync();
+  for (auto& f : fo_chain) f.reset();
+  {
+    TdaRunner r(*this, nroots, p, nullptr, true);
     r.run(omega, etot, resid2, iters, converged);
   }
   release_workspaces();
