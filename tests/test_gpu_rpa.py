@@ -74,3 +74,32 @@ def test_exact_reference_rpa_is_the_fci_spectrum():
     print(f"exact reference RPA {np.round(om, 10).tolist()} in {it} iterations", flush=True)
     assert conv, (it, r2)
     np.testing.assert_allclose(om, w[1:n + 1] - w[0], atol=1e-8)
+
+
+
+@pytest.mark.timeout(300)
+def test_rpa_at_full_bond_dimension_is_tda_and_fci_at_scale():
+    # L=8, N=8 random integrals at M=256, the full space (exact bond
+    # dimensions 1,4,16,64,256,...): the sweep's MPS is the FCI ground state,
+    # a stationary reference with (H - E0) Psi0 = 0, so W vanishes and the
+    # RPA roots are the TDA roots and the FCI excitations.  W vanishes here
+    # only through cancellations inside correct bra-side first-order
+    # operators (blocks up to 70 wide, both pair modes), so any error in
+    # them shows.  The iteration times of both runs are printed.
+    import paper_1311_1646_amd as lib
+    p = synth.config(0)
+    dets, H, w, _ = fci.fci(p.h, p.eri, p.ecore, p.Na, p.Nb, nroots=5)
+    ctx = lib.Context(p.L, p.Na, p.Nb, p.h, p.eri, p.ecore, device=0)
+    e, dw, ok = ctx.sweep_ground([32, 128, 256, 256, 256], davidson_tol=1e-13, davidson_max_iter=80, seed=1)
+    assert ok and abs(e - w[0]) < 1e-9
+    n = 4
+    om_t, _, r2_t, it_t, conv_t = ctx.tda_roots(n, max_iter=200, max_space=40, tol=1e-10, seed=3)
+    st_t = ctx.stats()
+    om_r, _, r2_r, it_r, conv_r = ctx.rpa_roots(n, max_iter=200, max_space=40, tol=1e-10, seed=3)
+    st_r = ctx.stats()
+    print(f"TDA {it_t} iterations {st_t['tda_total_ms'] / 1e3:.2f} s ({st_t['tda_total_ms'] / it_t:.1f} ms/it); "
+          f"RPA {it_r} iterations {st_r['tda_total_ms'] / 1e3:.2f} s ({st_r['tda_total_ms'] / it_r:.1f} ms/it); "
+          f"RPA - FCI {np.abs(om_r - (w[1:n + 1] - w[0])).max():.2e}", flush=True)
+    assert conv_t and conv_r, (it_t, r2_t, it_r, r2_r)
+    np.testing.assert_allclose(om_r, om_t, atol=1e-7)
+    np.testing.assert_allclose(om_r, w[1:n + 1] - w[0], atol=1e-7)
