@@ -105,7 +105,7 @@ void Ground::gemm(GemmPlan& P, const std::vector<GJob>& jobs0, std::vector<std::
 }
 
 double Ground::gram1(const double* a, const double* b, long n) {
-  part_.ensure(&x_, size_t(64) * 64 * 64 * 8);
+  part_.ensure(&x_, std::max<size_t>(size_t(64) * 64 * 64, size_t(gram_parts(n))) * 8);
   small_.ensure(&x_, 64 * 64 * 8);
   launch_gram_f64(a, n, 1, b, n, 1, n, small_.as<double>(), 1, part_.as<double>(), 1.0, false, x_.stream);
   x_.sync();
@@ -206,7 +206,7 @@ double Ground::davidson(int i, double* psi, long n, int* iters) {
   HV_.ensure(&x_, size_t(nmax) * n * 8);
   diag_.ensure(&x_, size_t(n) * 8);
   tmp_.ensure(&x_, size_t(2) * n * 8);
-  part_.ensure(&x_, size_t(64) * 64 * 64 * 8);
+  part_.ensure(&x_, std::max<size_t>(size_t(64) * 64 * 64, size_t(gram_parts(n)) * nmax * nmax) * 8);
   small_.ensure(&x_, 64 * 64 * 8 * 2);
   w_.ensure(&x_, 64 * 8);
   alpha_.ensure(&x_, 64 * 64 * 8);

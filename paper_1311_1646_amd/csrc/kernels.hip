@@ -1,6 +1,7 @@
 // FP64 device kernels: grouped block GEMM, operator linear combinations,
 // diagonal of the effective Hamiltonian, dense vector kernels of the Davidson
 // sweeps and the small generalized eigensolver.
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 
@@ -141,16 +142,24 @@ __global__ void diag_jobs_f64_kernel(const DiagJob* __restrict__ jobs, const Dia
 
 // ---- dense vector kernels
 
-constexpr long GRAM_CHUNK = 4096;
 constexpr int GRAM_SUB = 32;
+// Elements per partial sum of the Gram products: about 512 workgroups per
+// product (two per compute unit), chunks of 256 to 4096 elements in steps of
+// GRAM_SUB.  A fixed 4096 left vectors of 10^4-10^5 elements (a site at
+// M = 100-300) with a few dozen workgroups, each looping 128 times.
+long gram_chunk(long n) {
+  long c = (n + 511) / 512;
+  c = (c + GRAM_SUB - 1) / GRAM_SUB * GRAM_SUB;
+  return c < 256 ? 256 : (c > 4096 ? 4096 : c);
+}
 
 __global__ __launch_bounds__(256) void gram_part_kernel(const double* __restrict__ A, long lda, int na,
                                                         const double* __restrict__ B, long ldb, int nb, long n,
-                                                        double* __restrict__ part) {
+                                                        long chunk, double* __restrict__ part) {
   __shared__ double As[64][GRAM_SUB + 1];
   __shared__ double Bs[64][GRAM_SUB + 1];
-  const long e0 = long(blockIdx.x) * GRAM_CHUNK;
-  const long e1 = e0 + GRAM_CHUNK < n ? e0 + GRAM_CHUNK : n;
+  const long e0 = long(blockIdx.x) * chunk;
+  const long e1 = e0 + chunk < n ? e0 + chunk : n;
   const int tid = threadIdx.x;
   double acc[16];
 #pragma unroll
@@ -555,13 +564,21 @@ void launch_diag_jobs_f64(const DiagJob* j, int n, const DiagTerm* t, const Base
   hipLaunchKernelGGL(diag_jobs_f64_kernel, dim3(n), dim3(256), 0, s, j, t, b);
 }
 
-int gram_parts(long n) { return int((n + GRAM_CHUNK - 1) / GRAM_CHUNK); }
+// upper bound of the partial sums of any product of length <= n (the chunk
+// grows with n, so the count is not monotone in n): at most 512 while the
+// chunk is below its cap, n / 4096 beyond
+int gram_parts(long n) {
+  const long small = (n + 255) / 256, large = (n + 4095) / 4096;
+  return int(std::max<long>(std::min<long>(512, small), large));
+}
 
 void launch_gram_f64(const double* A, long lda, int na, const double* B, long ldb, int nb, long n, double* G,
                      int ldg, double* part, double alpha, bool accumulate, hipStream_t s) {
   if (na <= 0 || nb <= 0) return;
-  const int np = gram_parts(n);
-  if (np > 0) hipLaunchKernelGGL(gram_part_kernel, dim3(np), dim3(256), 0, s, A, lda, na, B, ldb, nb, n, part);
+  const long chunk = gram_chunk(n);
+  const int np = n > 0 ? int((n + chunk - 1) / chunk) : 0;  // <= gram_parts(n)
+  if (np > 0)
+    hipLaunchKernelGGL(gram_part_kernel, dim3(np), dim3(256), 0, s, A, lda, na, B, ldb, nb, n, chunk, part);
   hipLaunchKernelGGL(gram_reduce_kernel, dim3((na * nb + 255) / 256), dim3(256), 0, s, part, np, na, nb, G, ldg,
                      alpha, accumulate ? 1 : 0);
 }

@@ -130,8 +130,10 @@ void launch_diag_jobs_f64(const DiagJob* j, int n, const DiagTerm* t, const Base
 // ---- dense vector kernels on [nvec][n] arrays (FP64)
 
 // G[m*ldg + k] (+)= alpha * sum_e A[m*lda + e] * B[k*ldb + e]  (m < na, k < nb),
-// split over e with a deterministic two-pass reduction; part must hold
-// gram_parts(n) * na * nb doubles.
+// split over e with a deterministic two-pass reduction (the split depends on
+// n only); part must hold gram_parts(n) * na * nb doubles, and
+// gram_parts(n) bounds the partial sums of every product of length <= n, so
+// a buffer sized for the longest vector serves all shorter ones.
 int gram_parts(long n);
 void launch_gram_f64(const double* A, long lda, int na, const double* B, long ldb, int nb, long n, double* G,
                      int ldg, double* part, double alpha, bool accumulate, hipStream_t s);
