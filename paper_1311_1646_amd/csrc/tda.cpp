@@ -415,7 +415,7 @@ class TdaRunner {
   // RPA: solve the reduced problem of the l = lcur trial vectors (eq.
   // reducedrpa) and set the basis rotation (alpha_, m columns), the
   // coefficients of the residual vectors and their shifts
-  int rpa_step(int lcur, int& m, std::vector<double>& r2);
+  int rpa_step(int lcur, int& m);
 
   long size(int i) const { return k_.size[i]; }
   void copy(double* dst, const double* src, long n) {
@@ -531,8 +531,7 @@ void TdaRunner::response_step(int lcur, int rank, int m, std::vector<double>& w)
   DMRG_HIP(hipMemcpy(cres_.p, cm.data(), cm.size() * 8, hipMemcpyHostToDevice));
 }
 
-int TdaRunner::rpa_step(int lcur, int& m, std::vector<double>& r2) {
-  (void)r2;
+int TdaRunner::rpa_step(int lcur, int& m) {
   const size_t ll = size_t(lcur) * lcur;
   std::vector<double> hr(ll), sr(ll), wh(ll), wr(ll);
   DMRG_HIP(hipMemcpy(hr.data(), HR_.p, ll * 8, hipMemcpyDeviceToHost));
@@ -968,7 +967,7 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
     if (rpa_) {
       // reduced RPA problem (eq. reducedrpa) on the host; sets alpha, the
       // residual coefficients and shifts, and m
-      rpa_step(lcur, m, r2);
+      rpa_step(lcur, m);
       for (int v = 0; v < nr_; ++v) w[v] = E0_ + rpa_omega_[v];
     } else {
       // small generalized eigenproblem H_R a = w S_R a (eq. eigs)
