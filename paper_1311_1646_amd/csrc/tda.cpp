@@ -314,7 +314,9 @@ class TdaRunner {
     guess_ = p.guess;
     Nmax_ = p.max_space > 0 ? p.max_space : auto_space();
     DMRG_REQUIRE(Nmax_ <= 64, DMRG_ERR_INVALID_ARG, "max_space must be <= 64");
-    DMRG_REQUIRE(n_ >= 1 && 2 * n_ <= Nmax_, DMRG_ERR_INVALID_ARG, "need 1 <= nroots and 2*nroots <= max_space");
+    DMRG_REQUIRE(n_ >= 1 && 2 * n_ <= Nmax_, DMRG_ERR_INVALID_ARG,
+                 rpa_ ? "need 1 <= nroots and 4*nroots <= max_space (RPA: an X and a Y residual per root)"
+                      : "need 1 <= nroots and 2*nroots <= max_space");
     x.stats.tda_space = Nmax_;
     // per-site storage
     R1_.resize(L_);
