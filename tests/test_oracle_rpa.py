@@ -16,7 +16,10 @@ construction of the second-order vectors:
   lowest RPA root lies below the lowest TDA root (Thouless' variational
   bound: the TDA vector is a trial vector of the RPA functional);
 * a planted mistake (Lambda^-1 dropped from the first-order left tensor)
-  breaks the second-variation identity.
+  breaks the second-variation identity;
+* the two sweep directions of eq. bmatrix (pairs grouped by their right site
+  with first-order left block states, or by their left site with
+  first-order right block states) give the same W.
 """
 import numpy as np
 import pytest
@@ -136,3 +139,51 @@ def test_stable_stationary_reference_rpa_properties(L, Na, Nb, M, seed):
     assert om[0] <= tda_w[0] + 1e-12
     # W is not negligible here, so the bound is strict
     assert om[0] < tda_w[0] - 1e-6
+
+
+def _project_right(mps, dets, Rt, site, v):
+    """Components of v along |l n r'> at `site`, the right states r' built
+    from the tensors Rt[site+1..] (left states from the MPS's L tensors)."""
+    left = mpsvec._left_states(mps, mps.Lt, site)
+    right = mpsvec._right_states(mps, Rt, site + 1)
+    out = []
+    for a, n, c in mps.block_keys(site):
+        ml, mr = mps.bonds[site][a][1], mps.bonds[site + 1][c][1]
+        if a in left and c in right:
+            cl, Ul = left[a]
+            cr, Ur = right[c]
+            pos = np.searchsorted(dets, (cl[:, None] | (np.int64(n) << (2 * site)) | cr[None, :]).ravel())
+            out.append((Ul.T @ v[pos].reshape(len(cl), len(cr)) @ Ur).ravel())
+        else:
+            out.append(np.zeros(ml * mr))
+    return np.concatenate(out)
+
+
+def test_backward_sweep_form_of_the_w_matrix_equals_the_forward_form():
+    # eq. bmatrix accumulates W over the sites of one sweep.  The oracle
+    # groups each pair (p < q) by its right site q: the first-order left
+    # states of x up to q-1 and the right-gauge piece of y at q.  The library's
+    # backward sweep groups it by its left site p: the left-gauge piece of x
+    # at p and the first-order right states of y beyond p, built from
+    # R1_q = Lambda_{q-1}^-1 (C_q Q^R).  Both must give the same matrix.
+    L, Na, Nb, M, seed = 5, 2, 2, 6, 11
+    mps, dets, Hs, psi0 = _reference(L, Na, Nb, M, seed, stable_shift=False)
+    e0, A, W, B = rpa.rpa_matrices(mps, dets, Hs)
+    h0 = Hs @ psi0 - e0 * psi0
+    lam_inv = [{c: np.linalg.inv(g) for c, g in rpa.gauge_matrix(mps, i).items()} for i in range(L - 1)]
+    nb = B.shape[1]
+    pieces = [rpa.site_pieces(mps, dets, B[:, a]) for a in range(nb)]
+    left_flat = [np.stack([firstorder.flat(mps, p, pieces[a][0][p]) for a in range(nb)]) for p in range(L)]
+    half = np.zeros((nb, nb))
+    for b in range(nb):
+        br = pieces[b][1]
+        # R1_q[b] = Lambda_{q-1}^-1 (C_q Q^R), Lambda keyed by the left sector of site q
+        r1 = [None] + [{(s, n): lam_inv[q - 1][s] @ blk for (s, n), blk in br[q].items()} for q in range(1, L)]
+        for p in range(L - 1):
+            gam = np.zeros(mps.site_size(p))
+            for q in range(p + 1, L):
+                Rt = list(mps.Rt)
+                Rt[q] = r1[q]
+                gam += _project_right(mps, dets, Rt, p, h0)
+            half[:, b] += left_flat[p] @ gam
+    np.testing.assert_allclose(half + half.T, W, atol=1e-12 * max(1.0, np.abs(W).max()))
