@@ -19,7 +19,9 @@ construction of the second-order vectors:
   breaks the second-variation identity;
 * the two sweep directions of eq. bmatrix (pairs grouped by their right site
   with first-order left block states, or by their left site with
-  first-order right block states) give the same W.
+  first-order right block states) give the same W;
+* at a stationary reference the site-wise W gradient of the library's RPA
+  residual is the exact one (P_i^T of the representer of W(., v)).
 """
 import numpy as np
 import pytest
@@ -187,3 +189,38 @@ def test_backward_sweep_form_of_the_w_matrix_equals_the_forward_form():
                 gam += _project_right(mps, dets, Rt, p, h0)
             half[:, b] += left_flat[p] @ gam
     np.testing.assert_allclose(half + half.T, W, atol=1e-12 * max(1.0, np.abs(W).max()))
+
+
+@pytest.mark.parametrize("L,Na,Nb,M,seed", [(4, 2, 2, 4, 3), (5, 2, 2, 6, 11), (5, 3, 2, 5, 17)])
+def test_site_gradient_of_w_at_a_stationary_reference(L, Na, Nb, M, seed):
+    # The DMRG-RPA residual takes the site-i part of W v from the mixed-
+    # canonical MPS centred at i: <U_v n r|H|Psi0> + <l n V_v|H|Psi0>, with
+    # U_v (V_v) the first-order left (right) block states of v, projected off
+    # C^(0).  At a stationary reference that is exactly P_i^T w_v, where
+    # w_v = B W B^T v is the tangent-space representer of W(., v).
+    mps, dets, Hs, psi0 = _reference(L, Na, Nb, M, seed, stable_shift=False)
+    e0, A, W, B = rpa.rpa_matrices(mps, dets, Hs)
+    h0 = Hs @ psi0 - e0 * psi0
+    lam_inv = [{c: np.linalg.inv(g) for c, g in rpa.gauge_matrix(mps, i).items()} for i in range(L - 1)]
+    C0 = [firstorder.site_project(mps, dets, i, psi0) for i in range(L)]
+    rng = np.random.default_rng(seed)
+    for _ in range(2):
+        c = rng.normal(size=B.shape[1])
+        v, wv = B @ c, B @ (W @ c)
+        bl, br = rpa.site_pieces(mps, dets, v)
+        l1 = [{(s, n): b @ lam_inv[p][firstorder._right_sector(mps, p, s, n)] for (s, n), b in bl[p].items()}
+              for p in range(L - 1)]
+        r1 = [None] + [{(a, n): lam_inv[q - 1][a] @ b for (a, n), b in br[q].items()} for q in range(1, L)]
+        for i in range(L):
+            g = np.zeros(mps.site_size(i))
+            for p in range(i):
+                Lt = list(mps.Lt)
+                Lt[p] = l1[p]
+                g += rpa._project(mps, dets, Lt, i, h0)
+            for q in range(i + 1, L):
+                Rt = list(mps.Rt)
+                Rt[q] = r1[q]
+                g += _project_right(mps, dets, Rt, i, h0)
+            g -= C0[i] * (C0[i] @ g)
+            exact = firstorder.site_project(mps, dets, i, wv)
+            assert np.linalg.norm(g - exact) <= 1e-11 * max(1.0, np.linalg.norm(exact)), (i, np.linalg.norm(g - exact))
