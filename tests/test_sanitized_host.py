@@ -1,7 +1,8 @@
-"""The host-only tests (channel factorization, C-ABI checks) rerun against
-libdmrg_san.so, the library whose host C++ is built with AddressSanitizer
-and UndefinedBehaviorSanitizer, in a subprocess with the sanitizer runtime
-preloaded; any report aborts the subprocess."""
+"""The host-only tests (channel factorization, C-ABI checks, the reduced
+DMRG-RPA solver) rerun against libdmrg_san.so, the library whose host C++
+is built with AddressSanitizer and UndefinedBehaviorSanitizer, in a
+subprocess with the sanitizer runtime preloaded; any report aborts the
+subprocess."""
 import os
 import subprocess
 import sys
@@ -26,7 +27,7 @@ def test_host_paths_clean_under_asan_ubsan():
     r = subprocess.run([sys.executable, "-c", probe], cwd=ROOT, env=env, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-3000:]
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-m", "not gpu", "-p", "no:cacheprovider",
-                        "tests/test_host_factorization.py", "tests/test_abi.py"],
+                        "tests/test_host_factorization.py", "tests/test_abi.py", "tests/test_host_rpa_reduced.py"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, (r.stdout[-3000:], r.stderr[-3000:])
     assert "passed" in r.stdout
