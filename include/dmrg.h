@@ -251,6 +251,11 @@ typedef struct {
   int seed;               /* initial state                                 */
   int prec;               /* DMRG_FP64 / FP32 / BF16X3 contractions        */
   int verbose;
+  int onesite_sweeps;     /* one-site sweeps after the two-site ones (0:
+                             none): bond dimensions fixed, the centre
+                             optimized at every site, so the MPS converges
+                             to a stationary point of the energy on its
+                             manifold, the reference dmrg_rpa_roots needs   */
 } dmrg_sweep_params;
 
 /* Ground state by two-site sweeps with Davidson (Sec. II A, eq. dmrg and
@@ -260,7 +265,10 @@ typedef struct {
  * Starts from the imported MPS if there is one, else from a random MPS
  * (seed) with sector dimensions min(exact, M_schedule[0] / #sectors).
  * Each two-site step keeps at most M states over all sectors of the split
- * bond (singular values below 1e-12 of the largest are dropped).  prec is
+ * bond (singular values below 1e-12 of the largest are dropped).  Then
+ * onesite_sweeps one-site sweeps (right, then left) replace the centre by
+ * the lowest eigenvector of the one-site effective Hamiltonian at every
+ * site and move it by non-truncating splits.  prec is
  * the arithmetic of the sigma and renormalization contractions; Davidson,
  * SVD and the final energy are FP64.  energy receives <Psi|H|Psi> of the
  * final MPS; discarded the largest discarded weight of the last sweep.

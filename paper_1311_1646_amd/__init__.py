@@ -66,7 +66,7 @@ class Stats(ctypes.Structure):
 
 class SweepParams(ctypes.Structure):
     _fields_ = [("nsweeps", _I), ("M_schedule", _IP), ("noise", _DP), ("davidson_tol", _D),
-                ("davidson_max_iter", _I), ("seed", _I), ("prec", _I), ("verbose", _I)]
+                ("davidson_max_iter", _I), ("seed", _I), ("prec", _I), ("verbose", _I), ("onesite_sweeps", _I)]
 
 
 class DavidsonParams(ctypes.Structure):
@@ -347,11 +347,14 @@ class Context:
                             A1.numel(), prec))
 
     def sweep_ground(self, M_schedule, noise=None, davidson_tol=1e-12, davidson_max_iter=40,
-                     seed=1, prec=FP64, verbose=0):
+                     seed=1, prec=FP64, verbose=0, onesite_sweeps=0):
+        """Two-site sweeps with the bond schedule M_schedule, then
+        onesite_sweeps one-site sweeps (see dmrg_sweep_ground); returns
+        (energy, largest discarded weight of the last two-site sweep, True)."""
         Ms = np.ascontiguousarray(M_schedule, np.int32)
         nz = None if noise is None else np.ascontiguousarray(noise, np.float64)
         p = SweepParams(len(Ms), _ip(Ms), _dp(nz) if nz is not None else None, davidson_tol,
-                        davidson_max_iter, seed, prec, verbose)
+                        davidson_max_iter, seed, prec, verbose, int(onesite_sweeps))
         e = ctypes.c_double()
         dw = ctypes.c_double()
         rc = _sweep(self._h, ctypes.byref(p), ctypes.byref(e), ctypes.byref(dw))

@@ -80,11 +80,20 @@ class Ground {
   static std::vector<int> truncate(const SplitOut& o, int M, double* discarded);
   void copies(const std::vector<Copy2D>& c);
   void gemm(GemmPlan& P, const std::vector<GJob>& jobs, std::vector<std::vector<GContrib>>& per, const Bases& b);
-  double davidson(int i, double* psi, long n, int* iters);
+  double davidson(int i, double* psi, long n, int* iters, int width = 2);
   void random_start(int M0);
   void build_right_ops();
   void step(int i, bool right, int M, double* energy, double* dw);
   void final_pass();
+  // non-truncating split of the centre C_i at its right bond (the body of
+  // final_pass): L_i, Lambda_{i+1}, C_{i+1} = S V^T R_{i+1}
+  void move_right(int i);
+  // non-truncating split of the tensor in site[i].R at its left bond:
+  // site[i].R becomes R_i, bond i gets the Schmidt values, and the tensor in
+  // site[i-1].R is multiplied by U S
+  void split_left(int i);
+  // one-site sweep (right, then left) optimizing the centre at every site
+  double onesite_sweep();
   double gram1(const double* a, const double* b, long n);
 };
 
@@ -200,7 +209,7 @@ std::vector<int> Ground::truncate(const SplitOut& o, int M, double* discarded) {
 // Lowest eigenpair of the two-site effective Hamiltonian at (i, i+1); psi
 // (n elements) is the start vector on entry and the normalized Ritz vector
 // on exit.
-double Ground::davidson(int i, double* psi, long n, int* iters) {
+double Ground::davidson(int i, double* psi, long n, int* iters, int width) {
   const int nmax = int(std::min<long>(16, n));
   V_.ensure(&x_, size_t(nmax) * n * 8);
   HV_.ensure(&x_, size_t(nmax) * n * 8);
@@ -215,7 +224,7 @@ double Ground::davidson(int i, double* psi, long n, int* iters) {
   double* HV = HV_.as<double>();
   double* Hs = small_.as<double>();
   double* Ss = Hs + 64 * 64;
-  x_.diag(i, 2, diag_.as<double>());
+  x_.diag(i, width, diag_.as<double>());
   // v0 = psi / |psi|
   const double nrm = std::sqrt(gram1(psi, psi, n));
   DMRG_REQUIRE(nrm > 0, DMRG_ERR_INTERNAL, "zero start vector");
@@ -226,7 +235,8 @@ double Ground::davidson(int i, double* psi, long n, int* iters) {
   int k = 1, it = 0;
   double theta = 0;
   auto add_sigma = [&](int j) {
-    x_.sigma_general(i, 2, x_.left[i], x_.right[i + 2], V + long(j) * n, n, HV + long(j) * n, n, 1, p_.prec);
+    x_.sigma_general(i, width, x_.left[i], x_.right[i + width], V + long(j) * n, n, HV + long(j) * n, n, 1,
+                     p_.prec);
   };
   add_sigma(0);
   for (;;) {
@@ -393,92 +403,7 @@ void Ground::random_start(int M0) {
     put(x_, x_.site[i].R, v);
   }
   // right-canonicalize: split site i at its left bond
-  for (int i = L - 1; i >= 1; --i) {
-    const SiteLayout Si = x_.layout(i, 1);
-    const SiteLayout Sp = x_.layout(i - 1, 1);
-    const Bond bl = x_.bonds[i];
-    SplitSpec sp;
-    sp.q = bl.q;
-    sp.rows = bl.dim;
-    sp.cols.assign(bl.q.size(), 0);
-    std::map<std::pair<int, int>, int> c0;  // (n, c) within sector a
-    for (auto& b : Si.blk) {
-      auto key = std::make_pair(b.a * 64 + b.n, b.c);
-      c0[key] = sp.cols[b.a];
-      sp.places.push_back({long(b.off), b.rows, b.cols, b.a, 0, sp.cols[b.a]});
-      sp.cols[b.a] += b.cols;
-    }
-    SplitOut o;
-    svd(x_.site[i].R.as<double>(), sp, o);
-    std::vector<int> k = truncate(o, 1 << 30, nullptr);
-    Bond nb;
-    std::vector<std::vector<double>> lam;
-    std::vector<int> ni;
-    std::vector<double> sflat;
-    std::vector<long> soff;
-    kept_bond(sp, o, k, nb, lam, ni, sflat, soff);
-    // raw (unnormalized) singular values scale the carried part
-    std::vector<double> sraw;
-    std::vector<long> sroff(k.size(), 0);
-    for (size_t q = 0; q < k.size(); ++q) {
-      sroff[q] = long(sraw.size());
-      sraw.insert(sraw.end(), o.s[q].begin(), o.s[q].begin() + k[q]);
-    }
-    DBuf sdev;
-    put(x_, sdev, sraw);
-    // US = U scaled by S (column-major, ld = rows)
-    DBuf us;
-    us.ensure(&x_, std::max<size_t>(o.U.bytes / 8, 1) * 8);
-    std::vector<Copy2D> cp;
-    for (size_t q = 0; q < k.size(); ++q)
-      if (k[q] > 0)
-        cp.push_back({o.U.as<double>() + o.u_off[q], us.as<double>() + o.u_off[q], 1, long(sp.rows[q]), 1,
-                      long(sp.rows[q]), sdev.as<double>() + sroff[q], sp.rows[q], k[q], 2, 0});
-    copies(cp);
-    DBuf oldp = std::move(x_.site[i - 1].R);
-    x_.set_bond(i, nb, lam);
-    const SiteLayout& Ni = x_.layout(i, 1);
-    const SiteLayout& Np = x_.layout(i - 1, 1);
-    // R_i = rows of V^T
-    x_.site[i].R.alloc(&x_, std::max<size_t>(Ni.size, 1) * 8);
-    launch_fill_f64(x_.site[i].R.as<double>(), long(Ni.size), 0.0, x_.stream);
-    cp.clear();
-    for (auto& b : Ni.blk) {
-      const int q = bl.find(nb.q[b.a]);
-      // locate the old column block (n, c): same n, c index unchanged (bond i+1)
-      auto it = c0.find(std::make_pair(q * 64 + b.n, b.c));
-      if (it == c0.end()) continue;
-      cp.push_back({o.VT.as<double>() + o.vt_off[q] + long(it->second) * o.kmax[q],
-                    x_.site[i].R.as<double>() + b.off, 1, long(o.kmax[q]), long(b.cols), 1, nullptr, b.rows, b.cols,
-                    0, 0});
-    }
-    copies(cp);
-    // carry: T_{i-1}(a', n', a) <- T_{i-1}(a', n', a_old) (U S)_a
-    x_.site[i - 1].R.alloc(&x_, std::max<size_t>(Np.size, 1) * 8);
-    std::vector<GJob> jobs;
-    std::vector<std::vector<GContrib>> per;
-    for (auto& b : Np.blk) {
-      GJob j{};
-      j.offC = long(b.off);
-      j.baseC = B_SOUT;
-      j.ldc = b.cols;
-      j.m = b.rows;
-      j.n = b.cols;
-      jobs.push_back(j);
-      per.emplace_back();
-      const int q = bl.find(nb.q[b.c]);  // old sector of bond i
-      const int ob = Sp.find(b.a, b.n);
-      if (q < 0 || ob < 0 || Sp.blk[ob].c != q) continue;
-      per.back().push_back({long(Sp.blk[ob].off), o.u_off[q], Sp.blk[ob].cols, sp.rows[q], sp.rows[q], GC_TRANS_B,
-                            B_AKET, B_AUX, 1.0});
-    }
-    Bases bs{};
-    bs.p[B_AKET] = oldp.as<double>();
-    bs.p[B_AUX] = us.as<double>();
-    bs.p[B_SOUT] = x_.site[i - 1].R.as<double>();
-    GemmPlan P;
-    gemm(P, jobs, per, bs);
-  }
+  for (int i = L - 1; i >= 1; --i) split_left(i);
   // centre C_0 = T_0 / |T_0|
   const SiteLayout& S0 = x_.layout(0, 1);
   const double nrm = std::sqrt(gram1(x_.site[0].R.as<double>(), x_.site[0].R.as<double>(), long(S0.size)));
@@ -495,6 +420,93 @@ void Ground::random_start(int M0) {
   x_.lam_dev.resize(L + 1);
   x_.laminv_dev.resize(L + 1);
   for (int b = 0; b <= L; ++b) x_.upload_lambda_bond(b);
+}
+
+void Ground::split_left(int i) {
+  const SiteLayout Si = x_.layout(i, 1);
+  const SiteLayout Sp = x_.layout(i - 1, 1);
+  const Bond bl = x_.bonds[i];
+  SplitSpec sp;
+  sp.q = bl.q;
+  sp.rows = bl.dim;
+  sp.cols.assign(bl.q.size(), 0);
+  std::map<std::pair<int, int>, int> c0;  // (n, c) within sector a
+  for (auto& b : Si.blk) {
+    auto key = std::make_pair(b.a * 64 + b.n, b.c);
+    c0[key] = sp.cols[b.a];
+    sp.places.push_back({long(b.off), b.rows, b.cols, b.a, 0, sp.cols[b.a]});
+    sp.cols[b.a] += b.cols;
+  }
+  SplitOut o;
+  svd(x_.site[i].R.as<double>(), sp, o);
+  std::vector<int> k = truncate(o, 1 << 30, nullptr);
+  Bond nb;
+  std::vector<std::vector<double>> lam;
+  std::vector<int> ni;
+  std::vector<double> sflat;
+  std::vector<long> soff;
+  kept_bond(sp, o, k, nb, lam, ni, sflat, soff);
+  // raw (unnormalized) singular values scale the carried part
+  std::vector<double> sraw;
+  std::vector<long> sroff(k.size(), 0);
+  for (size_t q = 0; q < k.size(); ++q) {
+    sroff[q] = long(sraw.size());
+    sraw.insert(sraw.end(), o.s[q].begin(), o.s[q].begin() + k[q]);
+  }
+  DBuf sdev;
+  put(x_, sdev, sraw);
+  // US = U scaled by S (column-major, ld = rows)
+  DBuf us;
+  us.ensure(&x_, std::max<size_t>(o.U.bytes / 8, 1) * 8);
+  std::vector<Copy2D> cp;
+  for (size_t q = 0; q < k.size(); ++q)
+    if (k[q] > 0)
+      cp.push_back({o.U.as<double>() + o.u_off[q], us.as<double>() + o.u_off[q], 1, long(sp.rows[q]), 1,
+                    long(sp.rows[q]), sdev.as<double>() + sroff[q], sp.rows[q], k[q], 2, 0});
+  copies(cp);
+  DBuf oldp = std::move(x_.site[i - 1].R);
+  x_.set_bond(i, nb, lam);
+  const SiteLayout& Ni = x_.layout(i, 1);
+  const SiteLayout& Np = x_.layout(i - 1, 1);
+  // R_i = rows of V^T
+  x_.site[i].R.alloc(&x_, std::max<size_t>(Ni.size, 1) * 8);
+  launch_fill_f64(x_.site[i].R.as<double>(), long(Ni.size), 0.0, x_.stream);
+  cp.clear();
+  for (auto& b : Ni.blk) {
+    const int q = bl.find(nb.q[b.a]);
+    // locate the old column block (n, c): same n, c index unchanged (bond i+1)
+    auto it = c0.find(std::make_pair(q * 64 + b.n, b.c));
+    if (it == c0.end()) continue;
+    cp.push_back({o.VT.as<double>() + o.vt_off[q] + long(it->second) * o.kmax[q],
+                  x_.site[i].R.as<double>() + b.off, 1, long(o.kmax[q]), long(b.cols), 1, nullptr, b.rows, b.cols,
+                  0, 0});
+  }
+  copies(cp);
+  // carry: T_{i-1}(a', n', a) <- T_{i-1}(a', n', a_old) (U S)_a
+  x_.site[i - 1].R.alloc(&x_, std::max<size_t>(Np.size, 1) * 8);
+  std::vector<GJob> jobs;
+  std::vector<std::vector<GContrib>> per;
+  for (auto& b : Np.blk) {
+    GJob j{};
+    j.offC = long(b.off);
+    j.baseC = B_SOUT;
+    j.ldc = b.cols;
+    j.m = b.rows;
+    j.n = b.cols;
+    jobs.push_back(j);
+    per.emplace_back();
+    const int q = bl.find(nb.q[b.c]);  // old sector of bond i
+    const int ob = Sp.find(b.a, b.n);
+    if (q < 0 || ob < 0 || Sp.blk[ob].c != q) continue;
+    per.back().push_back({long(Sp.blk[ob].off), o.u_off[q], Sp.blk[ob].cols, sp.rows[q], sp.rows[q], GC_TRANS_B,
+                          B_AKET, B_AUX, 1.0});
+  }
+  Bases bs{};
+  bs.p[B_AKET] = oldp.as<double>();
+  bs.p[B_AUX] = us.as<double>();
+  bs.p[B_SOUT] = x_.site[i - 1].R.as<double>();
+  GemmPlan P;
+  gemm(P, jobs, per, bs);
 }
 
 // One two-site step at (i, i+1); right: the centre moves to i+1.
@@ -616,124 +628,126 @@ void Ground::step(int i, bool right, int M, double* energy, double* dw) {
                  right ? "->" : "<-", i, *energy, its, i + 1, bn.total(), *dw);
 }
 
+void Ground::move_right(int i) {
+  const SiteLayout Si = x_.layout(i, 1);
+  const SiteLayout Sn = x_.layout(i + 1, 1);
+  const Bond bo = x_.bonds[i + 1];
+  SplitSpec sp;
+  sp.q = bo.q;
+  sp.rows.assign(bo.q.size(), 0);
+  sp.cols = bo.dim;
+  std::map<std::pair<int, int>, int> r0;  // (a, n) -> row offset in sector c
+  for (auto& b : Si.blk) {
+    r0[{b.a, b.n}] = sp.rows[b.c];
+    sp.places.push_back({long(b.off), b.rows, b.cols, b.c, sp.rows[b.c], 0});
+    sp.rows[b.c] += b.rows;
+  }
+  SplitOut o;
+  svd(x_.site[i].C.as<double>(), sp, o);
+  std::vector<int> k = truncate(o, 1 << 30, nullptr);
+  Bond nb;
+  std::vector<std::vector<double>> lam;
+  std::vector<int> ni;
+  std::vector<double> sflat;
+  std::vector<long> soff;
+  kept_bond(sp, o, k, nb, lam, ni, sflat, soff);
+  DBuf sdev;
+  put(x_, sdev, sflat);
+  DBuf oldR_i = std::move(x_.site[i].R), oldR_n = std::move(x_.site[i + 1].R);
+  if (i == 0) oldR_i = DBuf();
+  x_.set_bond(i + 1, nb, lam);
+  const SiteLayout& Ni = x_.layout(i, 1);
+  const SiteLayout& Nn = x_.layout(i + 1, 1);
+  const Bond& bn = x_.bonds[i + 1];
+  for (auto* d : {&x_.site[i].L, &x_.site[i].C}) {
+    d->alloc(&x_, std::max<size_t>(Ni.size, 1) * 8);
+    launch_fill_f64(d->as<double>(), long(Ni.size), 0.0, x_.stream);
+  }
+  std::vector<Copy2D> cp;
+  for (auto& b : Ni.blk) {
+    const int sec = bo.find(bn.q[b.c]);
+    auto it = r0.find({b.a, b.n});
+    if (sec < 0 || it == r0.end()) continue;
+    for (int w = 0; w < 2; ++w)
+      cp.push_back({o.U.as<double>() + o.u_off[sec] + it->second,
+                    (w ? x_.site[i].C : x_.site[i].L).as<double>() + b.off, 1, long(sp.rows[sec]), long(b.cols), 1,
+                    w ? sdev.as<double>() + soff[sec] : nullptr, b.rows, b.cols, w ? 2 : 0, 0});
+  }
+  copies(cp);
+  // R_i <- R_i V (i >= 1); R_0 = C_0
+  x_.site[i].R.alloc(&x_, std::max<size_t>(Ni.size, 1) * 8);
+  if (i == 0) {
+    DMRG_HIP(hipMemcpyAsync(x_.site[0].R.p, x_.site[0].C.p, Ni.size * 8, hipMemcpyDeviceToDevice, x_.stream));
+  } else {
+    std::vector<GJob> jobs;
+    std::vector<std::vector<GContrib>> per;
+    for (auto& b : Ni.blk) {
+      GJob j{};
+      j.offC = long(b.off);
+      j.baseC = B_SOUT;
+      j.ldc = b.cols;
+      j.m = b.rows;
+      j.n = b.cols;
+      jobs.push_back(j);
+      per.emplace_back();
+      const int sec = bo.find(bn.q[b.c]);
+      const int ob = Si.find(b.a, b.n);
+      if (sec < 0 || ob < 0) continue;
+      // V(c_old, c_new) = VT[c_new + c_old * kmax]: row-major K x N with ldb = kmax
+      per.back().push_back({long(Si.blk[ob].off), o.vt_off[sec], Si.blk[ob].cols, o.kmax[sec], Si.blk[ob].cols, 0,
+                            B_AKET, B_AUX, 1.0});
+    }
+    Bases bs{};
+    bs.p[B_AKET] = oldR_i.as<double>();
+    bs.p[B_AUX] = o.VT.as<double>();
+    bs.p[B_SOUT] = x_.site[i].R.as<double>();
+    GemmPlan P;
+    gemm(P, jobs, per, bs);
+  }
+  // R_{i+1} <- V^T R_{i+1}, C_{i+1} = S R_{i+1}
+  x_.site[i + 1].R.alloc(&x_, std::max<size_t>(Nn.size, 1) * 8);
+  x_.site[i + 1].C.alloc(&x_, std::max<size_t>(Nn.size, 1) * 8);
+  {
+    std::vector<GJob> jobs;
+    std::vector<std::vector<GContrib>> per;
+    for (auto& b : Nn.blk) {
+      GJob j{};
+      j.offC = long(b.off);
+      j.baseC = B_SOUT;
+      j.ldc = b.cols;
+      j.m = b.rows;
+      j.n = b.cols;
+      jobs.push_back(j);
+      per.emplace_back();
+      const int sec = bo.find(bn.q[b.a]);
+      const int ob = Sn.find(sec, b.n);
+      if (sec < 0 || ob < 0 || Sn.blk[ob].c != b.c) continue;
+      // op(A) = V^T (k x m_old): A^T with A row-major m_old x kmax
+      per.back().push_back({o.vt_off[sec], long(Sn.blk[ob].off), o.kmax[sec], Sn.blk[ob].cols, Sn.blk[ob].rows,
+                            GC_TRANS_A, B_AUX, B_AKET, 1.0});
+    }
+    Bases bs{};
+    bs.p[B_AKET] = oldR_n.as<double>();
+    bs.p[B_AUX] = o.VT.as<double>();
+    bs.p[B_SOUT] = x_.site[i + 1].R.as<double>();
+    GemmPlan P;
+    gemm(P, jobs, per, bs);
+  }
+  cp.clear();
+  for (auto& b : Nn.blk) {
+    const int sec = bo.find(bn.q[b.a]);
+    cp.push_back({x_.site[i + 1].R.as<double>() + b.off, x_.site[i + 1].C.as<double>() + b.off, long(b.cols), 1,
+                  long(b.cols), 1, sdev.as<double>() + soff[sec], b.rows, b.cols, 1, 0});
+  }
+  copies(cp);
+}
+
 // Non-truncating one-site pass from the centre at site 0 to the right:
 // C_i = U S V^T at bond i+1 gives L_i = U, Lambda_{i+1} = S, C_i = U S,
 // R_i <- R_i V and R_{i+1} <- V^T R_{i+1}, C_{i+1} = S R_{i+1}.
 void Ground::final_pass() {
   const int L = x_.L;
-  for (int i = 0; i + 1 < L; ++i) {
-    const SiteLayout Si = x_.layout(i, 1);
-    const SiteLayout Sn = x_.layout(i + 1, 1);
-    const Bond bo = x_.bonds[i + 1];
-    SplitSpec sp;
-    sp.q = bo.q;
-    sp.rows.assign(bo.q.size(), 0);
-    sp.cols = bo.dim;
-    std::map<std::pair<int, int>, int> r0;  // (a, n) -> row offset in sector c
-    for (auto& b : Si.blk) {
-      r0[{b.a, b.n}] = sp.rows[b.c];
-      sp.places.push_back({long(b.off), b.rows, b.cols, b.c, sp.rows[b.c], 0});
-      sp.rows[b.c] += b.rows;
-    }
-    SplitOut o;
-    svd(x_.site[i].C.as<double>(), sp, o);
-    std::vector<int> k = truncate(o, 1 << 30, nullptr);
-    Bond nb;
-    std::vector<std::vector<double>> lam;
-    std::vector<int> ni;
-    std::vector<double> sflat;
-    std::vector<long> soff;
-    kept_bond(sp, o, k, nb, lam, ni, sflat, soff);
-    DBuf sdev;
-    put(x_, sdev, sflat);
-    DBuf oldR_i = std::move(x_.site[i].R), oldR_n = std::move(x_.site[i + 1].R);
-    if (i == 0) oldR_i = DBuf();
-    x_.set_bond(i + 1, nb, lam);
-    const SiteLayout& Ni = x_.layout(i, 1);
-    const SiteLayout& Nn = x_.layout(i + 1, 1);
-    const Bond& bn = x_.bonds[i + 1];
-    for (auto* d : {&x_.site[i].L, &x_.site[i].C}) {
-      d->alloc(&x_, std::max<size_t>(Ni.size, 1) * 8);
-      launch_fill_f64(d->as<double>(), long(Ni.size), 0.0, x_.stream);
-    }
-    std::vector<Copy2D> cp;
-    for (auto& b : Ni.blk) {
-      const int sec = bo.find(bn.q[b.c]);
-      auto it = r0.find({b.a, b.n});
-      if (sec < 0 || it == r0.end()) continue;
-      for (int w = 0; w < 2; ++w)
-        cp.push_back({o.U.as<double>() + o.u_off[sec] + it->second,
-                      (w ? x_.site[i].C : x_.site[i].L).as<double>() + b.off, 1, long(sp.rows[sec]), long(b.cols), 1,
-                      w ? sdev.as<double>() + soff[sec] : nullptr, b.rows, b.cols, w ? 2 : 0, 0});
-    }
-    copies(cp);
-    // R_i <- R_i V (i >= 1); R_0 = C_0
-    x_.site[i].R.alloc(&x_, std::max<size_t>(Ni.size, 1) * 8);
-    if (i == 0) {
-      DMRG_HIP(hipMemcpyAsync(x_.site[0].R.p, x_.site[0].C.p, Ni.size * 8, hipMemcpyDeviceToDevice, x_.stream));
-    } else {
-      std::vector<GJob> jobs;
-      std::vector<std::vector<GContrib>> per;
-      for (auto& b : Ni.blk) {
-        GJob j{};
-        j.offC = long(b.off);
-        j.baseC = B_SOUT;
-        j.ldc = b.cols;
-        j.m = b.rows;
-        j.n = b.cols;
-        jobs.push_back(j);
-        per.emplace_back();
-        const int sec = bo.find(bn.q[b.c]);
-        const int ob = Si.find(b.a, b.n);
-        if (sec < 0 || ob < 0) continue;
-        // V(c_old, c_new) = VT[c_new + c_old * kmax]: row-major K x N with ldb = kmax
-        per.back().push_back({long(Si.blk[ob].off), o.vt_off[sec], Si.blk[ob].cols, o.kmax[sec], Si.blk[ob].cols, 0,
-                              B_AKET, B_AUX, 1.0});
-      }
-      Bases bs{};
-      bs.p[B_AKET] = oldR_i.as<double>();
-      bs.p[B_AUX] = o.VT.as<double>();
-      bs.p[B_SOUT] = x_.site[i].R.as<double>();
-      GemmPlan P;
-      gemm(P, jobs, per, bs);
-    }
-    // R_{i+1} <- V^T R_{i+1}, C_{i+1} = S R_{i+1}
-    x_.site[i + 1].R.alloc(&x_, std::max<size_t>(Nn.size, 1) * 8);
-    x_.site[i + 1].C.alloc(&x_, std::max<size_t>(Nn.size, 1) * 8);
-    {
-      std::vector<GJob> jobs;
-      std::vector<std::vector<GContrib>> per;
-      for (auto& b : Nn.blk) {
-        GJob j{};
-        j.offC = long(b.off);
-        j.baseC = B_SOUT;
-        j.ldc = b.cols;
-        j.m = b.rows;
-        j.n = b.cols;
-        jobs.push_back(j);
-        per.emplace_back();
-        const int sec = bo.find(bn.q[b.a]);
-        const int ob = Sn.find(sec, b.n);
-        if (sec < 0 || ob < 0 || Sn.blk[ob].c != b.c) continue;
-        // op(A) = V^T (k x m_old): A^T with A row-major m_old x kmax
-        per.back().push_back({o.vt_off[sec], long(Sn.blk[ob].off), o.kmax[sec], Sn.blk[ob].cols, Sn.blk[ob].rows,
-                              GC_TRANS_A, B_AUX, B_AKET, 1.0});
-      }
-      Bases bs{};
-      bs.p[B_AKET] = oldR_n.as<double>();
-      bs.p[B_AUX] = o.VT.as<double>();
-      bs.p[B_SOUT] = x_.site[i + 1].R.as<double>();
-      GemmPlan P;
-      gemm(P, jobs, per, bs);
-    }
-    cp.clear();
-    for (auto& b : Nn.blk) {
-      const int sec = bo.find(bn.q[b.a]);
-      cp.push_back({x_.site[i + 1].R.as<double>() + b.off, x_.site[i + 1].C.as<double>() + b.off, long(b.cols), 1,
-                    long(b.cols), 1, sdev.as<double>() + soff[sec], b.rows, b.cols, 1, 0});
-    }
-    copies(cp);
-  }
+  for (int i = 0; i + 1 < L; ++i) move_right(i);
   // last site: bond L has one state, L_{L-1} = C_{L-1}
   const SiteLayout& Sl = x_.layout(L - 1, 1);
   x_.site[L - 1].L.alloc(&x_, std::max<size_t>(Sl.size, 1) * 8);
@@ -744,11 +758,54 @@ void Ground::final_pass() {
   x_.sync();
 }
 
+// One-site sweep (eq. dmrg on the one-site product basis, Sec. II A),
+// right then left, from the centre at site 0: at every site the lowest
+// eigenvector of H_0^[i] replaces the centre, which then moves on by a
+// non-truncating split.  The bond dimensions stay fixed, so repeated sweeps
+// converge to a stationary point of the energy on the MPS manifold of the
+// current bonds, which the two-site sweeps (they truncate after every step)
+// do not reach.  Ends with the centre at site 0, R_1..R_{L-1} and the right
+// operators of every bond consistent.  Returns the last local eigenvalue.
+double Ground::onesite_sweep() {
+  const int L = x_.L;
+  const int rp = p_.prec == DMRG_BF16X3 ? DMRG_FP32 : p_.prec;
+  double e = 0;
+  int its = 0;
+  auto copy = [&](DBuf& dst, const DBuf& src, long n) {
+    dst.alloc(&x_, std::max<size_t>(size_t(n), 1) * 8);
+    if (n > 0) DMRG_HIP(hipMemcpyAsync(dst.p, src.p, size_t(n) * 8, hipMemcpyDeviceToDevice, x_.stream));
+  };
+  for (int i = 0; i < L; ++i) {
+    e = davidson(i, x_.site[i].C.as<double>(), long(x_.layout(i, 1).size), &its, 1);
+    if (i + 1 == L) break;
+    move_right(i);
+    x_.alloc_opset(x_.left[i + 1], i + 1, 0, 1, false);
+    x_.renorm(DMRG_DIR_LEFT, i, x_.site[i].L.as<double>(), x_.site[i].L.as<double>(), 0, x_.left[i], x_.left[i + 1],
+              false, 1, rp);
+    x_.sync();
+  }
+  for (int i = L - 1; i >= 1; --i) {
+    // split the optimized centre at its left bond and carry U S into L_{i-1}
+    copy(x_.site[i].R, x_.site[i].C, long(x_.layout(i, 1).size));
+    copy(x_.site[i - 1].R, x_.site[i - 1].L, long(x_.layout(i - 1, 1).size));
+    split_left(i);
+    const long np = long(x_.layout(i - 1, 1).size);
+    copy(x_.site[i - 1].C, x_.site[i - 1].R, np);
+    x_.alloc_opset(x_.right[i], i, 1, 1, false);
+    x_.renorm(DMRG_DIR_RIGHT, i, x_.site[i].R.as<double>(), x_.site[i].R.as<double>(), 0, x_.right[i + 1],
+              x_.right[i], false, 1, rp);
+    x_.sync();
+    e = davidson(i - 1, x_.site[i - 1].C.as<double>(), np, &its, 1);
+  }
+  return e;
+}
+
 void Ground::run(double* energy, double* discarded, bool* converged) {
   const int L = x_.L;
   DMRG_REQUIRE(p_.nsweeps >= 1 && p_.M_schedule, DMRG_ERR_INVALID_ARG, "need nsweeps >= 1 and a bond schedule");
   for (int s = 0; s < p_.nsweeps; ++s) DMRG_REQUIRE(p_.M_schedule[s] >= 1, DMRG_ERR_INVALID_ARG, "bad M");
   DMRG_REQUIRE(L >= 2, DMRG_ERR_INVALID_ARG, "need at least two sites");
+  DMRG_REQUIRE(p_.onesite_sweeps >= 0, DMRG_ERR_INVALID_ARG, "onesite_sweeps must be >= 0");
   if (!x_.have_mps) random_start(p_.M_schedule[0]);
   build_right_ops();
   double e = 0, last = 0, dwmax = 0;
@@ -777,6 +834,17 @@ void Ground::run(double* energy, double* discarded, bool* converged) {
                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
       log_jsonl(buf);
     }
+    last = e;
+  }
+  for (int k = 0; k < p_.onesite_sweeps; ++k) {
+    const auto t0 = std::chrono::steady_clock::now();
+    e = onesite_sweep();
+    if (p_.verbose >= 1) std::fprintf(stderr, "[ground] one-site sweep %d E %.14f dE %.2e\n", k, e, e - last);
+    char buf[256];
+    std::snprintf(buf, sizeof buf,
+                  "{\"event\": \"onesite_sweep\", \"sweep\": %d, \"energy\": %.15g, \"dE\": %.6g, \"seconds\": %.4f}",
+                  k, e, e - last, std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+    log_jsonl(buf);
     last = e;
   }
   final_pass();

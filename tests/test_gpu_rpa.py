@@ -103,3 +103,30 @@ def test_rpa_at_full_bond_dimension_is_tda_and_fci_at_scale():
     assert conv_t and conv_r, (it_t, r2_t, it_r, r2_r)
     np.testing.assert_allclose(om_r, om_t, atol=1e-7)
     np.testing.assert_allclose(om_r, w[1:n + 1] - w[0], atol=1e-7)
+
+
+def test_rpa_from_the_librarys_onesite_polished_ground_state():
+    # two-site sweeps alone leave a truncated MPS off the stationary point of
+    # its manifold; one-site sweeps (dmrg_sweep_params.onesite_sweeps) bring
+    # the library's own ground state there, and its RPA roots then equal the
+    # oracle's RPA of the exported MPS
+    import paper_1311_1646_amd as lib
+    from synth import mps_from_arrays
+    L, Na, Nb, M, seed, n = 6, 3, 3, 10, 5, 3
+    h, eri, _ = synth.random_integrals(L, seed=seed, K=L, diag_lo=-2, diag_hi=0)
+    dets, H = fci.hamiltonian(h, eri, 0.0, Na, Nb)
+    ctx2 = lib.Context(L, Na, Nb, h, eri, 0.0, device=0)
+    e2, _, _ = ctx2.sweep_ground([M, M, M], davidson_tol=1e-14, davidson_max_iter=60, seed=1)
+    g2 = stationary_reference.gradient_norm(mps_from_arrays(L, Na, Nb, *ctx2.export_mps()), dets, H)
+    ctx1 = lib.Context(L, Na, Nb, h, eri, 0.0, device=0)
+    e1, _, _ = ctx1.sweep_ground([M, M, M], davidson_tol=1e-14, davidson_max_iter=60, seed=1, onesite_sweeps=60)
+    mps1 = mps_from_arrays(L, Na, Nb, *ctx1.export_mps())
+    g1 = stationary_reference.gradient_norm(mps1, dets, H)
+    print(f"two-site E {e2:.12f} gradient {g2:.2e}; + one-site sweeps E {e1:.12f} gradient {g1:.2e}", flush=True)
+    assert e1 <= e2 + 1e-10
+    assert g1 < 1e-5 and g1 < 1e-2 * g2
+    e0, om_ref, om_tda = rpa.rpa_roots(mps1, dets, H, n)
+    om, et, r2, it, conv = ctx1.rpa_roots(n, max_iter=150, tol=1e-11, seed=3, prec=0)
+    print(f"RPA {np.round(om, 10).tolist()} oracle {np.round(om_ref, 10).tolist()} in {it} iterations", flush=True)
+    assert conv, (it, r2)
+    np.testing.assert_allclose(om, om_ref, atol=1e-8)
