@@ -395,7 +395,9 @@ int dmrg_response(dmrg_ctx* ctx, const double* v, double omega, const dmrg_david
 
 /* DMRG-RPA roots (Sec. II C eq. dmrgrpa; Sec. III E eqs. reducedrpa and
  * bmatrix) of the current MPS, which is taken to be a stationary point of
- * the energy on the MPS manifold (a converged ground state).  The Davidson
+ * the energy on the MPS manifold (a converged ground state: the truncating
+ * two-site sweeps do not end there, dmrg_sweep_ground with onesite_sweeps
+ * does; away from it A +- W can be indefinite).  The Davidson
  * sweeps of dmrg_tda_roots run over trial first-order wavefunctions U; the
  * reduced matrices are H_R and S_R of eqs. hleft2 / sleft2 and the
  * second-order matrix W_R = W(U, U), accumulated in the backward sweep from
