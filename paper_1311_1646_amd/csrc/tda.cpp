@@ -1015,7 +1015,8 @@ void TdaRunner::run(double* omega, double* etot, double* resid2, int* iters, boo
     }
     if (polishing) x_.stats.tda_polish_iters = ++polish_iters;
     {
-      std::string js = resp_ ? "{\"event\": \"response_iteration\"" : "{\"event\": \"tda_iteration\"";
+      std::string js = resp_ ? "{\"event\": \"response_iteration\""
+                             : (rpa_ ? "{\"event\": \"rpa_iteration\"" : "{\"event\": \"tda_iteration\"");
       char buf[512];
       std::snprintf(buf, sizeof buf,
                     ", \"iteration\": %d, \"trial_vectors\": %d, \"max_r2\": %.6g, \"%s\": %.15g, \"%s\": %.15g, "
