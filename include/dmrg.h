@@ -184,8 +184,8 @@ int dmrg_sigma(dmrg_ctx* ctx, int site, int kind, int nvec, const double* C_in,
  * updated).  One ordinary dmrg_sigma call with the same site, kind, nvec and
  * precision must come first: it builds the plans and tile lists and records
  * the workspace sizes (and again after dmrg_sweep_ground, dmrg_tda_roots,
- * dmrg_tda_transition or dmrg_response, which drop the cached tile lists
- * when they end).  Every call on a GPU shares that GPU's scratch (it
+ * dmrg_rpa_roots, dmrg_tda_transition or dmrg_response, which drop the
+ * cached tile lists when they end).  Every call on a GPU shares that GPU's scratch (it
  * keeps the last call's contents; nothing in it needs clearing), so calls
  * that overlap on one GPU race.
  * Errors: INVALID_ARG (as dmrg_sigma, a TDA kind, or a workspace larger
